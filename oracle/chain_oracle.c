@@ -1,0 +1,146 @@
+/*
+ * chain_oracle.c -- plain, slow, obviously correct CPU reference for classical
+ * RK4 stepping of a periodic one-dimensional chain with nearest-neighbour
+ * coupling (Mulansky, "Optimizing Large-Scale ODE Simulations", Sec. 2).
+ *
+ * TEST INFRASTRUCTURE ONLY. The tests, the smoke check and the benchmark's
+ * CPU-baseline leg are the only code that may load this library. It shares no
+ * code, header or constant with the GPU library.
+ *
+ * Arithmetic is FP64 with no fused multiply-add (build with
+ * -ffp-contract=off). Every per-site loop may run under OpenMP; the sites of a
+ * sweep are independent, so the thread count never changes a result. Sums
+ * over sites (the energy) run in index order on one thread.
+ *
+ * Models (homogeneous nearest-neighbour ODE, Sec. 2.1 Eq. 2, written as
+ * dq_i/dt = p_i, dp_i/dt = F_i):
+ *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
+ *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
+ * Periodic boundary (Sec. 3.1): site 0's left neighbour is site N-1 and site
+ * N-1's right neighbour is site 0, for every N >= 1.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORACLE_QUARTIC = 0, ORACLE_HARMONIC = 1 };
+
+static int64_t left_of(int64_t i, int64_t n) { return i == 0 ? n - 1 : i - 1; }
+static int64_t right_of(int64_t i, int64_t n) { return i == n - 1 ? 0 : i + 1; }
+
+/* The force on one site from its own coordinate and its two neighbours'. */
+static double force_site(int model, double qm, double q, double qp)
+{
+    if (model == ORACLE_QUARTIC) {
+        double dr = qp - q;
+        double dl = q - qm;
+        return -(q + q * q * q) + dr * dr * dr - dl * dl * dl;
+    }
+    return -q + (qp - 2.0 * q + qm);
+}
+
+/* Energy density of one site: kinetic + on-site potential + the potential of
+ * the bond to the right neighbour. Its gradient gives the force above. */
+static double energy_site(int model, double q, double p, double qp)
+{
+    double d = qp - q;
+    if (model == ORACLE_QUARTIC)
+        return p * p / 2.0 + q * q / 2.0 + q * q * q * q / 4.0 + d * d * d * d / 4.0;
+    return p * p / 2.0 + q * q / 2.0 + d * d / 2.0;
+}
+
+/* Eq. 3: one evaluation of the right-hand side over the whole chain. */
+static void rhs(int model, int64_t n, const double *q, const double *p,
+                double *kq, double *kp, int threads)
+{
+    int64_t i;
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (i = 0; i < n; ++i) {
+        kq[i] = p[i];
+        kp[i] = force_site(model, q[left_of(i, n)], q[i], q[right_of(i, n)]);
+    }
+}
+
+/* Eq. 4: intermediate state y + a * dt * k. */
+static void intermediate(int64_t n, const double *q, const double *p,
+                         double a_dt, const double *kq, const double *kp,
+                         double *Q, double *P, int threads)
+{
+    int64_t i;
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (i = 0; i < n; ++i) {
+        Q[i] = q[i] + a_dt * kq[i];
+        P[i] = p[i] + a_dt * kp[i];
+    }
+}
+
+/* Public: the force F(q) over the whole chain. */
+void oracle_force(int model, int64_t n, const double *q, double *f)
+{
+    int64_t i;
+    for (i = 0; i < n; ++i)
+        f[i] = force_site(model, q[left_of(i, n)], q[i], q[right_of(i, n)]);
+}
+
+/*
+ * Public: advance (q, p) in place by `steps` classical RK4 steps of size dt
+ * (Sec. 2.2 Eq. 3-5 with the classical tableau c = (0, 1/2, 1/2, 1),
+ * a21 = a32 = 1/2, a43 = 1, b = (1/6, 1/3, 1/3, 1/6)). dt may be negative.
+ * Returns 0, or -1 if the work arrays cannot be allocated.
+ */
+int oracle_rk4_run(int model, int64_t n, double dt, int64_t steps,
+                   double *q, double *p, int threads)
+{
+    double *buf, *k1q, *k1p, *k2q, *k2p, *k3q, *k3p, *k4q, *k4p, *Q, *P;
+    int64_t s, i;
+    if (n < 1 || steps < 0)
+        return -1;
+    if (threads < 1)
+        threads = 1;
+    buf = (double *)malloc(sizeof(double) * (size_t)n * 10);
+    if (!buf)
+        return -1;
+    k1q = buf;          k1p = buf + n;
+    k2q = buf + 2 * n;  k2p = buf + 3 * n;
+    k3q = buf + 4 * n;  k3p = buf + 5 * n;
+    k4q = buf + 6 * n;  k4p = buf + 7 * n;
+    Q = buf + 8 * n;    P = buf + 9 * n;
+
+    for (s = 0; s < steps; ++s) {
+        rhs(model, n, q, p, k1q, k1p, threads);
+        intermediate(n, q, p, dt / 2.0, k1q, k1p, Q, P, threads);
+        rhs(model, n, Q, P, k2q, k2p, threads);
+        intermediate(n, q, p, dt / 2.0, k2q, k2p, Q, P, threads);
+        rhs(model, n, Q, P, k3q, k3p, threads);
+        intermediate(n, q, p, dt, k3q, k3p, Q, P, threads);
+        rhs(model, n, Q, P, k4q, k4p, threads);
+        /* Eq. 5 */
+#pragma omp parallel for num_threads(threads) schedule(static)
+        for (i = 0; i < n; ++i) {
+            q[i] = q[i] + (dt / 6.0) * (k1q[i] + 2.0 * k2q[i] + 2.0 * k3q[i] + k4q[i]);
+            p[i] = p[i] + (dt / 6.0) * (k1p[i] + 2.0 * k2p[i] + 2.0 * k3p[i] + k4p[i]);
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/*
+ * Public: total energy H = sum_i e_i, summed in index order with Neumaier's
+ * compensated summation (Neumaier 1974).
+ */
+double oracle_energy(int model, int64_t n, const double *q, const double *p)
+{
+    double sum = 0.0, comp = 0.0;
+    int64_t i;
+    for (i = 0; i < n; ++i) {
+        double e = energy_site(model, q[i], p[i], q[right_of(i, n)]);
+        double t = sum + e;
+        if ((sum >= 0 ? sum : -sum) >= (e >= 0 ? e : -e))
+            comp += (sum - t) + e;
+        else
+            comp += (e - t) + sum;
+        sum = t;
+    }
+    return sum + comp;
+}
