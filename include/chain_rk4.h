@@ -1,0 +1,165 @@
+/*
+ * chain_rk4.h -- C ABI of the MI355X (gfx950) library that advances large
+ * periodic one-dimensional chains with classical explicit RK4.
+ *
+ * The problem (Mulansky, "Optimizing Large-Scale ODE Simulations"):
+ *   a ring of N sites with state r_i = (q_i, p_i), a homogeneous
+ *   nearest-neighbour vector field (Sec. 2.1 Eq. 2), periodic boundary
+ *   (Sec. 3.1), advanced by RK4 with a fixed step dt (Sec. 2.2 Eq. 3-5):
+ *     dq_i/dt = p_i,   dp_i/dt = F_i(q_{i-1}, q_i, q_{i+1})
+ *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
+ *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device memory of the current device; host
+ *     pointers are ordinary host memory. The library never frees memory it
+ *     did not allocate.
+ *   - A stream argument is a hipStream_t passed as void*; NULL is the null
+ *     stream. Work is enqueued on that stream and calls return before it runs
+ *     unless stated otherwise.
+ *   - Every call returns a chain_status. Arguments are validated before any
+ *     HIP call, so an invalid argument has no side effect. A HIP failure
+ *     returns CHAIN_EHIP; chain_rk4_last_error() then gives the message.
+ *   - Handles are not thread-safe; distinct handles are independent.
+ *   - Results are bit-identical for every tile size, temporal depth, method
+ *     and batch placement of the FP64 path, and likewise of the FP32 path.
+ */
+#ifndef CHAIN_RK4_H
+#define CHAIN_RK4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chain_rk4 chain_rk4;
+
+enum chain_model {
+    CHAIN_QUARTIC = 0,   /* quartic on-site and bond potentials (formula above) */
+    CHAIN_HARMONIC = 1   /* the linear chain (formula above) */
+};
+
+enum chain_prec {
+    CHAIN_FP64 = 0,        /* q, p and every stage in FP64 */
+    CHAIN_FP32_KAHAN = 1   /* q, p and stages in FP32; the final update of each
+                              step is Kahan-compensated with a per-site FP32
+                              carry; energies are reduced in FP64 */
+};
+
+enum chain_method {
+    CHAIN_FUSED = 0,  /* one pass over memory per `kdepth` steps: each tile is
+                         extended by 4*kdepth sites per side that are recomputed
+                         and discarded (Sec. 2.3, the overlap of s sites per side
+                         per step, carried over several steps) */
+    CHAIN_NAIVE = 1   /* the standard implementation: one kernel per RK stage,
+                         every stage result goes through memory (Sec. 2.2) */
+};
+
+enum chain_flags {
+    CHAIN_FLAG_GRAPH = 1,        /* replay each distinct step count from a
+                                    captured hipGraph instead of launching pass
+                                    by pass */
+    CHAIN_FLAG_NO_RESIDENT = 2   /* never keep a short ring resident on chip;
+                                    always run the tiled passes */
+};
+
+typedef enum chain_status {
+    CHAIN_OK = 0,
+    CHAIN_EINVAL = -1,      /* invalid argument (nothing was done) */
+    CHAIN_ENOMEM = -2,      /* workspace too small */
+    CHAIN_EHIP = -3,        /* a HIP runtime call failed */
+    CHAIN_ENONFINITE = -4,  /* an energy came out NaN or infinite */
+    CHAIN_EDEVICE = -5      /* the current device is not a gfx950 GPU */
+} chain_status;
+
+typedef struct chain_rk4_desc {
+    int64_t n;               /* sites on the ring, >= 1 (N = 1, 2 are legal) */
+    int32_t model;           /* enum chain_model */
+    int32_t prec;            /* enum chain_prec */
+    double dt;               /* step size; finite, may be negative (reversal) */
+    int32_t method;          /* enum chain_method */
+    int32_t sites_per_lane;  /* fused: sites per GPU lane, 0 = default, else
+                                4, 8 or 16 */
+    int32_t kdepth;          /* fused: RK4 steps per pass over memory, 0 =
+                                default, else 1..16 */
+    int32_t flags;           /* enum chain_flags, or 0 */
+} chain_rk4_desc;
+
+/* Plan chosen for a handle: what one step call launches. */
+typedef struct chain_rk4_plan {
+    int32_t method, sites_per_lane, kdepth, resident; /* resident: 1 if the
+                                    whole ring stays on chip for all steps */
+    int64_t tile;                /* output sites per wavefront and pass */
+    int64_t halo;                /* recomputed sites per side (4 * kdepth) */
+    int64_t waves;               /* wavefronts per pass */
+    double overlap_factor;       /* sites computed / sites kept per pass,
+                                    1 + 2*halo/tile (Sec. 2.3) */
+} chain_rk4_plan;
+
+/*
+ * Device workspace bytes a chain described by `d` needs (the back buffer of
+ * the ping-pong update, the FP32 carries, the naive method's stage arrays and
+ * the energy partials). Returns 0 if `d` is invalid.
+ */
+size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d);
+
+/*
+ * Create a handle over caller-owned device buffers.
+ *   q, p       device arrays of d->n values (double for CHAIN_FP64, float for
+ *              CHAIN_FP32_KAHAN), 16-byte aligned; they hold the initial state
+ *              and, after each step call completes, the advanced state.
+ *   workspace  device buffer of ws_bytes >= chain_rk4_workspace_bytes(d),
+ *              256-byte aligned (NULL allowed only if that size is 0).
+ *   stream     stream for every later call on this handle.
+ * The handle borrows q, p and workspace until chain_rk4_destroy. The FP32
+ * carries are zeroed on `stream`. Returns CHAIN_EINVAL for NULL or misaligned
+ * pointers or an invalid descriptor, CHAIN_ENOMEM if ws_bytes is too small,
+ * CHAIN_EDEVICE if the current device is not gfx950.
+ */
+int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace,
+                     size_t ws_bytes, void *stream, chain_rk4 **out);
+
+/* Enqueue nsteps (>= 0) RK4 steps on the handle's stream (asynchronous). */
+int chain_rk4_step(chain_rk4 *h, int64_t nsteps);
+
+/*
+ * Total energy of the current state, in FP64, written to *e_out (host).
+ * Quartic: sum_i p_i^2/2 + q_i^2/2 + q_i^4/4 + (q_{i+1}-q_i)^4/4;
+ * harmonic: sum_i p_i^2/2 + q_i^2/2 + (q_{i+1}-q_i)^2/2. For CHAIN_FP32_KAHAN
+ * each coordinate enters as (hi - carry) in FP64. The sum order is fixed for
+ * a given n, so repeated calls agree bitwise. Synchronises the stream.
+ * Returns CHAIN_ENONFINITE (with *e_out set) if the energy is NaN or Inf.
+ */
+int chain_rk4_energy(chain_rk4 *h, double *e_out);
+
+/* Replace the stream used by later calls on this handle. */
+int chain_rk4_set_stream(chain_rk4 *h, void *stream);
+
+/* Report the plan of a handle (host struct). */
+int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out);
+
+/*
+ * Device pointers of the per-site FP32 carries (n floats each, inside the
+ * workspace) that complete the state of a CHAIN_FP32_KAHAN handle: the
+ * compensated coordinate is q - cq, the momentum p - cp. Copying q, p and
+ * both carries saves the full state; writing them restores it. For CHAIN_FP64
+ * both pointers are set to NULL.
+ */
+int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp);
+
+/* Release a handle (host memory and cached graphs only). NULL is a no-op. */
+int chain_rk4_destroy(chain_rk4 *h);
+
+/* Static description of a status code; never NULL. */
+const char *chain_rk4_strerror(int status);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *chain_rk4_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHAIN_RK4_H */

@@ -1,0 +1,120 @@
+"""Python binding of one chain: argument marshalling over the C ABI only.
+
+Torch supplies the device memory (state and workspace) and the stream; every
+step of the integration runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+MODELS = {"quartic": L.CHAIN_QUARTIC, "harmonic": L.CHAIN_HARMONIC}
+PRECS = {"fp64": L.CHAIN_FP64, "fp32_kahan": L.CHAIN_FP32_KAHAN}
+METHODS = {"fused": L.CHAIN_FUSED, "naive": L.CHAIN_NAIVE}
+
+
+def _code(table, v):
+    if isinstance(v, str):
+        return table[v]
+    return int(v)
+
+
+def state_dtype(prec) -> torch.dtype:
+    return torch.float64 if _code(PRECS, prec) == L.CHAIN_FP64 else torch.float32
+
+
+def aligned_empty(nbytes: int, device, align: int = 256) -> tuple[torch.Tensor, int]:
+    """A byte tensor holding at least nbytes at an `align`-aligned address."""
+    buf = torch.empty(max(1, nbytes + align), dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % align
+    return buf, buf.data_ptr() + off
+
+
+class Chain:
+    """One periodic chain advanced by the HIP library.
+
+    ``q0`` and ``p0`` (numpy arrays or tensors) are copied into device tensors
+    of the precision's dtype; ``state()`` returns those tensors.
+    """
+
+    def __init__(self, q0, p0, dt: float, model="quartic", prec="fp64", method="fused",
+                 sites_per_lane: int = 0, kdepth: int = 0, graph: bool = False,
+                 resident: bool = True, device="cuda", stream: torch.cuda.Stream | None = None):
+        self.device = torch.device(device)
+        dtype = state_dtype(prec)
+        self.q = torch.as_tensor(q0).to(device=self.device, dtype=dtype).contiguous().clone()
+        self.p = torch.as_tensor(p0).to(device=self.device, dtype=dtype).contiguous().clone()
+        if self.q.ndim != 1 or self.q.shape != self.p.shape:
+            raise ValueError("q0 and p0 must be 1-D of one length")
+        flags = (L.CHAIN_FLAG_GRAPH if graph else 0) | (0 if resident else L.CHAIN_FLAG_NO_RESIDENT)
+        self.desc = L.Desc(self.q.numel(), _code(MODELS, model), _code(PRECS, prec), float(dt),
+                           _code(METHODS, method), int(sites_per_lane), int(kdepth), flags)
+        lib = L.lib()
+        ws = lib.chain_rk4_workspace_bytes(ctypes.byref(self.desc))
+        if ws == 0:
+            L.check(L.CHAIN_EINVAL, "chain_rk4_workspace_bytes")
+        self._ws, ws_ptr = aligned_empty(ws, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = L.H()
+        L.check(lib.chain_rk4_create(ctypes.byref(self.desc), self.q.data_ptr(), self.p.data_ptr(),
+                                     ws_ptr, ws, self.stream.cuda_stream, ctypes.byref(h)),
+                "chain_rk4_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, nsteps: int) -> "Chain":
+        L.check(L.lib().chain_rk4_step(self._h, int(nsteps)), "chain_rk4_step")
+        return self
+
+    def energy(self) -> float:
+        e = ctypes.c_double()
+        L.check(L.lib().chain_rk4_energy(self._h, ctypes.byref(e)), "chain_rk4_energy")
+        return e.value
+
+    def set_stream(self, stream: torch.cuda.Stream) -> None:
+        L.check(L.lib().chain_rk4_set_stream(self._h, stream.cuda_stream), "chain_rk4_set_stream")
+        self.stream = stream
+
+    def plan(self) -> dict:
+        P = L.Plan()
+        L.check(L.lib().chain_rk4_get_plan(self._h, ctypes.byref(P)), "chain_rk4_get_plan")
+        return {k: getattr(P, k) for k, _ in L.Plan._fields_}
+
+    def carries(self):
+        """Device pointers (ints) of the FP32 carries, or (None, None) for FP64."""
+        cq, cp = L.VP(), L.VP()
+        L.check(L.lib().chain_rk4_get_carries(self._h, ctypes.byref(cq), ctypes.byref(cp)),
+                "chain_rk4_get_carries")
+        return cq.value, cp.value
+
+    def carry_tensors(self):
+        """Views of the FP32 carries as tensors (FP32 precision only)."""
+        cq, cp = self.carries()
+        if cq is None:
+            return None, None
+        base = self._ws.data_ptr()
+        n = self.q.numel()
+        flat = self._ws.view(torch.uint8)
+        tq = flat[cq - base: cq - base + 4 * n].view(torch.float32)
+        tp = flat[cp - base: cp - base + 4 * n].view(torch.float32)
+        return tq, tp
+
+    def state(self):
+        return self.q, self.p
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            L.lib().chain_rk4_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,394 @@
+// chain_rk4.cpp -- host side of the C ABI declared in include/chain_rk4.h:
+// argument validation, workspace layout, the pass plan of a step call, graph
+// capture, and the energy read-back.
+#include "chain_rk4.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+
+using namespace chainrk4;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(CHAIN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Defaults when the descriptor leaves the tile shape to the library.
+constexpr int kDefaultSitesFp64 = 8;
+constexpr int kDefaultSitesFp32 = 16;
+constexpr int kDefaultDepth = 4;
+constexpr int kMaxDepth = 16;
+
+bool valid_sites(int s) { return s == 4 || s == 8 || s == 16; }
+
+int check_desc(const chain_rk4_desc *d) {
+    if (!d) return fail(CHAIN_EINVAL, "descriptor is NULL");
+    if (d->n < 1) return fail(CHAIN_EINVAL, "n must be >= 1 (got %lld)", (long long)d->n);
+    if (d->n > (int64_t(1) << 40)) return fail(CHAIN_EINVAL, "n too large");
+    if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC)
+        return fail(CHAIN_EINVAL, "unknown model %d", d->model);
+    if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN)
+        return fail(CHAIN_EINVAL, "unknown precision %d", d->prec);
+    if (!std::isfinite(d->dt)) return fail(CHAIN_EINVAL, "dt must be finite");
+    if (d->method != CHAIN_FUSED && d->method != CHAIN_NAIVE)
+        return fail(CHAIN_EINVAL, "unknown method %d", d->method);
+    if (d->sites_per_lane != 0 && !valid_sites(d->sites_per_lane))
+        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16 (got %d)", d->sites_per_lane);
+    if (d->kdepth < 0 || d->kdepth > kMaxDepth)
+        return fail(CHAIN_EINVAL, "kdepth must be in 0..%d (got %d)", kMaxDepth, d->kdepth);
+    if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT))
+        return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
+    return CHAIN_OK;
+}
+
+size_t elem_bytes(int prec) { return prec == CHAIN_FP64 ? sizeof(double) : sizeof(float); }
+
+// Workspace regions, in order. Unused regions have size 0.
+struct Layout {
+    size_t back_q, back_p;            // fused: back buffer of the ping-pong
+    size_t cq, cp, back_cq, back_cp;  // FP32: carries (front and back)
+    size_t naive[10];                 // naive: k1..k3 and two stage arguments
+    size_t partials, result;          // energy
+    size_t total;
+};
+
+Layout layout(const chain_rk4_desc *d) {
+    Layout L{};
+    const size_t n = static_cast<size_t>(d->n);
+    const size_t arr = round_up(n * elem_bytes(d->prec));
+    const size_t carr = round_up(n * sizeof(float));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    const bool kahan = d->prec == CHAIN_FP32_KAHAN;
+    if (d->method == CHAIN_FUSED) {
+        L.back_q = take(arr);
+        L.back_p = take(arr);
+    }
+    if (kahan) {
+        L.cq = take(carr);
+        L.cp = take(carr);
+        if (d->method == CHAIN_FUSED) {
+            L.back_cq = take(carr);
+            L.back_cp = take(carr);
+        }
+    }
+    if (d->method == CHAIN_NAIVE)
+        for (int i = 0; i < 10; ++i) L.naive[i] = take(arr);
+    L.partials = take(round_up(kEnergyMaxBlocks * sizeof(double)));
+    L.result = take(kAlign);
+    L.total = off;
+    return L;
+}
+
+struct Plan {
+    bool resident = false;
+    int sites = 0, depth = 0;
+    int64_t tile = 0, halo = 0, waves = 0;
+};
+
+Plan make_plan(const chain_rk4_desc *d) {
+    Plan P;
+    if (d->method != CHAIN_FUSED) return P;
+    if (!(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites && d->sites_per_lane == 0 &&
+        d->kdepth == 0) {
+        P.resident = true;
+        return P;
+    }
+    P.sites = d->sites_per_lane ? d->sites_per_lane
+                                : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
+    P.depth = d->kdepth ? d->kdepth : kDefaultDepth;
+    // the kept part of a cluster must stay positive: 64*S > 8*depth
+    while (64 * P.sites <= 8 * P.depth && P.depth > 1) --P.depth;
+    P.halo = 4 * static_cast<int64_t>(P.depth);
+    P.tile = 64 * static_cast<int64_t>(P.sites) - 2 * P.halo;
+    P.waves = (d->n + P.tile - 1) / P.tile;
+    return P;
+}
+
+bool is_gfx950(int dev) {
+    static int cached[64];  // 0 unknown, 1 yes, 2 no
+    if (dev < 0 || dev >= 64) return false;
+    if (cached[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+        cached[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    }
+    return cached[dev] == 1;
+}
+
+}  // namespace
+
+struct chain_rk4 {
+    chain_rk4_desc d;
+    hipStream_t stream;
+    StateRef front, back;
+    NaiveBufs naive;
+    double *partials, *result;
+    Plan plan;
+    hipStream_t capture = nullptr;
+    std::map<int64_t, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+// Enqueue the passes of nsteps on stream s.
+int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
+    const chain_rk4_desc &d = h->d;
+    if (nsteps == 0) return CHAIN_OK;
+    if (d.method == CHAIN_NAIVE) {
+        for (int64_t i = 0; i < nsteps; ++i) {
+            hipError_t e = launch_naive_step(d.model, d.prec, h->front, h->naive, d.n, d.dt, s);
+            if (e != hipSuccess) return hip_fail(e, "naive step launch");
+        }
+        return CHAIN_OK;
+    }
+    if (h->plan.resident) {
+        ResidentRun r{h->front, h->front, d.n, d.dt, nsteps};
+        hipError_t e = launch_resident(d.model, d.prec, r, s);
+        if (e != hipSuccess) return hip_fail(e, "resident launch");
+        return CHAIN_OK;
+    }
+    // Passes of `depth` steps; the pass count is made even (by splitting one
+    // pass in two) so the state ends in the caller's buffers. Only when every
+    // pass is a single step does an odd count remain; then the state is copied
+    // back after the last pass.
+    const int K = h->plan.depth;
+    std::vector<int> ks(static_cast<size_t>(nsteps / K), K);
+    if (nsteps % K) ks.push_back(static_cast<int>(nsteps % K));
+    if (ks.size() % 2 == 1) {
+        for (size_t i = ks.size(); i-- > 0;) {
+            if (ks[i] >= 2) {
+                const int a = ks[i] / 2, b = ks[i] - a;
+                ks[i] = a;
+                ks.insert(ks.begin() + static_cast<long>(i) + 1, b);
+                break;
+            }
+        }
+    }
+    StateRef cur = h->front, nxt = h->back;
+    for (int k : ks) {
+        FusedPass a{cur, nxt, d.n, h->plan.tile, h->plan.halo, h->plan.waves, d.dt, k};
+        hipError_t e = launch_fused(d.model, d.prec, h->plan.sites, a, s);
+        if (e != hipSuccess) return hip_fail(e, "fused launch");
+        std::swap(cur, nxt);
+    }
+    if (ks.size() % 2 == 1) {
+        const size_t b = static_cast<size_t>(d.n) * elem_bytes(d.prec);
+        HIP_TRY(hipMemcpyAsync(h->front.q, cur.q, b, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->front.p, cur.p, b, hipMemcpyDeviceToDevice, s));
+        if (d.prec == CHAIN_FP32_KAHAN) {
+            const size_t cb = static_cast<size_t>(d.n) * sizeof(float);
+            HIP_TRY(hipMemcpyAsync(h->front.cq, cur.cq, cb, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(h->front.cp, cur.cp, cb, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    return CHAIN_OK;
+}
+
+int step_graph(chain_rk4 *h, int64_t nsteps) {
+    auto it = h->graphs.find(nsteps);
+    if (it == h->graphs.end()) {
+        if (h->graphs.size() >= 8) {
+            for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+            h->graphs.clear();
+        }
+        if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_steps(h, nsteps, h->capture);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(h->capture, &g);
+        if (rc != CHAIN_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        it = h->graphs.emplace(nsteps, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    return CHAIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d) {
+    if (check_desc(d) != CHAIN_OK) return 0;
+    return layout(d).total;
+}
+
+int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace, size_t ws_bytes,
+                     void *stream, chain_rk4 **out) {
+    int rc = check_desc(d);
+    if (rc != CHAIN_OK) return rc;
+    if (!out) return fail(CHAIN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!q || !p) return fail(CHAIN_EINVAL, "q and p must be device pointers");
+    if ((reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(p)) & 15)
+        return fail(CHAIN_EINVAL, "q and p must be 16-byte aligned");
+    const Layout L = layout(d);
+    if (ws_bytes < L.total)
+        return fail(CHAIN_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (!workspace) return fail(CHAIN_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1))
+        return fail(CHAIN_EINVAL, "workspace must be 256-byte aligned");
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (!is_gfx950(dev)) return fail(CHAIN_EDEVICE, "device %d is not a gfx950 GPU", dev);
+
+    chain_rk4 *h = new (std::nothrow) chain_rk4();
+    if (!h) return fail(CHAIN_ENOMEM, "out of host memory");
+    char *ws = static_cast<char *>(workspace);
+    h->d = *d;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->plan = make_plan(d);
+    h->front = StateRef{q, p, nullptr, nullptr};
+    h->back = StateRef{nullptr, nullptr, nullptr, nullptr};
+    if (d->method == CHAIN_FUSED) {
+        h->back.q = ws + L.back_q;
+        h->back.p = ws + L.back_p;
+    }
+    if (d->prec == CHAIN_FP32_KAHAN) {
+        h->front.cq = reinterpret_cast<float *>(ws + L.cq);
+        h->front.cp = reinterpret_cast<float *>(ws + L.cp);
+        if (d->method == CHAIN_FUSED) {
+            h->back.cq = reinterpret_cast<float *>(ws + L.back_cq);
+            h->back.cp = reinterpret_cast<float *>(ws + L.back_cp);
+        }
+    }
+    if (d->method == CHAIN_NAIVE) {
+        void **slots[10] = {&h->naive.k1q, &h->naive.k1p, &h->naive.k2q, &h->naive.k2p,
+                            &h->naive.k3q, &h->naive.k3p, &h->naive.yaq, &h->naive.yap,
+                            &h->naive.ybq, &h->naive.ybp};
+        for (int i = 0; i < 10; ++i) *slots[i] = ws + L.naive[i];
+    }
+    h->partials = reinterpret_cast<double *>(ws + L.partials);
+    h->result = reinterpret_cast<double *>(ws + L.result);
+    if (d->prec == CHAIN_FP32_KAHAN) {
+        const size_t cb = round_up(static_cast<size_t>(d->n) * sizeof(float));
+        hipError_t e = launch_fill_zero(h->front.cq, cb, h->stream);
+        if (e == hipSuccess) e = launch_fill_zero(h->front.cp, cb, h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "zeroing the carries");
+        }
+    }
+    *out = h;
+    return CHAIN_OK;
+}
+
+int chain_rk4_step(chain_rk4 *h, int64_t nsteps) {
+    if (!h) return fail(CHAIN_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(CHAIN_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return CHAIN_OK;
+    if (h->d.flags & CHAIN_FLAG_GRAPH) return step_graph(h, nsteps);
+    return enqueue_steps(h, nsteps, h->stream);
+}
+
+int chain_rk4_energy(chain_rk4 *h, double *e_out) {
+    if (!h || !e_out) return fail(CHAIN_EINVAL, "handle and e_out must be non-NULL");
+    hipError_t e = launch_energy(h->d.model, h->d.prec, h->front, h->d.n, h->partials, h->result,
+                                 h->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    double v = 0.0;
+    HIP_TRY(hipMemcpyAsync(&v, h->result, sizeof v, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *e_out = v;
+    if (!std::isfinite(v)) return fail(CHAIN_ENONFINITE, "energy is not finite (%g)", v);
+    return CHAIN_OK;
+}
+
+int chain_rk4_set_stream(chain_rk4 *h, void *stream) {
+    if (!h) return fail(CHAIN_EINVAL, "handle is NULL");
+    h->stream = static_cast<hipStream_t>(stream);
+    return CHAIN_OK;
+}
+
+int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out) {
+    if (!h || !out) return fail(CHAIN_EINVAL, "handle and out must be non-NULL");
+    chain_rk4_plan P{};
+    P.method = h->d.method;
+    P.resident = h->plan.resident ? 1 : 0;
+    P.sites_per_lane = h->plan.sites;
+    P.kdepth = h->plan.depth;
+    P.tile = h->plan.tile;
+    P.halo = h->plan.halo;
+    P.waves = h->plan.waves;
+    P.overlap_factor = h->plan.tile > 0 ? 1.0 + 2.0 * double(h->plan.halo) / double(h->plan.tile) : 1.0;
+    *out = P;
+    return CHAIN_OK;
+}
+
+int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp) {
+    if (!h || !cq || !cp) return fail(CHAIN_EINVAL, "handle, cq and cp must be non-NULL");
+    *cq = h->front.cq;
+    *cp = h->front.cp;
+    return CHAIN_OK;
+}
+
+int chain_rk4_destroy(chain_rk4 *h) {
+    if (!h) return CHAIN_OK;
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    delete h;
+    return CHAIN_OK;
+}
+
+const char *chain_rk4_strerror(int status) {
+    switch (status) {
+    case CHAIN_OK: return "success";
+    case CHAIN_EINVAL: return "invalid argument";
+    case CHAIN_ENOMEM: return "workspace too small";
+    case CHAIN_EHIP: return "HIP runtime error";
+    case CHAIN_ENONFINITE: return "energy is not finite";
+    case CHAIN_EDEVICE: return "device is not a gfx950 GPU";
+    default: return "unknown status";
+    }
+}
+
+const char *chain_rk4_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// fused.hip -- the fused, temporally blocked RK4 kernel and the resident
+// whole-ring kernel.
+//
+// Fused kernel (the GPU form of the granular scheme of Sec. 2.3): each
+// wavefront is one cluster. It holds E = 64*S consecutive sites, S per lane,
+// in registers, of which the middle `tile` sites are kept and `halo` sites on
+// each side are loaded only to be recomputed and discarded. With
+// halo = 4*ksteps the wrong values that enter at the cluster edges (one site
+// per stage, Sec. 2.3) never reach the kept sites, so one pass over memory
+// advances the chain by `ksteps` steps. Neighbour values inside a wavefront
+// move by DPP lane shifts; wavefronts never talk to each other, so there is no
+// LDS and no barrier. Input and output are different buffers (ping-pong):
+// clusters overlap, and updating in place would race.
+//
+// Resident kernel: one workgroup keeps a whole ring of up to 4096 sites on
+// chip (state in registers, stage arguments in LDS) for any number of steps.
+#include "launch.hpp"
+#include "rk4_device.hpp"
+
+namespace chainrk4 {
+namespace {
+
+template <class R, int S>
+__device__ __forceinline__ void load_contig(R (&dst)[S], const R *__restrict__ src) {
+    if constexpr (sizeof(R) == 8) {
+        const double2 *v = reinterpret_cast<const double2 *>(src);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) {
+            double2 t = v[m];
+            dst[2 * m] = t.x;
+            dst[2 * m + 1] = t.y;
+        }
+    } else {
+        const float4 *v = reinterpret_cast<const float4 *>(src);
+#pragma unroll
+        for (int m = 0; m < S / 4; ++m) {
+            float4 t = v[m];
+            dst[4 * m] = t.x;
+            dst[4 * m + 1] = t.y;
+            dst[4 * m + 2] = t.z;
+            dst[4 * m + 3] = t.w;
+        }
+    }
+}
+
+template <class R, int S>
+__device__ __forceinline__ void store_contig(R *__restrict__ dst, const R (&src)[S]) {
+    if constexpr (sizeof(R) == 8) {
+        double2 *v = reinterpret_cast<double2 *>(dst);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) v[m] = make_double2(src[2 * m], src[2 * m + 1]);
+    } else {
+        float4 *v = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+        for (int m = 0; m < S / 4; ++m)
+            v[m] = make_float4(src[4 * m], src[4 * m + 1], src[4 * m + 2], src[4 * m + 3]);
+    }
+}
+
+// One stage for the S sites of this lane, with the two edge bond terms
+// exchanged across lanes: first the right neighbour's first coordinate comes
+// in, this lane forms its last bond term, and that term goes to the right
+// neighbour lane as its left bond term.
+template <int M, int S, int STAGE, class R>
+__device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S], R (&aq)[S],
+                                           R (&ap)[S], const StepConsts<R> &c) {
+    const R first = (STAGE == 1) ? q[0] : Q[0];
+    const R last = (STAGE == 1) ? q[S - 1] : Q[S - 1];
+    const R right = from_right(first);
+    const R brS = ModelOps<M, R>::bond(right - last);
+    const R bl0 = from_left(brS);
+    stage_sites<M, S, STAGE>(Q, P, q, p, aq, ap, bl0, brS, c);
+}
+
+template <int M, class R, bool KAHAN, int S>
+__global__ __launch_bounds__(kFusedThreads) void fused_kernel(FusedPass a) {
+    constexpr int E = 64 * S;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kFusedThreads / 64) + (threadIdx.x >> 6);
+    if (wave >= a.waves) return;  // uniform per wavefront
+    const int64_t n = a.n;
+    const int64_t e0 = wave * a.tile - a.halo;
+    const int64_t s0 = e0 + static_cast<int64_t>(lane) * S;
+
+    const R *qin = static_cast<const R *>(a.in.q);
+    const R *pin = static_cast<const R *>(a.in.p);
+    R q[S], p[S];
+    float cq[S], cp[S];
+    const bool inside = e0 >= 0 && e0 + E <= n;
+    if (inside) {
+        load_contig<R, S>(q, qin + s0);
+        load_contig<R, S>(p, pin + s0);
+        if constexpr (KAHAN) {
+            load_contig<float, S>(cq, a.in.cq + s0);
+            load_contig<float, S>(cp, a.in.cp + s0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int64_t i = wrap_index(s0 + j, n);
+            q[j] = qin[i];
+            p[j] = pin[i];
+            if constexpr (KAHAN) {
+                cq[j] = a.in.cq[i];
+                cp[j] = a.in.cp[i];
+            }
+        }
+    }
+
+    const StepConsts<R> c(a.dt);
+    R Q[S], P[S], aq[S], ap[S];
+    for (int st = 0; st < a.ksteps; ++st) {
+        lane_stage<M, S, 1>(Q, P, q, p, aq, ap, c);
+        lane_stage<M, S, 2>(Q, P, q, p, aq, ap, c);
+        lane_stage<M, S, 3>(Q, P, q, p, aq, ap, c);
+        lane_stage<M, S, 4>(Q, P, q, p, aq, ap, c);
+        if constexpr (KAHAN)
+            final_update_kahan<S>(q, p, cq, cp, aq, ap, c);
+        else
+            final_update<S>(q, p, aq, ap, c);
+    }
+
+    R *qout = static_cast<R *>(a.out.q);
+    R *pout = static_cast<R *>(a.out.p);
+    const int lo = lane * S;
+    const int64_t keep_end = E - a.halo;
+    const bool full = lo >= a.halo && lo + S <= keep_end && s0 + S <= n;
+    if (full) {
+        store_contig<R, S>(qout + s0, q);
+        store_contig<R, S>(pout + s0, p);
+        if constexpr (KAHAN) {
+            store_contig<float, S>(a.out.cq + s0, cq);
+            store_contig<float, S>(a.out.cp + s0, cp);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int local = lo + j;
+            const int64_t g = s0 + j;
+            if (local >= a.halo && local < keep_end && g < n) {
+                qout[g] = q[j];
+                pout[g] = p[j];
+                if constexpr (KAHAN) {
+                    a.out.cq[g] = cq[j];
+                    a.out.cp[g] = cp[j];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Resident whole-ring kernel. Thread t owns sites t + 256*j, j < SPT. The
+// stage argument Q of every site is published in LDS (two buffers used in
+// turn, one barrier per stage); P, the accumulators and the state stay in
+// registers.
+// ---------------------------------------------------------------------------
+template <int M, class R, bool KAHAN, int SPT>
+__global__ __launch_bounds__(kResidentThreads) void resident_kernel(ResidentRun a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = static_cast<int>(a.n);
+    R *buf0 = reinterpret_cast<R *>(smem);
+    R *buf1 = buf0 + n;
+    const int t = threadIdx.x;
+    const R *qin = static_cast<const R *>(a.in.q);
+    const R *pin = static_cast<const R *>(a.in.p);
+
+    R q[SPT], p[SPT], P[SPT], aq[SPT], ap[SPT];
+    float cq[SPT], cp[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = t + kResidentThreads * j;
+        if (i < n) {
+            q[j] = qin[i];
+            p[j] = pin[i];
+            if constexpr (KAHAN) {
+                cq[j] = a.in.cq[i];
+                cp[j] = a.in.cp[i];
+            }
+            buf0[i] = q[j];
+        }
+    }
+    __syncthreads();
+
+    const StepConsts<R> c(a.dt);
+    for (int64_t st = 0; st < a.nsteps; ++st) {
+        // stage j reads its argument from `cur` and publishes the next one
+        // (after stage 4: the new coordinates) in `nxt`
+#pragma unroll
+        for (int stage = 1; stage <= 4; ++stage) {
+            const R *cur = (stage & 1) ? buf0 : buf1;
+            R *nxt = (stage & 1) ? buf1 : buf0;
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) {
+                const int i = t + kResidentThreads * j;
+                if (i < n) {
+                    const int im = (i == 0) ? n - 1 : i - 1;
+                    const int ip = (i == n - 1) ? 0 : i + 1;
+                    const R Qm = cur[im], Qj = cur[i], Qp = cur[ip];
+                    R Qn = Qj, Pn = P[j];
+                    if (stage == 1) {
+                        stage_one<M, 1, R>(Qm, Qj, Qp, p[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                    } else if (stage == 2) {
+                        stage_one<M, 2, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                    } else if (stage == 3) {
+                        stage_one<M, 3, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                    } else {
+                        stage_one<M, 4, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                        if constexpr (KAHAN) {
+                            kahan_add(q[j], cq[j], c.h6 * aq[j]);
+                            kahan_add(p[j], cp[j], c.h6 * ap[j]);
+                        } else {
+                            q[j] = __builtin_fma(c.h6, aq[j], q[j]);
+                            p[j] = __builtin_fma(c.h6, ap[j], p[j]);
+                        }
+                        Qn = q[j];  // the next step's first argument
+                    }
+                    nxt[i] = Qn;
+                    if (stage != 4) P[j] = Pn;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    R *qout = static_cast<R *>(a.out.q);
+    R *pout = static_cast<R *>(a.out.p);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = t + kResidentThreads * j;
+        if (i < n) {
+            qout[i] = q[j];
+            pout[i] = p[j];
+            if constexpr (KAHAN) {
+                a.out.cq[i] = cq[j];
+                a.out.cp[i] = cp[j];
+            }
+        }
+    }
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t fused_dispatch_s(int s, const FusedPass &a, hipStream_t st) {
+    const int64_t blocks64 = (a.waves + (kFusedThreads / 64) - 1) / (kFusedThreads / 64);
+    if (blocks64 <= 0 || blocks64 > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(blocks64)), block(kFusedThreads);
+    switch (s) {
+    case 4: fused_kernel<M, R, KAHAN, 4><<<grid, block, 0, st>>>(a); break;
+    case 8: fused_kernel<M, R, KAHAN, 8><<<grid, block, 0, st>>>(a); break;
+    case 16: fused_kernel<M, R, KAHAN, 16><<<grid, block, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t resident_dispatch(const ResidentRun &a, hipStream_t st) {
+    const int spt = static_cast<int>((a.n + kResidentThreads - 1) / kResidentThreads);
+    const size_t lds = 2 * static_cast<size_t>(a.n) * sizeof(R);
+    const dim3 grid(1), block(kResidentThreads);
+    if (spt <= 1) resident_kernel<M, R, KAHAN, 1><<<grid, block, lds, st>>>(a);
+    else if (spt <= 2) resident_kernel<M, R, KAHAN, 2><<<grid, block, lds, st>>>(a);
+    else if (spt <= 4) resident_kernel<M, R, KAHAN, 4><<<grid, block, lds, st>>>(a);
+    else if (spt <= 8) resident_kernel<M, R, KAHAN, 8><<<grid, block, lds, st>>>(a);
+    else if (spt <= 16) resident_kernel<M, R, KAHAN, 16><<<grid, block, lds, st>>>(a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fused(int model, int prec, int s, const FusedPass &a, hipStream_t st) {
+    if (model == kQuartic) {
+        return prec == 0 ? fused_dispatch_s<kQuartic, double, false>(s, a, st)
+                         : fused_dispatch_s<kQuartic, float, true>(s, a, st);
+    }
+    return prec == 0 ? fused_dispatch_s<kHarmonic, double, false>(s, a, st)
+                     : fused_dispatch_s<kHarmonic, float, true>(s, a, st);
+}
+
+size_t resident_lds_bytes(int prec, int64_t n) {
+    return 2 * static_cast<size_t>(n) * (prec == 0 ? sizeof(double) : sizeof(float));
+}
+
+hipError_t launch_resident(int model, int prec, const ResidentRun &a, hipStream_t st) {
+    if (a.n < 1 || a.n > kResidentMaxSites) return hipErrorInvalidValue;
+    if (model == kQuartic) {
+        return prec == 0 ? resident_dispatch<kQuartic, double, false>(a, st)
+                         : resident_dispatch<kQuartic, float, true>(a, st);
+    }
+    return prec == 0 ? resident_dispatch<kHarmonic, double, false>(a, st)
+                     : resident_dispatch<kHarmonic, float, true>(a, st);
+}
+
+}  // namespace chainrk4

@@ -1,0 +1,98 @@
+// naive.hip -- the standard implementation of an RK4 step (Sec. 2.2): one
+// kernel per stage, each a full sweep over the chain whose results (the
+// slope k_j and the next stage argument, Eq. 3-4) go through memory. Stage 4
+// reads k1..k3 back and applies the final combination (Eq. 5) in place. It is
+// the baseline the fused kernel is measured against, and it uses the same
+// per-site operation order, so both give identical bits.
+#include "launch.hpp"
+#include "rk4_device.hpp"
+
+namespace chainrk4 {
+namespace {
+
+constexpr int kNaiveThreads = 256;
+
+template <int M, class R, bool KAHAN, int STAGE>
+__global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBufs b, int64_t n,
+                                                             double dt) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kNaiveThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t im = (i == 0) ? n - 1 : i - 1;
+    const int64_t ip = (i == n - 1) ? 0 : i + 1;
+    const R *yq = static_cast<const R *>(y.q);
+    const R *yp = static_cast<const R *>(y.p);
+    // stage argument: y itself, then the ping-pong stage buffers
+    const R *aq = STAGE == 1 ? yq : STAGE == 3 ? static_cast<const R *>(b.ybq) : static_cast<const R *>(b.yaq);
+    const R *ap = STAGE == 1 ? yp : STAGE == 3 ? static_cast<const R *>(b.ybp) : static_cast<const R *>(b.yap);
+    const StepConsts<R> c(dt);
+
+    const R Qj = aq[i];
+    const R Pj = ap[i];
+    const R bl = ModelOps<M, R>::bond(Qj - aq[im]);
+    const R br = ModelOps<M, R>::bond(aq[ip] - Qj);
+    const R F = site_force<M, R>(bl, br, Qj);
+    const R qj = yq[i];
+    const R pj = yp[i];
+
+    if constexpr (STAGE < 4) {
+        R *kq = static_cast<R *>(STAGE == 1 ? b.k1q : STAGE == 2 ? b.k2q : b.k3q);
+        R *kp = static_cast<R *>(STAGE == 1 ? b.k1p : STAGE == 2 ? b.k2p : b.k3p);
+        R *nq = static_cast<R *>(STAGE == 2 ? b.ybq : b.yaq);
+        R *np = static_cast<R *>(STAGE == 2 ? b.ybp : b.yap);
+        const R a = STAGE == 3 ? c.h : c.hh;
+        kq[i] = Pj;
+        kp[i] = F;
+        nq[i] = __builtin_fma(a, Pj, qj);
+        np[i] = __builtin_fma(a, F, pj);
+    } else {
+        R accq = static_cast<const R *>(b.k1q)[i];
+        R accp = static_cast<const R *>(b.k1p)[i];
+        accq = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k2q)[i], accq);
+        accp = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k2p)[i], accp);
+        accq = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k3q)[i], accq);
+        accp = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k3p)[i], accp);
+        accq = accq + Pj;
+        accp = accp + F;
+        R *wq = static_cast<R *>(y.q);
+        R *wp = static_cast<R *>(y.p);
+        if constexpr (KAHAN) {
+            R q1 = qj, p1 = pj;
+            float cq = y.cq[i], cp = y.cp[i];
+            kahan_add(q1, cq, c.h6 * accq);
+            kahan_add(p1, cp, c.h6 * accp);
+            wq[i] = q1;
+            wp[i] = p1;
+            y.cq[i] = cq;
+            y.cp[i] = cp;
+        } else {
+            wq[i] = __builtin_fma(c.h6, accq, qj);
+            wp[i] = __builtin_fma(c.h6, accp, pj);
+        }
+    }
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t naive_dispatch(StateRef y, const NaiveBufs &b, int64_t n, double dt, hipStream_t s) {
+    const int64_t blocks = (n + kNaiveThreads - 1) / kNaiveThreads;
+    if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(blocks)), block(kNaiveThreads);
+    naive_stage<M, R, KAHAN, 1><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 2><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 3><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 4><<<grid, block, 0, s>>>(y, b, n, dt);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,
+                             double dt, hipStream_t s) {
+    if (model == kQuartic) {
+        return prec == 0 ? naive_dispatch<kQuartic, double, false>(y, b, n, dt, s)
+                         : naive_dispatch<kQuartic, float, true>(y, b, n, dt, s);
+    }
+    return prec == 0 ? naive_dispatch<kHarmonic, double, false>(y, b, n, dt, s)
+                     : naive_dispatch<kHarmonic, float, true>(y, b, n, dt, s);
+}
+
+}  // namespace chainrk4

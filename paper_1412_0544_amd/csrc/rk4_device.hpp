@@ -1,0 +1,214 @@
+// rk4_device.hpp -- per-site arithmetic of the chain RK4 step, shared by every
+// GPU kernel of the library so that all of them produce identical bits.
+//
+// The vector field is the homogeneous nearest-neighbour form of Sec. 2.1
+// Eq. 2 written for a chain with coordinates q and momenta p:
+//   dq_i/dt = p_i,  dp_i/dt = F_i = (phi(d_i) - phi(d_{i-1})) - U'(q_i),
+//   d_i = q_{i+1} - q_i  (the bond to the right neighbour).
+// quartic:  phi(d) = d^3, U'(q) = q + q^3
+// harmonic: phi(d) = d,   U'(q) = q
+// Every bond term phi(d_i) is computed once and used by both sites it joins.
+//
+// One RK4 step (Sec. 2.2 Eq. 3-5, classical tableau) per site, h = dt:
+//   stage j evaluates F at the stage argument (Q, P); k_j = (P, F)
+//   acc = k1 + 2 k2 + 2 k3 + k4, accumulated in that order
+//   stage arguments: (Q, P) = (q, p) + a_j h k_j with a = (1/2, 1/2, 1)
+//   final: y = y + (h/6) acc   (FP64: one fma; FP32: Kahan-compensated)
+// Operation order is fixed here; kernels call these helpers only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chainrk4 {
+
+enum Model : int { kQuartic = 0, kHarmonic = 1 };
+
+template <int M, class R>
+struct ModelOps;
+
+template <class R>
+struct ModelOps<kQuartic, R> {
+    __device__ __forceinline__ static R bond(R d) { return (d * d) * d; }
+    __device__ __forceinline__ static R onsite(R q) { return __builtin_fma(q * q, q, q); }
+    // energy density of the site and its right bond, in FP64
+    __device__ __forceinline__ static double energy(double q, double p, double d) {
+        double q2 = q * q, d2 = d * d;
+        return 0.5 * (p * p) + 0.5 * q2 + 0.25 * (q2 * q2) + 0.25 * (d2 * d2);
+    }
+};
+
+template <class R>
+struct ModelOps<kHarmonic, R> {
+    __device__ __forceinline__ static R bond(R d) { return d; }
+    __device__ __forceinline__ static R onsite(R q) { return q; }
+    __device__ __forceinline__ static double energy(double q, double p, double d) {
+        return 0.5 * (p * p) + 0.5 * (q * q) + 0.5 * (d * d);
+    }
+};
+
+// Force on a site from its left bond term, right bond term and coordinate.
+template <int M, class R>
+__device__ __forceinline__ R site_force(R bl, R br, R q) {
+    return (br - bl) - ModelOps<M, R>::onsite(q);
+}
+
+// Step constants in the working precision.
+template <class R>
+struct StepConsts {
+    R h, hh, h6;
+    __device__ __forceinline__ explicit StepConsts(double dt)
+        : h(static_cast<R>(dt)),
+          hh(static_cast<R>(0.5) * static_cast<R>(dt)),
+          h6(static_cast<R>(dt) / static_cast<R>(6)) {}
+};
+
+// Kahan-compensated y += delta with carry c (the true value is y - c).
+__device__ __forceinline__ void kahan_add(float &y, float &c, float delta) {
+    float v = delta - c;
+    float t = y + v;
+    c = (t - y) - v;
+    y = t;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront neighbour exchange (wave64, DPP). from_right(x): lane i receives
+// lane i+1's x; lane 63 keeps its own. from_left(x): lane i receives lane
+// i-1's x; lane 0 keeps its own. The kernels only use the edge lanes' results
+// inside the recomputed halo, so what those lanes keep never reaches output.
+// ---------------------------------------------------------------------------
+constexpr int kDppWaveShl1 = 0x130;  // wave_shl:1
+constexpr int kDppWaveShr1 = 0x138;  // wave_shr:1
+constexpr int kDppWaveRol1 = 0x134;  // wave_rol:1
+constexpr int kDppWaveRor1 = 0x13C;  // wave_ror:1
+
+template <int Ctrl>
+__device__ __forceinline__ int dpp32(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, Ctrl, 0xF, 0xF, false);
+}
+
+template <int Ctrl>
+__device__ __forceinline__ double dpp(double x) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = dpp32<Ctrl>(lo);
+    hi = dpp32<Ctrl>(hi);
+    return __hiloint2double(hi, lo);
+}
+
+template <int Ctrl>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(dpp32<Ctrl>(__float_as_int(x)));
+}
+
+template <class R>
+__device__ __forceinline__ R from_right(R x) { return dpp<kDppWaveShl1>(x); }
+template <class R>
+__device__ __forceinline__ R from_left(R x) { return dpp<kDppWaveShr1>(x); }
+// Rotations (lane 63 <-> lane 0) for a ring held by exactly one wavefront.
+template <class R>
+__device__ __forceinline__ R from_right_ring(R x) { return dpp<kDppWaveRol1>(x); }
+template <class R>
+__device__ __forceinline__ R from_left_ring(R x) { return dpp<kDppWaveRor1>(x); }
+
+// ---------------------------------------------------------------------------
+// One RK4 stage over the S consecutive sites a lane holds.
+//   Q, P    stage argument (in), overwritten with the next stage argument
+//   q, p    state at the start of the step; after stage 4, the new state
+//   aq, ap  accumulators k1 + 2 k2 + 2 k3 (+ k4)
+//   bl0     bond term left of site 0; brS bond term right of site S-1
+// Stage 1 reads its argument from q, p (Q, P are outputs only).
+// ---------------------------------------------------------------------------
+template <int M, int S, int STAGE, class R>
+__device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
+                                            R (&aq)[S], R (&ap)[S], R bl0, R brS,
+                                            const StepConsts<R> &c) {
+    R bl = bl0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const R Qj = (STAGE == 1) ? q[j] : Q[j];
+        const R Pj = (STAGE == 1) ? p[j] : P[j];
+        R br;
+        if (j + 1 < S) {
+            const R Qn = (STAGE == 1) ? q[j + 1] : Q[j + 1];
+            br = ModelOps<M, R>::bond(Qn - Qj);
+        } else {
+            br = brS;
+        }
+        const R F = site_force<M, R>(bl, br, Qj);
+        bl = br;
+        if (STAGE == 1) {
+            aq[j] = Pj;
+            ap[j] = F;
+            Q[j] = __builtin_fma(c.hh, Pj, q[j]);
+            P[j] = __builtin_fma(c.hh, F, p[j]);
+        } else if (STAGE == 2) {
+            aq[j] = __builtin_fma(static_cast<R>(2), Pj, aq[j]);
+            ap[j] = __builtin_fma(static_cast<R>(2), F, ap[j]);
+            Q[j] = __builtin_fma(c.hh, Pj, q[j]);
+            P[j] = __builtin_fma(c.hh, F, p[j]);
+        } else if (STAGE == 3) {
+            aq[j] = __builtin_fma(static_cast<R>(2), Pj, aq[j]);
+            ap[j] = __builtin_fma(static_cast<R>(2), F, ap[j]);
+            Q[j] = __builtin_fma(c.h, Pj, q[j]);
+            P[j] = __builtin_fma(c.h, F, p[j]);
+        } else {
+            aq[j] = aq[j] + Pj;
+            ap[j] = ap[j] + F;
+        }
+    }
+}
+
+// Final combination (Eq. 5) for FP64: y = y + (h/6) acc.
+template <int S>
+__device__ __forceinline__ void final_update(double (&q)[S], double (&p)[S], const double (&aq)[S],
+                                             const double (&ap)[S], const StepConsts<double> &c) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        q[j] = __builtin_fma(c.h6, aq[j], q[j]);
+        p[j] = __builtin_fma(c.h6, ap[j], p[j]);
+    }
+}
+
+// Final combination for FP32 with the Kahan-compensated sum.
+template <int S>
+__device__ __forceinline__ void final_update_kahan(float (&q)[S], float (&p)[S], float (&cq)[S],
+                                                   float (&cp)[S], const float (&aq)[S],
+                                                   const float (&ap)[S], const StepConsts<float> &c) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        kahan_add(q[j], cq[j], c.h6 * aq[j]);
+        kahan_add(p[j], cp[j], c.h6 * ap[j]);
+    }
+}
+
+// Same arithmetic for one site held alone (naive and resident kernels).
+template <int M, int STAGE, class R>
+__device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R &aq, R &ap,
+                                          R &Qn, R &Pn, const StepConsts<R> &c) {
+    const R bl = ModelOps<M, R>::bond(Qj - Qm);
+    const R br = ModelOps<M, R>::bond(Qp - Qj);
+    const R F = site_force<M, R>(bl, br, Qj);
+    if (STAGE == 1) {
+        aq = Pj; ap = F;
+        Qn = __builtin_fma(c.hh, Pj, qj); Pn = __builtin_fma(c.hh, F, pj);
+    } else if (STAGE == 2) {
+        aq = __builtin_fma(static_cast<R>(2), Pj, aq);
+        ap = __builtin_fma(static_cast<R>(2), F, ap);
+        Qn = __builtin_fma(c.hh, Pj, qj); Pn = __builtin_fma(c.hh, F, pj);
+    } else if (STAGE == 3) {
+        aq = __builtin_fma(static_cast<R>(2), Pj, aq);
+        ap = __builtin_fma(static_cast<R>(2), F, ap);
+        Qn = __builtin_fma(c.h, Pj, qj); Pn = __builtin_fma(c.h, F, pj);
+    } else {
+        aq = aq + Pj; ap = ap + F;
+    }
+}
+
+// Ring index of an unwrapped site index (any sign, any multiple of n).
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
+    if (i >= 0 && i < n) return i;
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace chainrk4

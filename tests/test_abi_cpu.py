@@ -1,0 +1,100 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol,
+and rejects invalid arguments before touching the HIP runtime."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_0544_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chain_rk4.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chain_rk4_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = L.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def desc(**kw):
+    d = dict(n=1000, model=0, prec=0, dt=0.01, method=0, sites_per_lane=0, kdepth=0, flags=0)
+    d.update(kw)
+    return L.Desc(**d)
+
+
+def test_workspace_bytes():
+    lib = L.lib()
+    f = lambda d: lib.chain_rk4_workspace_bytes(ctypes.byref(d))
+    fused = f(desc(n=1 << 20))
+    assert fused >= 2 * 8 * (1 << 20)
+    assert f(desc(n=1 << 20, prec=1)) >= 6 * 4 * (1 << 20)
+    assert f(desc(n=1 << 20, method=1)) >= 10 * 8 * (1 << 20)
+    for bad in (desc(n=0), desc(model=7), desc(prec=3), desc(dt=float("nan")),
+                desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
+                desc(kdepth=17), desc(kdepth=-1), desc(flags=64)):
+        assert f(bad) == 0
+    assert lib.chain_rk4_workspace_bytes(None) == 0
+
+
+def test_create_rejects_bad_arguments_before_any_hip_call():
+    lib = L.lib()
+    h = L.H()
+    d = desc()
+    ws = lib.chain_rk4_workspace_bytes(ctypes.byref(d))
+    fake = 1 << 20  # never dereferenced: validation fails first
+    cases = [
+        (ctypes.byref(desc(n=0)), fake, fake, fake, ws, L.CHAIN_EINVAL),
+        (ctypes.byref(d), None, fake, fake, ws, L.CHAIN_EINVAL),
+        (ctypes.byref(d), fake, None, fake, ws, L.CHAIN_EINVAL),
+        (ctypes.byref(d), fake + 8, fake, fake, ws, L.CHAIN_EINVAL),
+        (ctypes.byref(d), fake, fake, fake, ws - 1, L.CHAIN_ENOMEM),
+        (ctypes.byref(d), fake, fake, None, ws, L.CHAIN_EINVAL),
+        (ctypes.byref(d), fake, fake, fake + 16, ws, L.CHAIN_EINVAL),
+    ]
+    for dp, q, p, w, nb, want in cases:
+        assert lib.chain_rk4_create(dp, q, p, w, nb, None, ctypes.byref(h)) == want
+        assert lib.chain_rk4_last_error()
+    assert lib.chain_rk4_create(ctypes.byref(d), fake, fake, fake, ws, None, None) == L.CHAIN_EINVAL
+
+
+def test_null_handles():
+    lib = L.lib()
+    assert lib.chain_rk4_destroy(None) == L.CHAIN_OK
+    assert lib.chain_rk4_step(None, 1) == L.CHAIN_EINVAL
+    e = ctypes.c_double()
+    assert lib.chain_rk4_energy(None, ctypes.byref(e)) == L.CHAIN_EINVAL
+    assert lib.chain_rk4_get_plan(None, None) == L.CHAIN_EINVAL
+    assert lib.chain_rk4_set_stream(None, None) == L.CHAIN_EINVAL
+
+
+def test_strerror_covers_all_codes():
+    lib = L.lib()
+    seen = set()
+    for code in (0, -1, -2, -3, -4, -5):
+        s = lib.chain_rk4_strerror(code).decode()
+        assert s and s != "unknown status"
+        seen.add(s)
+    assert len(seen) == 6
+    assert lib.chain_rk4_strerror(12345) == b"unknown status"
+
+
+def test_oracle_is_not_linked_into_the_product():
+    import subprocess
+    out = subprocess.run(["nm", "-D", L.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle_" not in out
+    src_dir = os.path.join(ROOT, "paper_1412_0544_amd")
+    for dirpath, _, files in os.walk(src_dir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f

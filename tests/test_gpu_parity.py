@@ -1,0 +1,245 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+FP64 bar: max-abs state error <= 1e-10 after 100 steps (and after 1000 on the
+1024-site ring), energy within 1e-12 relative. Every GPU path (fused at any
+tile shape and depth, naive, resident) gives the same bits.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.special import ellipj
+
+import oracle
+import workloads
+from paper_1412_0544_amd import Chain
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+MODELS = {"quartic": oracle.QUARTIC, "harmonic": oracle.HARMONIC}
+
+
+def gpu_run(q0, p0, dt, steps, **kw):
+    ch = Chain(q0, p0, dt, **kw)
+    ch.step(steps)
+    e = ch.energy()
+    q, p = (t.cpu().numpy() for t in ch.state())
+    plan = ch.plan()
+    ch.close()
+    return q, p, e, plan
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run(model, n, seed, dt, steps):
+    q0, p0 = workloads.chain_ics(n, seed)
+    return oracle.rk4(MODELS[model], q0, p0, dt, steps, threads=8)
+
+
+def maxerr(a, b):
+    return float(np.max(np.abs(a - b))) if a.size else 0.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257, 1000, 5003, 20011])
+@pytest.mark.parametrize("sites,depth", [(4, 1), (8, 3), (16, 8), (8, 16), (4, 4)])
+def test_fused_tiled_matches_oracle(n, sites, depth):
+    q0, p0 = workloads.chain_ics(n, 1)
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 100, sites_per_lane=sites, kdepth=depth,
+                            resident=False)
+    assert plan["resident"] == 0 and plan["sites_per_lane"] == sites
+    qo, po = oracle_run("quartic", n, 1, 0.01, 100)
+    assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
+    eo = oracle.energy(oracle.QUARTIC, qo, po)
+    assert abs(e - eo) <= 1e-12 * abs(eo)
+
+
+@pytest.mark.parametrize("n", [1, 5, 640, 4099])
+def test_harmonic_fused_matches_oracle(n):
+    q0, p0 = workloads.chain_ics(n, 2)
+    q, p, e, _ = gpu_run(q0, p0, 0.05, 100, model="harmonic", sites_per_lane=8, kdepth=4,
+                         resident=False)
+    qo, po = oracle_run("harmonic", n, 2, 0.05, 100)
+    assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
+    eo = oracle.energy(oracle.HARMONIC, qo, po)
+    assert abs(e - eo) <= 1e-12 * abs(eo)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 100, 1024, 4096])
+@pytest.mark.parametrize("model", ["quartic", "harmonic"])
+def test_resident_naive_and_tiled_identical_bits(n, model):
+    q0, p0 = workloads.chain_ics(n, 3)
+    ref = gpu_run(q0, p0, 0.01, 37, model=model, sites_per_lane=8, kdepth=5, resident=False)
+    res = gpu_run(q0, p0, 0.01, 37, model=model)
+    assert res[3]["resident"] == 1
+    nav = gpu_run(q0, p0, 0.01, 37, model=model, method="naive")
+    for other in (res, nav):
+        assert np.array_equal(other[0], ref[0]) and np.array_equal(other[1], ref[1])
+    qo, po = oracle_run(model, n, 3, 0.01, 37)
+    assert maxerr(ref[0], qo) <= TOL and maxerr(ref[1], po) <= TOL
+
+
+def test_tile_shapes_and_depths_identical_bits():
+    n = 30011
+    q0, p0 = workloads.chain_ics(n, 4)
+    ref = gpu_run(q0, p0, 0.01, 24, sites_per_lane=4, kdepth=1, resident=False)
+    for s in (4, 8, 16):
+        for k in (2, 3, 6, 8, 12, 16):
+            got = gpu_run(q0, p0, 0.01, 24, sites_per_lane=s, kdepth=k, resident=False)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (s, k)
+            assert got[2] == ref[2]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ring_1024_1000_steps(seed):
+    """The 1024-site ring, dt = 0.01, 1000 steps, resident on chip."""
+    q0, p0 = workloads.chain_ics(1024, seed)
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 1000)
+    assert plan["resident"] == 1
+    qo, po = oracle_run("quartic", 1024, seed, 0.01, 1000)
+    assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
+    eo = oracle.energy(oracle.QUARTIC, qo, po)
+    assert abs(e - eo) <= 1e-12 * abs(eo)
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 3, 5, 8, 9, 17])
+@pytest.mark.parametrize("depth", [1, 4])
+def test_step_counts_and_pass_parity(steps, depth):
+    """Odd and even pass counts, split passes and the copy-back path."""
+    n = 3001
+    q0, p0 = workloads.chain_ics(n, 5)
+    q, p, _, _ = gpu_run(q0, p0, 0.01, steps, sites_per_lane=8, kdepth=depth, resident=False)
+    qo, po = oracle_run("quartic", n, 5, 0.01, steps)
+    assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
+    if steps == 0:
+        assert np.array_equal(q, q0) and np.array_equal(p, p0)
+
+
+def test_split_calls_equal_one_call():
+    n = 7000
+    q0, p0 = workloads.chain_ics(n, 6)
+    one = gpu_run(q0, p0, 0.01, 60, sites_per_lane=8, kdepth=8, resident=False)
+    ch = Chain(q0, p0, 0.01, sites_per_lane=8, kdepth=8, resident=False)
+    for k in (1, 7, 13, 39):
+        ch.step(k)
+    q, p = (t.cpu().numpy() for t in ch.state())
+    ch.close()
+    assert np.array_equal(q, one[0]) and np.array_equal(p, one[1])
+
+
+def test_time_reversal_bitwise():
+    n = 2050
+    q0, p0 = workloads.chain_ics(n, 7)
+    a = gpu_run(q0, -p0, 0.01, 40, sites_per_lane=8, kdepth=4, resident=False)
+    b = gpu_run(q0, p0, -0.01, 40, sites_per_lane=16, kdepth=8, resident=False)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], -b[1])
+
+
+def test_shift_and_reflection_bitwise():
+    n = 5000
+    q0, p0 = workloads.chain_ics(n, 8)
+    kw = dict(sites_per_lane=8, kdepth=4, resident=False)
+    base = gpu_run(q0, p0, 0.01, 32, **kw)
+    for s in (1, 77, 4999):
+        sh = gpu_run(np.roll(q0, s), np.roll(p0, s), 0.01, 32, **kw)
+        assert np.array_equal(sh[0], np.roll(base[0], s)) and np.array_equal(sh[1], np.roll(base[1], s))
+    rf = gpu_run(q0[::-1].copy(), p0[::-1].copy(), 0.01, 32, **kw)
+    assert np.array_equal(rf[0][::-1], base[0]) and np.array_equal(rf[1][::-1], base[1])
+
+
+def test_graph_replays_match_eager():
+    n = 9000
+    q0, p0 = workloads.chain_ics(n, 9)
+    eager = Chain(q0, p0, 0.01, sites_per_lane=8, kdepth=4, resident=False)
+    graph = Chain(q0, p0, 0.01, sites_per_lane=8, kdepth=4, resident=False, graph=True)
+    for rep in range(4):
+        eager.step(10)
+        graph.step(10)
+        torch.cuda.synchronize()
+        assert torch.equal(eager.q, graph.q) and torch.equal(eager.p, graph.p), rep
+        _ = eager.energy()
+    eager.close()
+    graph.close()
+
+
+FULL = 1 << 24
+
+
+@pytest.fixture(scope="module")
+def full_ics():
+    return workloads.chain_ics(FULL, 0)
+
+
+def test_full_size_sampled_sites(full_ics):
+    """N = 2^24, dt = 0.01, 100 steps, default fused plan: sampled sites vs the
+    oracle, each from its own light cone."""
+    q0, p0 = full_ics
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 100)
+    assert plan["resident"] == 0
+    tile = plan["tile"]
+    rng = np.random.default_rng(0)
+    sites = np.unique(np.concatenate([
+        [0, 1, FULL - 1, FULL - 2, tile - 1, tile, 2 * tile - 1, 2 * tile],
+        (np.arange(1, 9) * 1_999_993) % FULL,
+        rng.integers(0, FULL, 16)]))
+    qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, 0.01, 100, sites)
+    assert maxerr(q[sites], qs) <= TOL and maxerr(p[sites], ps) <= TOL
+    assert np.all(np.isfinite(q)) and np.all(np.isfinite(p))
+
+
+def test_full_size_pi_mode_closed_form():
+    """q_i = (-1)^i A stays an exact alternation (any halo or tile-edge error
+    breaks it) and follows A cn(Omega t | m) with Omega^2 = 1 + 17 A^2."""
+    A, dt, steps = 0.8, 0.01, 1000
+    q0, p0 = workloads.mode_ics(FULL, "pi", A)
+    q, p, e, _ = gpu_run(q0, p0, dt, steps)
+    s = np.where(np.arange(FULL) % 2 == 0, 1.0, -1.0)
+    assert np.array_equal(q * s, np.full(FULL, q[0]))
+    assert np.array_equal(p * s, np.full(FULL, p[0]))
+    om = math.sqrt(1 + 17 * A * A)
+    m = 17 * A * A / (2 * om * om)
+    sn, cn, dn, _ = ellipj(om * steps * dt, m)
+    assert abs(q[0] - A * cn) < 2e-6
+    assert abs(e - FULL * (A * A / 2 + 17 * A ** 4 / 4)) <= 1e-6 * e
+
+
+# --------------------------------------------------------------------------
+# FP32 state with compensated update (stated accuracy against the FP64
+# oracle started from the FP32-rounded initial state).
+# --------------------------------------------------------------------------
+
+FP32_TOL_100 = 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 3, 1000, 20011])
+def test_fp32_kahan_error_bound(n):
+    q0, p0 = workloads.chain_ics(n, 10, dtype=np.float32)
+    ch = Chain(q0, p0, 0.01, prec="fp32_kahan", sites_per_lane=16, kdepth=4, resident=False)
+    ch.step(100)
+    cq, cp = ch.carry_tensors()
+    q = ch.q.double() - cq.double()
+    p = ch.p.double() - cp.double()
+    e = ch.energy()
+    q, p = q.cpu().numpy(), p.cpu().numpy()
+    ch.close()
+    qo, po = oracle.rk4(oracle.QUARTIC, q0.astype(np.float64), p0.astype(np.float64), 0.01, 100)
+    assert maxerr(q, qo) <= FP32_TOL_100 and maxerr(p, po) <= FP32_TOL_100
+    eo = oracle.energy(oracle.QUARTIC, qo, po)
+    assert abs(e - eo) <= 1e-5 * abs(eo)
+
+
+def test_fp32_paths_identical_bits():
+    n = 4000
+    q0, p0 = workloads.chain_ics(n, 11, dtype=np.float32)
+    outs = []
+    for kw in (dict(sites_per_lane=16, kdepth=4, resident=False),
+               dict(sites_per_lane=8, kdepth=7, resident=False),
+               dict(method="naive"), dict()):
+        ch = Chain(q0, p0, 0.01, prec="fp32_kahan", **kw)
+        ch.step(30)
+        cq, cp = ch.carry_tensors()
+        outs.append([t.cpu().numpy().copy() for t in (ch.q, ch.p, cq, cp)])
+        ch.close()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
