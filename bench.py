@@ -136,8 +136,9 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--job-steps", type=int, default=1000)
     ap.add_argument("--sites", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--kdepth", type=int, default=0)
-    ap.add_argument("--sweep", action="store_true", help="time every (sites, depth) and naive")
+    ap.add_argument("--sweep", action="store_true", help="time the full (S, W, k) grid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args(argv)
@@ -160,25 +161,23 @@ def main(argv=None):
     qd = torch.from_numpy(q0).to(dev)
     pd = torch.from_numpy(p0).to(dev)
 
+    from paper_1412_0544_amd import autotune
     sweep = {}
-    if args.sweep or (args.sites == 0 and args.kdepth == 0):
-        cands = [(s, k) for s in (8, 16) for k in (1, 2, 4, 6, 8, 12, 16)]
-        if args.sweep:
-            cands = [(s, k) for s in (4, 8, 16) for k in (1, 2, 4, 6, 8, 12, 16)]
-        for s, k in cands:
-            ch = Chain(qd, pd, dt, sites_per_lane=s, kdepth=k, resident=False, device=dev)
-            ch.step(2 * k)
-            _, g, _ = time_jobs(ch, 48, 3, with_energy=False)
-            sweep[f"s{s}_k{k}"] = n * 48 / min(g)
-            log(f"[bench] sweep S={s} K={k}: {sweep[f's{s}_k{k}']:.3e} SU/s")
-            ch.close()
-        best = max(sweep, key=sweep.get)
-        S, K = (int(x[1:]) for x in best.split("_"))
+    if args.sites and args.waves and args.kdepth:
+        S, W, K = args.sites, args.waves, args.kdepth
     else:
-        S, K = args.sites or 8, args.kdepth or 8
-    log(f"[bench] plan S={S} K={K}")
+        cands = None
+        if args.sweep:
+            cands = [(s, w, k) for s in autotune.SITES for w in autotune.WAVES
+                     for k in autotune.DEPTHS if 64 * s * w > 16 * k]
+        log("[bench] autotuning the cluster shape")
+        (S, W, K), table = autotune.tune(n, q=qd, p=pd, dt=dt, candidates=cands, device=dev,
+                                        use_cache=False)
+        sweep = {f"s{s}_w{w}_k{k}": v for (s, w, k), v in sorted(table.items())}
+    log(f"[bench] plan S={S} W={W} K={K}")
 
-    ch = Chain(qd, pd, dt, sites_per_lane=S, kdepth=K, resident=False, device=dev)
+    ch = Chain(qd, pd, dt, sites_per_lane=S, waves_per_cluster=W, kdepth=K, resident=False,
+               device=dev)
     plan = ch.plan()
     time_jobs(ch, js, args.warmup)
     log(f"[bench] timing {args.steps} jobs of {js} steps")
@@ -189,7 +188,8 @@ def main(argv=None):
     value = su / wall
     launches = fused_launches(plan, js)
     t_launch = statistics.mean(gpu) / launches
-    rl = roofline(n, K, t_launch)
+    rl = roofline(n, js / launches, t_launch)
+    rl["launches_per_job"] = launches
     rl["traffic"] = None
 
     out = {
@@ -207,18 +207,19 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": "quartic chain, N=2^24, periodic, q,p~U[-1,1) seed 0, dt=0.01, "
                                "1000 RK4 steps per job + energy",
-                   "n": n, "job_steps": js, "sites_per_lane": S, "kdepth": K,
-                   "tile": plan["tile"], "halo": plan["halo"]},
+                   "n": n, "job_steps": js, "sites_per_lane": S, "waves_per_cluster": W,
+                   "kdepth": K, "tile": plan["tile"], "halo": plan["halo"],
+                   "overlap_factor": plan["overlap_factor"]},
         "hbm_roofline_pct": 100.0 * value / (HBM_PEAK_GBPS * 1e9 / 32),
         "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99)},
         "roofline": rl,
         "energy_final": e_final,
     }
     if sweep:
-        out["sweep_su_per_s"] = sweep
+        out["autotune_su_per_s"] = sweep
 
     if not args.no_variants:
-        out["variants"] = variants(qd, pd, dt, n, dev)
+        out["variants"] = variants(qd, pd, dt, n, dev, (S, W))
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -227,11 +228,15 @@ def main(argv=None):
     return 0
 
 
-def variants(qd, pd, dt, n, dev):
+def variants(qd, pd, dt, n, dev, sw):
     """Other rows of the hot path, measured briefly at the same N."""
-    from paper_1412_0544_amd import Chain
+    from paper_1412_0544_amd import Chain, autotune
     import workloads
     res = {}
+    # temporal depth k = 1, 2, 4, 8 at the tuned cluster shape
+    res["fused_k_su_per_s"] = {
+        str(k): autotune.time_shape(qd, pd, dt, (sw[0], sw[1], k), steps=48, device=dev)
+        for k in (1, 2, 4, 8)}
     # the standard implementation: one kernel per stage
     ch = Chain(qd, pd, dt, method="naive", device=dev)
     ch.step(2)
@@ -239,12 +244,8 @@ def variants(qd, pd, dt, n, dev):
     res["naive_su_per_s"] = n * 20 / min(g)
     ch.close()
     # FP32 state with compensated update
-    ch = Chain(qd.float(), pd.float(), dt, prec="fp32_kahan", sites_per_lane=16, kdepth=8,
-               resident=False, device=dev)
-    ch.step(16)
-    _, g, _ = time_jobs(ch, 200, 2, with_energy=False)
-    res["fp32_kahan_su_per_s"] = n * 200 / min(g)
-    ch.close()
+    res["fp32_kahan_su_per_s"] = autotune.time_shape(
+        qd.float(), pd.float(), dt, (16, 4, 12), prec="fp32_kahan", steps=96, device=dev)
     # the 1024-site ring resident on chip, 1000 steps per job
     q0, p0 = workloads.chain_ics(1024, 0)
     ch = Chain(q0, p0, dt, device=dev)

@@ -84,16 +84,21 @@ typedef struct chain_rk4_desc {
                                 4, 8 or 16 */
     int32_t kdepth;          /* fused: RK4 steps per pass over memory, 0 =
                                 default, else 1..16 */
+    int32_t waves_per_cluster; /* fused: wavefronts that share one cluster
+                                (edge values through LDS), 0 = default,
+                                else 1, 2, 4 or 8 */
     int32_t flags;           /* enum chain_flags, or 0 */
+    int32_t reserved;        /* must be 0 */
 } chain_rk4_desc;
 
 /* Plan chosen for a handle: what one step call launches. */
 typedef struct chain_rk4_plan {
     int32_t method, sites_per_lane, kdepth, resident; /* resident: 1 if the
                                     whole ring stays on chip for all steps */
-    int64_t tile;                /* output sites per wavefront and pass */
+    int32_t waves_per_cluster, reserved;
+    int64_t tile;                /* output sites per cluster and pass */
     int64_t halo;                /* recomputed sites per side (4 * kdepth) */
-    int64_t waves;               /* wavefronts per pass */
+    int64_t waves;               /* clusters per pass */
     double overlap_factor;       /* sites computed / sites kept per pass,
                                     1 + 2*halo/tile (Sec. 2.3) */
 } chain_rk4_plan;

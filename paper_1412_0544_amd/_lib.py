@@ -28,12 +28,14 @@ class Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("model", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("method", ctypes.c_int32),
                 ("sites_per_lane", ctypes.c_int32), ("kdepth", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("waves_per_cluster", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("sites_per_lane", ctypes.c_int32),
                 ("kdepth", ctypes.c_int32), ("resident", ctypes.c_int32),
+                ("waves_per_cluster", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tile", ctypes.c_int64), ("halo", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("overlap_factor", ctypes.c_double)]
 

@@ -1,0 +1,124 @@
+"""Autotuner for the fused kernel's cluster shape.
+
+The paper picks its cluster size G from a performance study over G
+(Sec. 2.3, Sec. 3.2.1). On the GPU the cluster is 64*S*W sites (S sites per
+lane, W wavefronts) and a pass advances k steps, so the study runs over
+(S, W, k): each candidate is timed on the device with HIP events over a few
+passes of a chain of the requested length, and the fastest is kept. Results
+are cached in a JSON file keyed by device, model, precision and the length
+bucket (the next power of two), so a later process reuses them.
+"""
+from __future__ import annotations
+
+import json
+import os
+import threading
+
+import torch
+
+from .chain import Chain, state_dtype
+
+CACHE_ENV = "CHAIN_RK4_TUNE_CACHE"
+_lock = threading.Lock()
+
+SITES = (4, 8, 16)
+WAVES = (1, 2, 4, 8)
+DEPTHS = (1, 2, 4, 6, 8, 12, 16)
+
+
+def default_candidates(prec: str = "fp64"):
+    """Shapes worth timing: cluster sizes that keep the halo small."""
+    out = []
+    for s in (8, 16):
+        for w in WAVES:
+            for k in (4, 8, 12, 16):
+                if 64 * s * w > 16 * k:
+                    out.append((s, w, k))
+    return out
+
+
+def cache_path() -> str:
+    return os.environ.get(CACHE_ENV) or os.path.join(
+        os.path.expanduser("~"), ".cache", "chainrk4", "tune.json")
+
+
+def bucket(n: int) -> int:
+    b = 1
+    while b < n:
+        b <<= 1
+    return b
+
+
+def key(device, model: str, prec: str, n: int) -> str:
+    name = torch.cuda.get_device_name(device).replace(" ", "_")
+    return f"{name}|{model}|{prec}|{bucket(n)}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(entries: dict) -> None:
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def time_shape(q, p, dt, shape, model="quartic", prec="fp64", steps=48, reps=3, device=None):
+    """Best site-updates/s of one (S, W, k) over `reps` runs of `steps` steps."""
+    s, w, k = shape
+    ch = Chain(q, p, dt, model=model, prec=prec, sites_per_lane=s, waves_per_cluster=w,
+               kdepth=k, resident=False, device=device or q.device)
+    try:
+        ch.step(2 * k)
+        best = 0.0
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(ch.stream)
+            ch.step(steps)
+            b.record(ch.stream)
+            b.synchronize()
+            best = max(best, q.numel() * steps / (a.elapsed_time(b) / 1e3))
+        return best
+    finally:
+        ch.close()
+
+
+def tune(n: int, model: str = "quartic", prec: str = "fp64", dt: float = 0.01,
+         candidates=None, device="cuda", use_cache: bool = True, steps: int = 48,
+         q=None, p=None):
+    """Return (best (S, W, k), {shape: SU/s}) for chains of length n."""
+    device = torch.device(device)
+    k_ = key(device, model, prec, n)
+    with _lock:
+        if use_cache:
+            hit = _load().get(k_)
+            if hit:
+                return tuple(hit["best"]), {tuple(map(int, s.split(","))): v
+                                            for s, v in hit["table"].items()}
+    if q is None or p is None:
+        g = torch.Generator(device="cpu").manual_seed(12345)
+        dtype = state_dtype(prec)
+        q = (torch.rand(n, generator=g, dtype=torch.float64) * 2 - 1).to(device, dtype)
+        p = (torch.rand(n, generator=g, dtype=torch.float64) * 2 - 1).to(device, dtype)
+    table = {}
+    for shape in candidates or default_candidates(prec):
+        table[tuple(shape)] = time_shape(q, p, dt, shape, model, prec, steps=steps, device=device)
+    best = max(table, key=table.get)
+    with _lock:
+        entries = _load()
+        entries[k_] = {"best": list(best),
+                       "table": {",".join(map(str, s)): v for s, v in table.items()}}
+        _store(entries)
+    return best, table

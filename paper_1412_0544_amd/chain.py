@@ -41,7 +41,8 @@ class Chain:
     """
 
     def __init__(self, q0, p0, dt: float, model="quartic", prec="fp64", method="fused",
-                 sites_per_lane: int = 0, kdepth: int = 0, graph: bool = False,
+                 sites_per_lane: int = 0, kdepth: int = 0, waves_per_cluster: int = 0,
+                 graph: bool = False,
                  resident: bool = True, device="cuda", stream: torch.cuda.Stream | None = None):
         self.device = torch.device(device)
         dtype = state_dtype(prec)
@@ -51,7 +52,8 @@ class Chain:
             raise ValueError("q0 and p0 must be 1-D of one length")
         flags = (L.CHAIN_FLAG_GRAPH if graph else 0) | (0 if resident else L.CHAIN_FLAG_NO_RESIDENT)
         self.desc = L.Desc(self.q.numel(), _code(MODELS, model), _code(PRECS, prec), float(dt),
-                           _code(METHODS, method), int(sites_per_lane), int(kdepth), flags)
+                           _code(METHODS, method), int(sites_per_lane), int(kdepth),
+                           int(waves_per_cluster), flags, 0)
         lib = L.lib()
         ws = lib.chain_rk4_workspace_bytes(ctypes.byref(self.desc))
         if ws == 0:

@@ -50,10 +50,12 @@ size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Defaults when the descriptor leaves the tile shape to the library.
 constexpr int kDefaultSitesFp64 = 8;
 constexpr int kDefaultSitesFp32 = 16;
-constexpr int kDefaultDepth = 4;
+constexpr int kDefaultWaves = 4;
+constexpr int kDefaultDepth = 12;
 constexpr int kMaxDepth = 16;
 
 bool valid_sites(int s) { return s == 4 || s == 8 || s == 16; }
+bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
 
 int check_desc(const chain_rk4_desc *d) {
     if (!d) return fail(CHAIN_EINVAL, "descriptor is NULL");
@@ -70,6 +72,10 @@ int check_desc(const chain_rk4_desc *d) {
         return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16 (got %d)", d->sites_per_lane);
     if (d->kdepth < 0 || d->kdepth > kMaxDepth)
         return fail(CHAIN_EINVAL, "kdepth must be in 0..%d (got %d)", kMaxDepth, d->kdepth);
+    if (d->waves_per_cluster != 0 && !valid_waves(d->waves_per_cluster))
+        return fail(CHAIN_EINVAL, "waves_per_cluster must be 0, 1, 2, 4 or 8 (got %d)",
+                    d->waves_per_cluster);
+    if (d->reserved != 0) return fail(CHAIN_EINVAL, "reserved must be 0");
     if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT))
         return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
     return CHAIN_OK;
@@ -120,7 +126,7 @@ Layout layout(const chain_rk4_desc *d) {
 
 struct Plan {
     bool resident = false;
-    int sites = 0, depth = 0;
+    int sites = 0, depth = 0, waves_per_cluster = 0;
     int64_t tile = 0, halo = 0, waves = 0;
 };
 
@@ -128,17 +134,19 @@ Plan make_plan(const chain_rk4_desc *d) {
     Plan P;
     if (d->method != CHAIN_FUSED) return P;
     if (!(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites && d->sites_per_lane == 0 &&
-        d->kdepth == 0) {
+        d->kdepth == 0 && d->waves_per_cluster == 0) {
         P.resident = true;
         return P;
     }
     P.sites = d->sites_per_lane ? d->sites_per_lane
                                 : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
+    P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster : kDefaultWaves;
     P.depth = d->kdepth ? d->kdepth : kDefaultDepth;
-    // the kept part of a cluster must stay positive: 64*S > 8*depth
-    while (64 * P.sites <= 8 * P.depth && P.depth > 1) --P.depth;
+    const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
+    // the kept part of a cluster must stay positive: E > 8*depth
+    while (E <= 8 * P.depth && P.depth > 1) --P.depth;
     P.halo = 4 * static_cast<int64_t>(P.depth);
-    P.tile = 64 * static_cast<int64_t>(P.sites) - 2 * P.halo;
+    P.tile = E - 2 * P.halo;
     P.waves = (d->n + P.tile - 1) / P.tile;
     return P;
 }
@@ -206,7 +214,7 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
     StateRef cur = h->front, nxt = h->back;
     for (int k : ks) {
         FusedPass a{cur, nxt, d.n, h->plan.tile, h->plan.halo, h->plan.waves, d.dt, k};
-        hipError_t e = launch_fused(d.model, d.prec, h->plan.sites, a, s);
+        hipError_t e = launch_fused(d.model, d.prec, h->plan.sites, h->plan.waves_per_cluster, a, s);
         if (e != hipSuccess) return hip_fail(e, "fused launch");
         std::swap(cur, nxt);
     }
@@ -354,6 +362,7 @@ int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out) {
     P.resident = h->plan.resident ? 1 : 0;
     P.sites_per_lane = h->plan.sites;
     P.kdepth = h->plan.depth;
+    P.waves_per_cluster = h->plan.waves_per_cluster;
     P.tile = h->plan.tile;
     P.halo = h->plan.halo;
     P.waves = h->plan.waves;

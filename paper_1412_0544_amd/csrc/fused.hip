@@ -1,16 +1,17 @@
 // fused.hip -- the fused, temporally blocked RK4 kernel and the resident
 // whole-ring kernel.
 //
-// Fused kernel (the GPU form of the granular scheme of Sec. 2.3): each
-// wavefront is one cluster. It holds E = 64*S consecutive sites, S per lane,
-// in registers, of which the middle `tile` sites are kept and `halo` sites on
-// each side are loaded only to be recomputed and discarded. With
-// halo = 4*ksteps the wrong values that enter at the cluster edges (one site
-// per stage, Sec. 2.3) never reach the kept sites, so one pass over memory
-// advances the chain by `ksteps` steps. Neighbour values inside a wavefront
-// move by DPP lane shifts; wavefronts never talk to each other, so there is no
-// LDS and no barrier. Input and output are different buffers (ping-pong):
-// clusters overlap, and updating in place would race.
+// Fused kernel (the GPU form of the granular scheme of Sec. 2.3): a cluster is
+// W wavefronts holding E = 64*S*W consecutive sites, S per lane, in
+// registers. The middle `tile` sites are kept; `halo` sites on each side are
+// loaded only to be recomputed and discarded. With halo = 4*ksteps the wrong
+// values that enter at the cluster edges (one site per stage, Sec. 2.3) never
+// reach the kept sites, so one pass over memory advances the chain by
+// `ksteps` steps. Inside a wavefront neighbour values move by DPP lane
+// shifts; between the wavefronts of a cluster only the two edge coordinates
+// go through LDS, with one barrier per stage. Clusters never talk to each
+// other. Input and output are different buffers (ping-pong): clusters
+// overlap, and updating in place would race.
 //
 // Resident kernel: one workgroup keeps a whole ring of up to 4096 sites on
 // chip (state in registers, stage arguments in LDS) for any number of steps.
@@ -57,30 +58,62 @@ __device__ __forceinline__ void store_contig(R *__restrict__ dst, const R (&src)
     }
 }
 
-// One stage for the S sites of this lane, with the two edge bond terms
-// exchanged across lanes: first the right neighbour's first coordinate comes
-// in, this lane forms its last bond term, and that term goes to the right
-// neighbour lane as its left bond term.
-template <int M, int S, int STAGE, class R>
+// Edge coordinates a wavefront publishes for its neighbours in the cluster,
+// double-buffered by stage parity so one barrier per stage suffices.
+template <class R, int WPB>
+struct EdgeSlots {
+    R first[2][WPB];
+    R last[2][WPB];
+};
+
+// One stage for the S sites of this lane. The right neighbour's first
+// coordinate comes in, this lane forms its last bond term, and that term goes
+// to the right neighbour lane as its left bond term. At a wavefront edge
+// inside the cluster the neighbour coordinate comes from LDS instead, and
+// lane 0 forms its left bond term itself (the same operation on the same
+// values as the left wavefront's lane 63).
+template <int M, int S, int STAGE, int W, int WPB, class R>
 __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S], R (&aq)[S],
-                                           R (&ap)[S], const StepConsts<R> &c) {
+                                           R (&ap)[S], const StepConsts<R> &c,
+                                           EdgeSlots<R, WPB> *slots, int lane, int wib, int wic,
+                                           int parity) {
     const R first = (STAGE == 1) ? q[0] : Q[0];
     const R last = (STAGE == 1) ? q[S - 1] : Q[S - 1];
-    const R right = from_right(first);
+    R right = from_right(first);
+    if constexpr (W > 1) {
+        if (lane == 0) slots->first[parity][wib] = first;
+        if (lane == 63) slots->last[parity][wib] = last;
+        __syncthreads();
+        if (lane == 63 && wic + 1 < W) right = slots->first[parity][wib + 1];
+    }
     const R brS = ModelOps<M, R>::bond(right - last);
-    const R bl0 = from_left(brS);
+    R bl0 = from_left(brS);
+    if constexpr (W > 1) {
+        if (lane == 0 && wic > 0) bl0 = ModelOps<M, R>::bond(first - slots->last[parity][wib - 1]);
+    }
     stage_sites<M, S, STAGE>(Q, P, q, p, aq, ap, bl0, brS, c);
 }
 
-template <int M, class R, bool KAHAN, int S>
-__global__ __launch_bounds__(kFusedThreads) void fused_kernel(FusedPass a) {
-    constexpr int E = 64 * S;
+constexpr int fused_block_threads(int W) { return W == 1 ? kFusedThreads : 64 * W; }
+
+template <int M, class R, bool KAHAN, int S, int W>
+__global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass a) {
+    constexpr int WPB = fused_block_threads(W) / 64;  // wavefronts per block
+    constexpr int E = 64 * S * W;                      // sites per cluster
     const int lane = threadIdx.x & 63;
-    const int64_t wave = static_cast<int64_t>(blockIdx.x) * (kFusedThreads / 64) + (threadIdx.x >> 6);
-    if (wave >= a.waves) return;  // uniform per wavefront
+    const int wib = threadIdx.x >> 6;                  // wavefront in block
+    const int wic = wib % W;                           // wavefront in cluster
+    const int64_t cluster = static_cast<int64_t>(blockIdx.x) * (WPB / W) + wib / W;
+    __shared__ EdgeSlots<R, WPB> slots;
+    if constexpr (W == 1) {
+        if (cluster >= a.waves) return;  // uniform per wavefront; no barriers below
+    }
+    // With W > 1 a block is exactly one cluster and the grid has no extra
+    // blocks, so every wavefront reaches every barrier.
     const int64_t n = a.n;
-    const int64_t e0 = wave * a.tile - a.halo;
-    const int64_t s0 = e0 + static_cast<int64_t>(lane) * S;
+    const int64_t e0 = cluster * a.tile - a.halo;
+    const int lo = (wic * 64 + lane) * S;              // first site in the cluster
+    const int64_t s0 = e0 + lo;
 
     const R *qin = static_cast<const R *>(a.in.q);
     const R *pin = static_cast<const R *>(a.in.p);
@@ -110,10 +143,10 @@ __global__ __launch_bounds__(kFusedThreads) void fused_kernel(FusedPass a) {
     const StepConsts<R> c(a.dt);
     R Q[S], P[S], aq[S], ap[S];
     for (int st = 0; st < a.ksteps; ++st) {
-        lane_stage<M, S, 1>(Q, P, q, p, aq, ap, c);
-        lane_stage<M, S, 2>(Q, P, q, p, aq, ap, c);
-        lane_stage<M, S, 3>(Q, P, q, p, aq, ap, c);
-        lane_stage<M, S, 4>(Q, P, q, p, aq, ap, c);
+        lane_stage<M, S, 1, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 0);
+        lane_stage<M, S, 2, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 1);
+        lane_stage<M, S, 3, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 0);
+        lane_stage<M, S, 4, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 1);
         if constexpr (KAHAN)
             final_update_kahan<S>(q, p, cq, cp, aq, ap, c);
         else
@@ -122,7 +155,6 @@ __global__ __launch_bounds__(kFusedThreads) void fused_kernel(FusedPass a) {
 
     R *qout = static_cast<R *>(a.out.q);
     R *pout = static_cast<R *>(a.out.p);
-    const int lo = lane * S;
     const int64_t keep_end = E - a.halo;
     const bool full = lo >= a.halo && lo + S <= keep_end && s0 + S <= n;
     if (full) {
@@ -239,18 +271,35 @@ __global__ __launch_bounds__(kResidentThreads) void resident_kernel(ResidentRun 
     }
 }
 
-template <int M, class R, bool KAHAN>
-hipError_t fused_dispatch_s(int s, const FusedPass &a, hipStream_t st) {
-    const int64_t blocks64 = (a.waves + (kFusedThreads / 64) - 1) / (kFusedThreads / 64);
+template <int M, class R, bool KAHAN, int S, int W>
+hipError_t fused_launch_one(const FusedPass &a, hipStream_t st) {
+    constexpr int T = fused_block_threads(W);
+    constexpr int clusters_per_block = T / 64 / W;
+    const int64_t blocks64 = (a.waves + clusters_per_block - 1) / clusters_per_block;
     if (blocks64 <= 0 || blocks64 > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid(static_cast<unsigned>(blocks64)), block(kFusedThreads);
-    switch (s) {
-    case 4: fused_kernel<M, R, KAHAN, 4><<<grid, block, 0, st>>>(a); break;
-    case 8: fused_kernel<M, R, KAHAN, 8><<<grid, block, 0, st>>>(a); break;
-    case 16: fused_kernel<M, R, KAHAN, 16><<<grid, block, 0, st>>>(a); break;
+    fused_kernel<M, R, KAHAN, S, W><<<dim3(static_cast<unsigned>(blocks64)), dim3(T), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int M, class R, bool KAHAN, int S>
+hipError_t fused_dispatch_w(int w, const FusedPass &a, hipStream_t st) {
+    switch (w) {
+    case 1: return fused_launch_one<M, R, KAHAN, S, 1>(a, st);
+    case 2: return fused_launch_one<M, R, KAHAN, S, 2>(a, st);
+    case 4: return fused_launch_one<M, R, KAHAN, S, 4>(a, st);
+    case 8: return fused_launch_one<M, R, KAHAN, S, 8>(a, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t fused_dispatch_s(int s, int w, const FusedPass &a, hipStream_t st) {
+    switch (s) {
+    case 4: return fused_dispatch_w<M, R, KAHAN, 4>(w, a, st);
+    case 8: return fused_dispatch_w<M, R, KAHAN, 8>(w, a, st);
+    case 16: return fused_dispatch_w<M, R, KAHAN, 16>(w, a, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int M, class R, bool KAHAN>
@@ -269,13 +318,13 @@ hipError_t resident_dispatch(const ResidentRun &a, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_fused(int model, int prec, int s, const FusedPass &a, hipStream_t st) {
+hipError_t launch_fused(int model, int prec, int s, int w, const FusedPass &a, hipStream_t st) {
     if (model == kQuartic) {
-        return prec == 0 ? fused_dispatch_s<kQuartic, double, false>(s, a, st)
-                         : fused_dispatch_s<kQuartic, float, true>(s, a, st);
+        return prec == 0 ? fused_dispatch_s<kQuartic, double, false>(s, w, a, st)
+                         : fused_dispatch_s<kQuartic, float, true>(s, w, a, st);
     }
-    return prec == 0 ? fused_dispatch_s<kHarmonic, double, false>(s, a, st)
-                     : fused_dispatch_s<kHarmonic, float, true>(s, a, st);
+    return prec == 0 ? fused_dispatch_s<kHarmonic, double, false>(s, w, a, st)
+                     : fused_dispatch_s<kHarmonic, float, true>(s, w, a, st);
 }
 
 size_t resident_lds_bytes(int prec, int64_t n) {

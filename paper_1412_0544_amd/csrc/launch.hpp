@@ -15,8 +15,9 @@ struct StateRef {
     float *cq, *cp;
 };
 
-// One pass of the fused kernel: every wavefront owns `tile` output sites and
-// recomputes `halo` sites on each side, advancing `ksteps` <= halo/4 steps.
+// One pass of the fused kernel: every cluster (W wavefronts) owns `tile`
+// output sites and recomputes `halo` sites on each side, advancing
+// `ksteps` <= halo/4 steps. `waves` counts clusters.
 struct FusedPass {
     StateRef in, out;
     int64_t n;
@@ -43,10 +44,10 @@ struct NaiveBufs {
 
 constexpr int kResidentThreads = 256;
 constexpr int kResidentMaxSites = 4096;   // 16 sites per thread
-constexpr int kFusedThreads = 256;        // 4 independent wavefronts
+constexpr int kFusedThreads = 256;        // 4 one-wavefront clusters per block
 
-hipError_t launch_fused(int model, int prec, int sites_per_lane, const FusedPass &a,
-                        hipStream_t s);
+hipError_t launch_fused(int model, int prec, int sites_per_lane, int waves_per_cluster,
+                        const FusedPass &a, hipStream_t s);
 hipError_t launch_resident(int model, int prec, const ResidentRun &a, hipStream_t s);
 size_t resident_lds_bytes(int prec, int64_t n);
 hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,

@@ -27,7 +27,8 @@ def test_library_exports_every_declared_function():
 
 
 def desc(**kw):
-    d = dict(n=1000, model=0, prec=0, dt=0.01, method=0, sites_per_lane=0, kdepth=0, flags=0)
+    d = dict(n=1000, model=0, prec=0, dt=0.01, method=0, sites_per_lane=0, kdepth=0,
+             waves_per_cluster=0, flags=0, reserved=0)
     d.update(kw)
     return L.Desc(**d)
 
@@ -41,7 +42,8 @@ def test_workspace_bytes():
     assert f(desc(n=1 << 20, method=1)) >= 10 * 8 * (1 << 20)
     for bad in (desc(n=0), desc(model=7), desc(prec=3), desc(dt=float("nan")),
                 desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
-                desc(kdepth=17), desc(kdepth=-1), desc(flags=64)):
+                desc(kdepth=17), desc(kdepth=-1), desc(flags=64), desc(waves_per_cluster=3),
+                desc(waves_per_cluster=16), desc(reserved=1)):
         assert f(bad) == 0
     assert lib.chain_rk4_workspace_bytes(None) == 0
 

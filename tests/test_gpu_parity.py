@@ -42,12 +42,14 @@ def maxerr(a, b):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257, 1000, 5003, 20011])
-@pytest.mark.parametrize("sites,depth", [(4, 1), (8, 3), (16, 8), (8, 16), (4, 4)])
-def test_fused_tiled_matches_oracle(n, sites, depth):
+@pytest.mark.parametrize("sites,waves,depth", [(4, 1, 1), (8, 2, 3), (16, 1, 8), (8, 4, 16),
+                                               (4, 8, 4), (8, 4, 12), (16, 8, 12)])
+def test_fused_tiled_matches_oracle(n, sites, waves, depth):
     q0, p0 = workloads.chain_ics(n, 1)
-    q, p, e, plan = gpu_run(q0, p0, 0.01, 100, sites_per_lane=sites, kdepth=depth,
-                            resident=False)
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 100, sites_per_lane=sites, waves_per_cluster=waves,
+                            kdepth=depth, resident=False)
     assert plan["resident"] == 0 and plan["sites_per_lane"] == sites
+    assert plan["waves_per_cluster"] == waves
     qo, po = oracle_run("quartic", n, 1, 0.01, 100)
     assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
     eo = oracle.energy(oracle.QUARTIC, qo, po)
@@ -82,12 +84,15 @@ def test_resident_naive_and_tiled_identical_bits(n, model):
 def test_tile_shapes_and_depths_identical_bits():
     n = 30011
     q0, p0 = workloads.chain_ics(n, 4)
-    ref = gpu_run(q0, p0, 0.01, 24, sites_per_lane=4, kdepth=1, resident=False)
+    ref = gpu_run(q0, p0, 0.01, 24, sites_per_lane=4, waves_per_cluster=1, kdepth=1,
+                  resident=False)
     for s in (4, 8, 16):
-        for k in (2, 3, 6, 8, 12, 16):
-            got = gpu_run(q0, p0, 0.01, 24, sites_per_lane=s, kdepth=k, resident=False)
-            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (s, k)
-            assert got[2] == ref[2]
+        for w in (1, 2, 4, 8):
+            for k in (2, 3, 8, 12, 16):
+                got = gpu_run(q0, p0, 0.01, 24, sites_per_lane=s, waves_per_cluster=w, kdepth=k,
+                              resident=False)
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (s, w, k)
+                assert got[2] == ref[2]
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -131,7 +136,8 @@ def test_time_reversal_bitwise():
     n = 2050
     q0, p0 = workloads.chain_ics(n, 7)
     a = gpu_run(q0, -p0, 0.01, 40, sites_per_lane=8, kdepth=4, resident=False)
-    b = gpu_run(q0, p0, -0.01, 40, sites_per_lane=16, kdepth=8, resident=False)
+    b = gpu_run(q0, p0, -0.01, 40, sites_per_lane=16, waves_per_cluster=4, kdepth=8,
+                resident=False)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], -b[1])
 
 
@@ -187,6 +193,25 @@ def test_full_size_sampled_sites(full_ics):
     assert np.all(np.isfinite(q)) and np.all(np.isfinite(p))
 
 
+def test_full_size_every_tuned_shape_identical_bits(full_ics):
+    """Every cluster shape the autotuner may pick for the benchmark gives the
+    same bits at N = 2^24 as the default plan (checked against the oracle
+    above)."""
+    from paper_1412_0544_amd import autotune
+    q0, p0 = full_ics
+    qd = torch.from_numpy(q0).cuda()
+    pd = torch.from_numpy(p0).cuda()
+    ref = Chain(qd, pd, 0.01)
+    ref.step(30)
+    for s, w, k in autotune.default_candidates():
+        ch = Chain(qd, pd, 0.01, sites_per_lane=s, waves_per_cluster=w, kdepth=k, resident=False)
+        ch.step(30)
+        torch.cuda.synchronize()
+        assert torch.equal(ch.q, ref.q) and torch.equal(ch.p, ref.p), (s, w, k)
+        ch.close()
+    ref.close()
+
+
 def test_full_size_pi_mode_closed_form():
     """q_i = (-1)^i A stays an exact alternation (any halo or tile-edge error
     breaks it) and follows A cn(Omega t | m) with Omega^2 = 1 + 17 A^2."""
@@ -233,7 +258,8 @@ def test_fp32_paths_identical_bits():
     q0, p0 = workloads.chain_ics(n, 11, dtype=np.float32)
     outs = []
     for kw in (dict(sites_per_lane=16, kdepth=4, resident=False),
-               dict(sites_per_lane=8, kdepth=7, resident=False),
+               dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1, resident=False),
+               dict(sites_per_lane=4, kdepth=12, waves_per_cluster=8, resident=False),
                dict(method="naive"), dict()):
         ch = Chain(q0, p0, 0.01, prec="fp32_kahan", **kw)
         ch.step(30)
