@@ -96,73 +96,57 @@ __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&
 
 constexpr int fused_block_threads(int W) { return W == 1 ? kFusedThreads : 64 * W; }
 
-template <int M, class R, bool KAHAN, int S, int W>
-__global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass a) {
-    constexpr int WPB = fused_block_threads(W) / 64;  // wavefronts per block
-    constexpr int E = 64 * S * W;                      // sites per cluster
-    const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;                  // wavefront in block
-    const int wic = wib % W;                           // wavefront in cluster
-    const int64_t cluster = static_cast<int64_t>(blockIdx.x) * (WPB / W) + wib / W;
-    __shared__ EdgeSlots<R, WPB> slots;
-    if constexpr (W == 1) {
-        if (cluster >= a.waves) return;  // uniform per wavefront; no barriers below
-    }
-    // With W > 1 a block is exactly one cluster and the grid has no extra
-    // blocks, so every wavefront reaches every barrier.
-    const int64_t n = a.n;
-    const int64_t e0 = cluster * a.tile - a.halo;
-    const int lo = (wic * 64 + lane) * S;              // first site in the cluster
-    const int64_t s0 = e0 + lo;
+// Registers of one cluster's state (this lane's S sites).
+template <class R, bool KAHAN, int S>
+struct LaneState {
+    R q[S], p[S];
+    float cq[KAHAN ? S : 1], cp[KAHAN ? S : 1];
+};
 
+// Load this lane's S sites of the cluster starting at unwrapped site e0.
+template <class R, bool KAHAN, int S, int E>
+__device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const FusedPass &a, int64_t e0,
+                                          int lo) {
+    const int64_t n = a.n;
+    const int64_t s0 = e0 + lo;
     const R *qin = static_cast<const R *>(a.in.q);
     const R *pin = static_cast<const R *>(a.in.p);
-    R q[S], p[S];
-    float cq[S], cp[S];
-    const bool inside = e0 >= 0 && e0 + E <= n;
-    if (inside) {
-        load_contig<R, S>(q, qin + s0);
-        load_contig<R, S>(p, pin + s0);
+    if (e0 >= 0 && e0 + E <= n) {
+        load_contig<R, S>(st.q, qin + s0);
+        load_contig<R, S>(st.p, pin + s0);
         if constexpr (KAHAN) {
-            load_contig<float, S>(cq, a.in.cq + s0);
-            load_contig<float, S>(cp, a.in.cp + s0);
+            load_contig<float, S>(st.cq, a.in.cq + s0);
+            load_contig<float, S>(st.cp, a.in.cp + s0);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const int64_t i = wrap_index(s0 + j, n);
-            q[j] = qin[i];
-            p[j] = pin[i];
+            st.q[j] = qin[i];
+            st.p[j] = pin[i];
             if constexpr (KAHAN) {
-                cq[j] = a.in.cq[i];
-                cp[j] = a.in.cp[i];
+                st.cq[j] = a.in.cq[i];
+                st.cp[j] = a.in.cp[i];
             }
         }
     }
+}
 
-    const StepConsts<R> c(a.dt);
-    R Q[S], P[S], aq[S], ap[S];
-    for (int st = 0; st < a.ksteps; ++st) {
-        lane_stage<M, S, 1, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 0);
-        lane_stage<M, S, 2, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 1);
-        lane_stage<M, S, 3, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 0);
-        lane_stage<M, S, 4, W, WPB>(Q, P, q, p, aq, ap, c, &slots, lane, wib, wic, 1);
-        if constexpr (KAHAN)
-            final_update_kahan<S>(q, p, cq, cp, aq, ap, c);
-        else
-            final_update<S>(q, p, aq, ap, c);
-    }
-
+// Store the kept sites of this lane.
+template <class R, bool KAHAN, int S, int E>
+__device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, const FusedPass &a,
+                                           int64_t e0, int lo) {
+    const int64_t n = a.n;
+    const int64_t s0 = e0 + lo;
     R *qout = static_cast<R *>(a.out.q);
     R *pout = static_cast<R *>(a.out.p);
     const int64_t keep_end = E - a.halo;
-    const bool full = lo >= a.halo && lo + S <= keep_end && s0 + S <= n;
-    if (full) {
-        store_contig<R, S>(qout + s0, q);
-        store_contig<R, S>(pout + s0, p);
+    if (lo >= a.halo && lo + S <= keep_end && s0 + S <= n) {
+        store_contig<R, S>(qout + s0, st.q);
+        store_contig<R, S>(pout + s0, st.p);
         if constexpr (KAHAN) {
-            store_contig<float, S>(a.out.cq + s0, cq);
-            store_contig<float, S>(a.out.cp + s0, cp);
+            store_contig<float, S>(a.out.cq + s0, st.cq);
+            store_contig<float, S>(a.out.cp + s0, st.cp);
         }
     } else {
 #pragma unroll
@@ -170,14 +154,70 @@ __global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass
             const int local = lo + j;
             const int64_t g = s0 + j;
             if (local >= a.halo && local < keep_end && g < n) {
-                qout[g] = q[j];
-                pout[g] = p[j];
+                qout[g] = st.q[j];
+                pout[g] = st.p[j];
                 if constexpr (KAHAN) {
-                    a.out.cq[g] = cq[j];
-                    a.out.cp[g] = cp[j];
+                    a.out.cq[g] = st.cq[j];
+                    a.out.cp[g] = st.cp[j];
                 }
             }
         }
+    }
+}
+
+// Whether a lane prefetches the next cluster's sites into registers: only
+// where the extra 4*S registers still leave room for three wavefronts per
+// SIMD (state, stage arguments and accumulators take 6 values per site).
+template <class R, int S>
+constexpr bool fused_prefetch() {
+    return S * 6 * static_cast<int>(sizeof(R) / 4) + S * 4 <= 128;
+}
+
+// The grid is sized to what the device holds at once; each cluster slot
+// walks over clusters with a stride of the whole grid. Where registers allow,
+// it loads the next cluster's sites while it computes the current one, so
+// memory traffic and arithmetic overlap instead of alternating.
+template <int M, class R, bool KAHAN, int S, int W>
+__global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(
+    FusedPass a) {
+    constexpr int WPB = fused_block_threads(W) / 64;  // wavefronts per block
+    constexpr int CPB = WPB / W;                       // clusters per block
+    constexpr int E = 64 * S * W;                      // sites per cluster
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;                  // wavefront in block
+    const int wic = wib % W;                           // wavefront in cluster
+    const int lo = (wic * 64 + lane) * S;              // first site in the cluster
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * CPB;
+    int64_t cluster = static_cast<int64_t>(blockIdx.x) * CPB + wib / W;
+    __shared__ EdgeSlots<R, WPB> slots;
+    // With W > 1 a block is one cluster slot, so its wavefronts run the same
+    // number of iterations and all reach every barrier.
+
+    constexpr bool PF = fused_prefetch<R, S>();
+    LaneState<R, KAHAN, S> cur, nxt;
+    if (PF && cluster < a.waves) load_lane<R, KAHAN, S, E>(cur, a, cluster * a.tile - a.halo, lo);
+    const StepConsts<R> c(a.dt);
+    for (; cluster < a.waves; cluster += stride) {
+        const int64_t e0 = cluster * a.tile - a.halo;
+        if constexpr (PF) {
+            if (cluster + stride < a.waves)
+                load_lane<R, KAHAN, S, E>(nxt, a, (cluster + stride) * a.tile - a.halo, lo);
+        } else {
+            load_lane<R, KAHAN, S, E>(cur, a, e0, lo);
+        }
+        R Q[S], P[S], aq[S], ap[S];
+        for (int st = 0; st < a.ksteps; ++st) {
+            lane_stage<M, S, 1, W, WPB>(Q, P, cur.q, cur.p, aq, ap, c, &slots, lane, wib, wic, 0);
+            lane_stage<M, S, 2, W, WPB>(Q, P, cur.q, cur.p, aq, ap, c, &slots, lane, wib, wic, 1);
+            lane_stage<M, S, 3, W, WPB>(Q, P, cur.q, cur.p, aq, ap, c, &slots, lane, wib, wic, 0);
+            lane_stage<M, S, 4, W, WPB>(Q, P, cur.q, cur.p, aq, ap, c, &slots, lane, wib, wic, 1);
+            if constexpr (KAHAN)
+                final_update_kahan<S>(cur.q, cur.p, cur.cq, cur.cp, aq, ap, c);
+            else
+                final_update<S>(cur.q, cur.p, aq, ap, c);
+        }
+        store_lane<R, KAHAN, S, E>(cur, a, e0, lo);
+        if constexpr (PF) cur = nxt;
     }
 }
 
@@ -242,8 +282,8 @@ __global__ __launch_bounds__(kResidentThreads) void resident_kernel(ResidentRun 
                             kahan_add(q[j], cq[j], c.h6 * aq[j]);
                             kahan_add(p[j], cp[j], c.h6 * ap[j]);
                         } else {
-                            q[j] = __builtin_fma(c.h6, aq[j], q[j]);
-                            p[j] = __builtin_fma(c.h6, ap[j], p[j]);
+                            q[j] = fma_r(c.h6, aq[j], q[j]);
+                            p[j] = fma_r(c.h6, ap[j], p[j]);
                         }
                         Qn = q[j];  // the next step's first argument
                     }
@@ -271,12 +311,32 @@ __global__ __launch_bounds__(kResidentThreads) void resident_kernel(ResidentRun 
     }
 }
 
+// Blocks the device holds at once for one kernel instance (per device).
+template <class K>
+int resident_blocks(K kernel, int threads) {
+    static int cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = per_cu * cus > 0 ? per_cu * cus : 1;
+    }
+    return cached[dev];
+}
+
 template <int M, class R, bool KAHAN, int S, int W>
 hipError_t fused_launch_one(const FusedPass &a, hipStream_t st) {
     constexpr int T = fused_block_threads(W);
     constexpr int clusters_per_block = T / 64 / W;
-    const int64_t blocks64 = (a.waves + clusters_per_block - 1) / clusters_per_block;
-    if (blocks64 <= 0 || blocks64 > 0x7fffffff) return hipErrorInvalidValue;
+    int64_t blocks64 = (a.waves + clusters_per_block - 1) / clusters_per_block;
+    const int cap = resident_blocks(fused_kernel<M, R, KAHAN, S, W>, T);
+    if (cap <= 0) return hipErrorInvalidValue;
+    if (blocks64 > cap) blocks64 = cap;
+    if (blocks64 <= 0) return hipErrorInvalidValue;
     fused_kernel<M, R, KAHAN, S, W><<<dim3(static_cast<unsigned>(blocks64)), dim3(T), 0, st>>>(a);
     return hipGetLastError();
 }

@@ -42,15 +42,15 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
         const R a = STAGE == 3 ? c.h : c.hh;
         kq[i] = Pj;
         kp[i] = F;
-        nq[i] = __builtin_fma(a, Pj, qj);
-        np[i] = __builtin_fma(a, F, pj);
+        nq[i] = fma_r(a, Pj, qj);
+        np[i] = fma_r(a, F, pj);
     } else {
         R accq = static_cast<const R *>(b.k1q)[i];
         R accp = static_cast<const R *>(b.k1p)[i];
-        accq = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k2q)[i], accq);
-        accp = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k2p)[i], accp);
-        accq = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k3q)[i], accq);
-        accp = __builtin_fma(static_cast<R>(2), static_cast<const R *>(b.k3p)[i], accp);
+        accq = fma_r(static_cast<R>(2), static_cast<const R *>(b.k2q)[i], accq);
+        accp = fma_r(static_cast<R>(2), static_cast<const R *>(b.k2p)[i], accp);
+        accq = fma_r(static_cast<R>(2), static_cast<const R *>(b.k3q)[i], accq);
+        accp = fma_r(static_cast<R>(2), static_cast<const R *>(b.k3p)[i], accp);
         accq = accq + Pj;
         accp = accp + F;
         R *wq = static_cast<R *>(y.q);
@@ -65,8 +65,8 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
             y.cq[i] = cq;
             y.cp[i] = cp;
         } else {
-            wq[i] = __builtin_fma(c.h6, accq, qj);
-            wp[i] = __builtin_fma(c.h6, accp, pj);
+            wq[i] = fma_r(c.h6, accq, qj);
+            wp[i] = fma_r(c.h6, accp, pj);
         }
     }
 }

@@ -24,13 +24,17 @@ namespace chainrk4 {
 
 enum Model : int { kQuartic = 0, kHarmonic = 1 };
 
+// Fused multiply-add in the working precision (one rounding).
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <int M, class R>
 struct ModelOps;
 
 template <class R>
 struct ModelOps<kQuartic, R> {
     __device__ __forceinline__ static R bond(R d) { return (d * d) * d; }
-    __device__ __forceinline__ static R onsite(R q) { return __builtin_fma(q * q, q, q); }
+    __device__ __forceinline__ static R onsite(R q) { return fma_r(q * q, q, q); }
     // energy density of the site and its right bond, in FP64
     __device__ __forceinline__ static double energy(double q, double p, double d) {
         double q2 = q * q, d2 = d * d;
@@ -139,18 +143,18 @@ __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (
         if (STAGE == 1) {
             aq[j] = Pj;
             ap[j] = F;
-            Q[j] = __builtin_fma(c.hh, Pj, q[j]);
-            P[j] = __builtin_fma(c.hh, F, p[j]);
+            Q[j] = fma_r(c.hh, Pj, q[j]);
+            P[j] = fma_r(c.hh, F, p[j]);
         } else if (STAGE == 2) {
-            aq[j] = __builtin_fma(static_cast<R>(2), Pj, aq[j]);
-            ap[j] = __builtin_fma(static_cast<R>(2), F, ap[j]);
-            Q[j] = __builtin_fma(c.hh, Pj, q[j]);
-            P[j] = __builtin_fma(c.hh, F, p[j]);
+            aq[j] = fma_r(static_cast<R>(2), Pj, aq[j]);
+            ap[j] = fma_r(static_cast<R>(2), F, ap[j]);
+            Q[j] = fma_r(c.hh, Pj, q[j]);
+            P[j] = fma_r(c.hh, F, p[j]);
         } else if (STAGE == 3) {
-            aq[j] = __builtin_fma(static_cast<R>(2), Pj, aq[j]);
-            ap[j] = __builtin_fma(static_cast<R>(2), F, ap[j]);
-            Q[j] = __builtin_fma(c.h, Pj, q[j]);
-            P[j] = __builtin_fma(c.h, F, p[j]);
+            aq[j] = fma_r(static_cast<R>(2), Pj, aq[j]);
+            ap[j] = fma_r(static_cast<R>(2), F, ap[j]);
+            Q[j] = fma_r(c.h, Pj, q[j]);
+            P[j] = fma_r(c.h, F, p[j]);
         } else {
             aq[j] = aq[j] + Pj;
             ap[j] = ap[j] + F;
@@ -164,8 +168,8 @@ __device__ __forceinline__ void final_update(double (&q)[S], double (&p)[S], con
                                              const double (&ap)[S], const StepConsts<double> &c) {
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        q[j] = __builtin_fma(c.h6, aq[j], q[j]);
-        p[j] = __builtin_fma(c.h6, ap[j], p[j]);
+        q[j] = fma_r(c.h6, aq[j], q[j]);
+        p[j] = fma_r(c.h6, ap[j], p[j]);
     }
 }
 
@@ -190,15 +194,15 @@ __device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R 
     const R F = site_force<M, R>(bl, br, Qj);
     if (STAGE == 1) {
         aq = Pj; ap = F;
-        Qn = __builtin_fma(c.hh, Pj, qj); Pn = __builtin_fma(c.hh, F, pj);
+        Qn = fma_r(c.hh, Pj, qj); Pn = fma_r(c.hh, F, pj);
     } else if (STAGE == 2) {
-        aq = __builtin_fma(static_cast<R>(2), Pj, aq);
-        ap = __builtin_fma(static_cast<R>(2), F, ap);
-        Qn = __builtin_fma(c.hh, Pj, qj); Pn = __builtin_fma(c.hh, F, pj);
+        aq = fma_r(static_cast<R>(2), Pj, aq);
+        ap = fma_r(static_cast<R>(2), F, ap);
+        Qn = fma_r(c.hh, Pj, qj); Pn = fma_r(c.hh, F, pj);
     } else if (STAGE == 3) {
-        aq = __builtin_fma(static_cast<R>(2), Pj, aq);
-        ap = __builtin_fma(static_cast<R>(2), F, ap);
-        Qn = __builtin_fma(c.h, Pj, qj); Pn = __builtin_fma(c.h, F, pj);
+        aq = fma_r(static_cast<R>(2), Pj, aq);
+        ap = fma_r(static_cast<R>(2), F, ap);
+        Qn = fma_r(c.h, Pj, qj); Pn = fma_r(c.h, F, pj);
     } else {
         aq = aq + Pj; ap = ap + F;
     }
