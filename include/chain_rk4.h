@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 typedef struct chain_rk4 chain_rk4;
+typedef struct chain_rk4_batch chain_rk4_batch;
 
 enum chain_model {
     CHAIN_QUARTIC = 0,   /* quartic on-site and bond potentials (formula above) */
@@ -71,7 +72,8 @@ typedef enum chain_status {
     CHAIN_ENOMEM = -2,      /* workspace too small */
     CHAIN_EHIP = -3,        /* a HIP runtime call failed */
     CHAIN_ENONFINITE = -4,  /* an energy came out NaN or infinite */
-    CHAIN_EDEVICE = -5      /* the current device is not a gfx950 GPU */
+    CHAIN_EDEVICE = -5,     /* the current device is not a gfx950 GPU */
+    CHAIN_ETIMEOUT = -6     /* a batched launch hit its bounded wait */
 } chain_status;
 
 typedef struct chain_rk4_desc {
@@ -162,6 +164,74 @@ const char *chain_rk4_strerror(int status);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *chain_rk4_last_error(void);
+
+/*
+ * Batches: many independent chains advanced by ONE persistent launch.
+ *
+ * The launch holds as many workgroups as the device keeps resident. They
+ * claim work items in a fixed order from a device counter: first one item
+ * per short ring (n <= 1024), which stays on chip for all of its steps, then,
+ * pass by pass, one item per (chain, cluster), each the same cluster pass as
+ * the fused method (a cluster of 64*sites_per_lane*4 sites, 4*kdepth of them
+ * recomputed per side, Sec. 2.3). A cluster's pass e starts once its own
+ * cluster and its two neighbours have finished pass e-1 (per-cluster progress
+ * flags), so passes of different clusters and chains overlap. Every chain
+ * gives the same bits as when stepped alone (any handle settings, any grid).
+ *
+ * All handles of a batch share one model and one precision, use
+ * CHAIN_FUSED, appear once, and must stay valid while the batch exists; each
+ * chain keeps its own dt. Calls that overlap on one batch's workspace race.
+ */
+typedef struct chain_rk4_batch_desc {
+    int64_t max_steps;       /* largest per-chain step count of one step call */
+    int32_t sites_per_lane;  /* 0 = default (8), else 4, 8 or 16 */
+    int32_t kdepth;          /* steps per pass, 0 = default (12), else 2..16 */
+    int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
+                                once; any value >= 1 gives the same results */
+    int32_t flags;           /* must be 0 */
+    int32_t spin_limit;      /* polls before a wait for a neighbour gives up,
+                                0 = default (about 4 s); small values force
+                                CHAIN_ETIMEOUT for failure-path tests */
+    int32_t reserved;        /* must be 0 */
+} chain_rk4_batch_desc;
+
+typedef struct chain_rk4_batch_plan {
+    int32_t sites_per_lane, kdepth, waves_per_cluster, grid_blocks;
+    int64_t halo;            /* recomputed sites per cluster side */
+    int64_t tile_max;        /* most sites a cluster keeps per pass */
+    int64_t total_clusters;  /* clusters over all tiled chains */
+    int64_t resident_chains; /* chains kept on chip for a whole launch */
+} chain_rk4_batch_plan;
+
+/* Device workspace bytes (256-byte aligned) of a batch over hs[0..count):
+ * per-cluster progress flags, the work counter, the item tables. 0 if the
+ * arguments are invalid. */
+size_t chain_rk4_batch_workspace_bytes(chain_rk4 *const *hs, int count,
+                                       const chain_rk4_batch_desc *d);
+
+/* Create a batch (host object plus a pinned host staging buffer for the
+ * tables). `stream` carries every launch of the batch. */
+int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batch_desc *d,
+                           void *workspace, size_t ws_bytes, void *stream,
+                           chain_rk4_batch **out);
+
+/* Advance chain j by nsteps[j] (0..max_steps) steps in one persistent launch
+ * (asynchronous; nsteps is read before the call returns). */
+int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps);
+
+/* Synchronise the batch's stream; CHAIN_ETIMEOUT if a wait for a neighbour
+ * expired (the result is then invalid; the kernel still terminated). */
+int chain_rk4_batch_check(chain_rk4_batch *b);
+
+/* Energies of every chain into e_out[count] (host), as chain_rk4_energy. */
+int chain_rk4_batch_energy(chain_rk4_batch *b, double *e_out);
+
+/* Report the shape the batch uses. */
+int chain_rk4_batch_get_plan(const chain_rk4_batch *b, chain_rk4_batch_plan *out);
+
+/* Release a batch (host memory only; waits for its last table upload).
+ * NULL is a no-op. */
+int chain_rk4_batch_destroy(chain_rk4_batch *b);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ CHAIN_ENOMEM = -2
 CHAIN_EHIP = -3
 CHAIN_ENONFINITE = -4
 CHAIN_EDEVICE = -5
+CHAIN_ETIMEOUT = -6
 
 
 class Desc(ctypes.Structure):
@@ -38,6 +39,20 @@ class Plan(ctypes.Structure):
                 ("waves_per_cluster", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tile", ctypes.c_int64), ("halo", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("overlap_factor", ctypes.c_double)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int64), ("sites_per_lane", ctypes.c_int32),
+                ("kdepth", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("sites_per_lane", ctypes.c_int32), ("kdepth", ctypes.c_int32),
+                ("waves_per_cluster", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("halo", ctypes.c_int64), ("tile_max", ctypes.c_int64),
+                ("total_clusters", ctypes.c_int64), ("resident_chains", ctypes.c_int64)]
 
 
 class ChainError(RuntimeError):
@@ -65,6 +80,16 @@ def _declare(lib):
         "chain_rk4_get_carries": (ctypes.c_int, [H, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
         "chain_rk4_destroy": (ctypes.c_int, [H]),
         "chain_rk4_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "chain_rk4_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(H), ctypes.c_int,
+                                                              ctypes.POINTER(BatchDesc)]),
+        "chain_rk4_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int,
+                                                  ctypes.POINTER(BatchDesc), VP, ctypes.c_size_t,
+                                                  VP, ctypes.POINTER(VP)]),
+        "chain_rk4_batch_step": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64)]),
+        "chain_rk4_batch_check": (ctypes.c_int, [VP]),
+        "chain_rk4_batch_energy": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
+        "chain_rk4_batch_get_plan": (ctypes.c_int, [VP, ctypes.POINTER(BatchPlan)]),
+        "chain_rk4_batch_destroy": (ctypes.c_int, [VP]),
         "chain_rk4_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -15,15 +15,15 @@
 #include <string>
 #include <vector>
 
+#include "handle.hpp"
 #include "launch.hpp"
 
 using namespace chainrk4;
 
-namespace {
+namespace chainrk4 {
 
 thread_local std::string g_last_error;
 
-int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int status, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -38,11 +38,22 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(CHAIN_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr)                                        \
-    do {                                                     \
-        hipError_t e_ = (expr);                              \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
-    } while (0)
+size_t elem_bytes(int prec) { return prec == CHAIN_FP64 ? sizeof(double) : sizeof(float); }
+
+bool is_gfx950(int dev) {
+    static int cached[64];  // 0 unknown, 1 yes, 2 no
+    if (dev < 0 || dev >= 64) return false;
+    if (cached[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+        cached[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    }
+    return cached[dev] == 1;
+}
+
+}  // namespace chainrk4
+
+namespace {
 
 constexpr size_t kAlign = 256;
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -80,8 +91,6 @@ int check_desc(const chain_rk4_desc *d) {
         return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
     return CHAIN_OK;
 }
-
-size_t elem_bytes(int prec) { return prec == CHAIN_FP64 ? sizeof(double) : sizeof(float); }
 
 // Workspace regions, in order. Unused regions have size 0.
 struct Layout {
@@ -124,11 +133,6 @@ Layout layout(const chain_rk4_desc *d) {
     return L;
 }
 
-struct Plan {
-    bool resident = false;
-    int sites = 0, depth = 0, waves_per_cluster = 0;
-    int64_t tile = 0, halo = 0, waves = 0;
-};
 
 Plan make_plan(const chain_rk4_desc *d) {
     Plan P;
@@ -151,29 +155,9 @@ Plan make_plan(const chain_rk4_desc *d) {
     return P;
 }
 
-bool is_gfx950(int dev) {
-    static int cached[64];  // 0 unknown, 1 yes, 2 no
-    if (dev < 0 || dev >= 64) return false;
-    if (cached[dev] == 0) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
-        cached[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
-    }
-    return cached[dev] == 1;
-}
 
 }  // namespace
 
-struct chain_rk4 {
-    chain_rk4_desc d;
-    hipStream_t stream;
-    StateRef front, back;
-    NaiveBufs naive;
-    double *partials, *result;
-    Plan plan;
-    hipStream_t capture = nullptr;
-    std::map<int64_t, hipGraphExec_t> graphs;
-};
 
 namespace {
 
@@ -394,6 +378,7 @@ const char *chain_rk4_strerror(int status) {
     case CHAIN_EHIP: return "HIP runtime error";
     case CHAIN_ENONFINITE: return "energy is not finite";
     case CHAIN_EDEVICE: return "device is not a gfx950 GPU";
+    case CHAIN_ETIMEOUT: return "a batched launch timed out waiting for a neighbour";
     default: return "unknown status";
     }
 }

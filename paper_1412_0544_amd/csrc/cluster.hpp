@@ -1,0 +1,272 @@
+// cluster.hpp -- device code shared by the fused, resident and persistent
+// kernels: one cluster pass (Sec. 2.3 with the overlap carried over several
+// steps) and one whole-ring resident run. Every kernel that advances a chain
+// goes through these two functions, so every launch shape gives the same bits.
+#pragma once
+
+#include "launch.hpp"
+#include "rk4_device.hpp"
+
+namespace chainrk4 {
+
+template <class R, int S>
+__device__ __forceinline__ void load_contig(R (&dst)[S], const R *__restrict__ src) {
+    if constexpr (sizeof(R) == 8) {
+        const double2 *v = reinterpret_cast<const double2 *>(src);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) {
+            double2 t = v[m];
+            dst[2 * m] = t.x;
+            dst[2 * m + 1] = t.y;
+        }
+    } else {
+        const float4 *v = reinterpret_cast<const float4 *>(src);
+#pragma unroll
+        for (int m = 0; m < S / 4; ++m) {
+            float4 t = v[m];
+            dst[4 * m] = t.x;
+            dst[4 * m + 1] = t.y;
+            dst[4 * m + 2] = t.z;
+            dst[4 * m + 3] = t.w;
+        }
+    }
+}
+
+template <class R, int S>
+__device__ __forceinline__ void store_contig(R *__restrict__ dst, const R (&src)[S]) {
+    if constexpr (sizeof(R) == 8) {
+        double2 *v = reinterpret_cast<double2 *>(dst);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) v[m] = make_double2(src[2 * m], src[2 * m + 1]);
+    } else {
+        float4 *v = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+        for (int m = 0; m < S / 4; ++m)
+            v[m] = make_float4(src[4 * m], src[4 * m + 1], src[4 * m + 2], src[4 * m + 3]);
+    }
+}
+
+// Edge coordinates a wavefront publishes for its neighbours in the cluster,
+// double-buffered by stage parity so one barrier per stage suffices.
+template <class R, int WPB>
+struct EdgeSlots {
+    R first[2][WPB];
+    R last[2][WPB];
+};
+
+// One stage for the S sites of this lane. The right neighbour's first
+// coordinate comes in, this lane forms its last bond term, and that term goes
+// to the right neighbour lane as its left bond term. At a wavefront edge
+// inside the cluster the neighbour coordinate comes from LDS instead, and
+// lane 0 forms its left bond term itself (the same operation on the same
+// values as the left wavefront's lane 63).
+template <int M, int S, int STAGE, int W, int WPB, class R>
+__device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S], R (&aq)[S],
+                                           R (&ap)[S], const StepConsts<R> &c,
+                                           EdgeSlots<R, WPB> *slots, int lane, int wib, int wic,
+                                           int parity) {
+    const R first = (STAGE == 1) ? q[0] : Q[0];
+    const R last = (STAGE == 1) ? q[S - 1] : Q[S - 1];
+    R right = from_right(first);
+    if constexpr (W > 1) {
+        if (lane == 0) slots->first[parity][wib] = first;
+        if (lane == 63) slots->last[parity][wib] = last;
+        __syncthreads();
+        if (lane == 63 && wic + 1 < W) right = slots->first[parity][wib + 1];
+    }
+    const R brS = ModelOps<M, R>::bond(right - last);
+    R bl0 = from_left(brS);
+    if constexpr (W > 1) {
+        if (lane == 0 && wic > 0) bl0 = ModelOps<M, R>::bond(first - slots->last[parity][wib - 1]);
+    }
+    stage_sites<M, S, STAGE>(Q, P, q, p, aq, ap, bl0, brS, c);
+}
+
+// Registers of one lane's S sites.
+template <class R, bool KAHAN, int S>
+struct LaneState {
+    R q[S], p[S];
+    float cq[KAHAN ? S : 1], cp[KAHAN ? S : 1];
+};
+
+// Load this lane's S sites, starting at unwrapped site s0 of a ring of n
+// sites. `contiguous` (uniform over the cluster) says the cluster's sites
+// need no wrap, so vector loads apply.
+template <class R, bool KAHAN, int S>
+__device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const StateRef &in, int64_t n,
+                                          int64_t s0, bool contiguous) {
+    const R *qin = static_cast<const R *>(in.q);
+    const R *pin = static_cast<const R *>(in.p);
+    if (contiguous) {
+        load_contig<R, S>(st.q, qin + s0);
+        load_contig<R, S>(st.p, pin + s0);
+        if constexpr (KAHAN) {
+            load_contig<float, S>(st.cq, in.cq + s0);
+            load_contig<float, S>(st.cp, in.cp + s0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int64_t i = wrap_index(s0 + j, n);
+            st.q[j] = qin[i];
+            st.p[j] = pin[i];
+            if constexpr (KAHAN) {
+                st.cq[j] = in.cq[i];
+                st.cp[j] = in.cp[i];
+            }
+        }
+    }
+}
+
+// Store the kept sites of this lane: cluster-local positions
+// [keep_lo, keep_hi) that are also below n (lo is the lane's first local
+// position, s0 its unwrapped site; kept sites never wrap).
+template <class R, bool KAHAN, int S>
+__device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, const StateRef &out,
+                                           int64_t n, int64_t s0, int lo, int64_t keep_lo,
+                                           int64_t keep_hi) {
+    R *qout = static_cast<R *>(out.q);
+    R *pout = static_cast<R *>(out.p);
+    if (lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n) {
+        store_contig<R, S>(qout + s0, st.q);
+        store_contig<R, S>(pout + s0, st.p);
+        if constexpr (KAHAN) {
+            store_contig<float, S>(out.cq + s0, st.cq);
+            store_contig<float, S>(out.cp + s0, st.cp);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int local = lo + j;
+            const int64_t g = s0 + j;
+            if (local >= keep_lo && local < keep_hi && g < n) {
+                qout[g] = st.q[j];
+                pout[g] = st.p[j];
+                if constexpr (KAHAN) {
+                    out.cq[g] = st.cq[j];
+                    out.cp[g] = st.cp[j];
+                }
+            }
+        }
+    }
+}
+
+// One cluster pass: the cluster holds sites [e0, e0 + 64*S*W) of the
+// unwrapped ring (wrapped mod n on load), advances them `ksteps` steps and
+// stores the sites at cluster-local positions [halo, halo + keep). The caller
+// guarantees halo >= 4*ksteps and halo + keep <= 64*S*W, so the stored sites
+// are exact (the wrong values entering at the cluster edges travel one site
+// per stage). All wavefronts of the cluster must call this together.
+template <int M, class R, bool KAHAN, int S, int W, int WPB>
+__device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
+                                            int64_t e0, int64_t halo, int64_t keep, int ksteps,
+                                            double dt, EdgeSlots<R, WPB> *slots, int lane, int wib,
+                                            int wic) {
+    constexpr int E = 64 * S * W;
+    const int lo = (wic * 64 + lane) * S;
+    const int64_t s0 = e0 + lo;
+    LaneState<R, KAHAN, S> st;
+    load_lane<R, KAHAN, S>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
+    const StepConsts<R> c(dt);
+    R Q[S], P[S], aq[S], ap[S];
+    for (int k = 0; k < ksteps; ++k) {
+        lane_stage<M, S, 1, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
+        lane_stage<M, S, 2, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
+        lane_stage<M, S, 3, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
+        lane_stage<M, S, 4, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
+        if constexpr (KAHAN)
+            final_update_kahan<S>(st.q, st.p, st.cq, st.cp, aq, ap, c);
+        else
+            final_update<S>(st.q, st.p, aq, ap, c);
+    }
+    store_lane<R, KAHAN, S>(st, out, n, s0, lo, halo, halo + keep);
+}
+
+// Whole-ring resident run by a block of T threads: thread t owns sites
+// t + T*j (j < SPT, n <= T*SPT). The stage argument of every site is
+// published in LDS (`lds` holds 2*n values, two buffers used in turn, one
+// barrier per stage); the state, P and the accumulators stay in registers.
+// `out` may equal `in`: every load happens before the first store.
+template <int M, class R, bool KAHAN, int T, int SPT>
+__device__ __forceinline__ void run_resident(const StateRef &in, const StateRef &out, int n,
+                                             int64_t nsteps, double dt, R *lds) {
+    R *buf0 = lds;
+    R *buf1 = lds + n;
+    const int t = threadIdx.x;
+    const R *qin = static_cast<const R *>(in.q);
+    const R *pin = static_cast<const R *>(in.p);
+    R q[SPT], p[SPT], P[SPT], aq[SPT], ap[SPT];
+    float cq[KAHAN ? SPT : 1], cp[KAHAN ? SPT : 1];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = t + T * j;
+        if (i < n) {
+            q[j] = qin[i];
+            p[j] = pin[i];
+            if constexpr (KAHAN) {
+                cq[j] = in.cq[i];
+                cp[j] = in.cp[i];
+            }
+            buf0[i] = q[j];
+        }
+    }
+    __syncthreads();
+
+    const StepConsts<R> c(dt);
+    for (int64_t st = 0; st < nsteps; ++st) {
+        // stage s reads its argument from `cur` and publishes the next one
+        // (after stage 4: the new coordinates) in `nxt`
+#pragma unroll
+        for (int stage = 1; stage <= 4; ++stage) {
+            const R *cur = (stage & 1) ? buf0 : buf1;
+            R *nxt = (stage & 1) ? buf1 : buf0;
+#pragma unroll
+            for (int j = 0; j < SPT; ++j) {
+                const int i = t + T * j;
+                if (i < n) {
+                    const int im = (i == 0) ? n - 1 : i - 1;
+                    const int ip = (i == n - 1) ? 0 : i + 1;
+                    const R Qm = cur[im], Qj = cur[i], Qp = cur[ip];
+                    R Qn = Qj, Pn = P[j];
+                    if (stage == 1) {
+                        stage_one<M, 1, R>(Qm, Qj, Qp, p[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                    } else if (stage == 2) {
+                        stage_one<M, 2, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                    } else if (stage == 3) {
+                        stage_one<M, 3, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                    } else {
+                        stage_one<M, 4, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                        if constexpr (KAHAN) {
+                            kahan_add(q[j], cq[j], c.h6 * aq[j]);
+                            kahan_add(p[j], cp[j], c.h6 * ap[j]);
+                        } else {
+                            q[j] = fma_r(c.h6, aq[j], q[j]);
+                            p[j] = fma_r(c.h6, ap[j], p[j]);
+                        }
+                        Qn = q[j];
+                    }
+                    nxt[i] = Qn;
+                    if (stage != 4) P[j] = Pn;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    R *qout = static_cast<R *>(out.q);
+    R *pout = static_cast<R *>(out.p);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = t + T * j;
+        if (i < n) {
+            qout[i] = q[j];
+            pout[i] = p[j];
+            if constexpr (KAHAN) {
+                out.cq[i] = cq[j];
+                out.cp[i] = cp[j];
+            }
+        }
+    }
+}
+
+}  // namespace chainrk4

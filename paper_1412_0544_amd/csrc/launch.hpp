@@ -62,4 +62,57 @@ hipError_t launch_energy(int model, int prec, StateRef y, int64_t n, double *par
 
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batches: one persistent launch over many chains. Work items, claimed in
+// increasing order from a counter: first one item per resident chain (a ring
+// short enough to stay in LDS for all its steps), then, pass by pass, one
+// item per (chain, cluster). Item (c, g, e) needs clusters g-1, g, g+1 of
+// chain c to have finished pass e-1; those items have smaller indices, so
+// waiting on them cannot deadlock.
+// ---------------------------------------------------------------------------
+constexpr int kBatchThreads = 256;      // 4 wavefronts = one cluster
+constexpr int kBatchWaves = 4;
+constexpr int kBatchResidentSites = 1024;  // longest ring a batch keeps on chip
+
+constexpr int batch_resident_max(int /*prec*/) { return kBatchResidentSites; }
+
+struct BatchChain {
+    StateRef front, back;
+    int64_t n;
+    int64_t nsteps;        // resident chains: steps of this launch
+    int64_t uq, ur;        // tiled: each cluster keeps 4*uq or 4*(uq+1) sites
+                           // (the first ur clusters the larger), the last
+                           // cluster also the n % 4 remainder
+    double dt;
+    int32_t clusters;      // tiled: clusters per pass
+    int32_t passes;        // tiled: passes of this launch
+    int32_t head0, head1;  // steps of passes 0 and 1 when nhead == 2
+    int32_t nhead;         // 0 or 2
+    int32_t tail;          // steps of the last pass, 0 if it is a full pass
+    int32_t flag_base;     // first progress flag of this chain
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const BatchChain *chains;      // tiled chains (by passes, descending), then resident
+    const int64_t *pass_off;       // pass_off[e]: first tiled item of pass e
+    const int32_t *item_chain;     // chain of the w-th item of a pass
+    const int32_t *item_cluster;   // cluster of the w-th item of a pass
+    int32_t *flags;                // per cluster: passes completed
+    unsigned long long *counter;   // next unclaimed item
+    int32_t *error;                // set when a bounded wait expires
+    int64_t total_items;
+    int64_t halo;                  // 4 * depth
+    int32_t n_resident, n_tiled;
+    int32_t max_passes;
+    int32_t depth;                 // steps of a full pass
+    int32_t spin_limit;            // polls before a wait gives up
+    int32_t pad;
+};
+
+// Blocks of the persistent kernel the device holds at once (0 on error).
+int persistent_capacity(int model, int prec, int sites_per_lane);
+hipError_t launch_persistent(int model, int prec, int sites_per_lane, int blocks,
+                             const BatchArgs &a, hipStream_t s);
+
 }  // namespace chainrk4

@@ -1,0 +1,165 @@
+// persistent.hip -- one launch advances many chains (or one long chain) by
+// many passes. Blocks claim work items in increasing order from a counter:
+// resident rings first (each whole run in one item, on chip), then pass by
+// pass one item per (chain, cluster). A cluster item of pass e waits until
+// its own cluster and both neighbours have finished pass e-1 (progress
+// flags), so passes overlap across the chip instead of ending at a kernel
+// boundary. Each cluster item is the same cluster pass as the fused kernel
+// (Sec. 2.3 overlap carried over several steps) and each resident item the
+// same run as the resident kernel, so results are identical bits.
+//
+// Memory ordering: a finished item's stores are released at agent scope
+// before its flag is set; a waiting item acquires at agent scope after it
+// sees the flags, so the neighbour data is visible across XCDs. Every wait is
+// bounded: past the limit the error word is set and the item goes on, so
+// every block always exits.
+#include "cluster.hpp"
+
+namespace chainrk4 {
+namespace {
+
+__device__ __forceinline__ int load_flag(const int32_t *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: wait until flags f0, f1, f2 reach `need`.
+__device__ bool wait_flags(const int32_t *f0, const int32_t *f1, const int32_t *f2, int need,
+                           int32_t *error, int spin_limit) {
+    for (int spin = 0;; ++spin) {
+        if (load_flag(f0) >= need && load_flag(f1) >= need && load_flag(f2) >= need) return true;
+        if (spin >= spin_limit || load_flag(error) != 0) {
+            __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// A value every lane holds alike, moved to a scalar register.
+__device__ __forceinline__ long long uniform64(long long x) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(x));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(x >> 32));
+    return static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ int pass_steps(const BatchChain &ch, int e, int depth) {
+    if (e < ch.nhead) return e == 0 ? ch.head0 : ch.head1;
+    if (ch.tail > 0 && e == ch.passes - 1) return ch.tail;
+    return depth;
+}
+
+template <int M, class R, bool KAHAN, int S>
+__global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) {
+    constexpr int W = kBatchWaves, WPB = kBatchWaves;
+    constexpr int RMAX = kBatchResidentSites;
+    constexpr int SPT = RMAX / kBatchThreads;
+    constexpr int E = 64 * S * W;
+    __shared__ EdgeSlots<R, WPB> slots;
+    __shared__ __align__(16) R ring[2 * RMAX];
+    __shared__ long long claimed;
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    int pass = 0;  // forward scan position in pass_off (uniform over the block)
+
+    for (;;) {
+        if (threadIdx.x == 0)
+            claimed = static_cast<long long>(atomicAdd(a.counter, 1ull));
+        __syncthreads();
+        const long long item = uniform64(claimed);
+        __syncthreads();
+        if (item >= a.total_items) break;
+
+        if (item < a.n_resident) {
+            const BatchChain &ch = a.chains[a.n_tiled + item];
+            run_resident<M, R, KAHAN, kBatchThreads, SPT>(ch.front, ch.front, static_cast<int>(ch.n),
+                                                          ch.nsteps, ch.dt, ring);
+            continue;
+        }
+
+        const int64_t j = item - a.n_resident;
+        while (a.pass_off[pass + 1] <= j) ++pass;
+        const int64_t w = j - a.pass_off[pass];
+        const BatchChain &ch = a.chains[__builtin_amdgcn_readfirstlane(a.item_chain[w])];
+        const int g = __builtin_amdgcn_readfirstlane(a.item_cluster[w]);
+        const int G = ch.clusters;
+        int32_t *fl = a.flags + ch.flag_base;
+        if (pass > 0) {
+            if (threadIdx.x == 0)
+                wait_flags(fl + (g == 0 ? G - 1 : g - 1), fl + g, fl + (g == G - 1 ? 0 : g + 1), pass,
+                           a.error, a.spin_limit);
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        const int64_t start = 4 * (static_cast<int64_t>(g) * ch.uq + (g < ch.ur ? g : ch.ur));
+        const int64_t keep = (g == G - 1) ? ch.n - start : 4 * (ch.uq + (g < ch.ur ? 1 : 0));
+        const StateRef &in = (pass & 1) ? ch.back : ch.front;
+        const StateRef &out = (pass & 1) ? ch.front : ch.back;
+        run_cluster<M, R, KAHAN, S, W, WPB>(in, out, ch.n, start - a.halo, a.halo, keep,
+                                            pass_steps(ch, pass, a.depth), ch.dt, &slots, lane, wib,
+                                            wib);
+        static_assert(E >= 64, "cluster");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(fl + g, pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int M, class R, bool KAHAN, int S>
+int capacity_one() {
+    static int cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<M, R, KAHAN, S>,
+                                                         kBatchThreads, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = per_cu * cus;
+    }
+    return cached[dev];
+}
+
+template <int M, class R, bool KAHAN>
+int capacity_s(int s) {
+    switch (s) {
+    case 4: return capacity_one<M, R, KAHAN, 4>();
+    case 8: return capacity_one<M, R, KAHAN, 8>();
+    case 16: return capacity_one<M, R, KAHAN, 16>();
+    default: return 0;
+    }
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t launch_s(int s, int blocks, const BatchArgs &a, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>(blocks)), block(kBatchThreads);
+    switch (s) {
+    case 4: persistent_kernel<M, R, KAHAN, 4><<<grid, block, 0, st>>>(a); break;
+    case 8: persistent_kernel<M, R, KAHAN, 8><<<grid, block, 0, st>>>(a); break;
+    case 16: persistent_kernel<M, R, KAHAN, 16><<<grid, block, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int persistent_capacity(int model, int prec, int s) {
+    if (model == kQuartic)
+        return prec == 0 ? capacity_s<kQuartic, double, false>(s) : capacity_s<kQuartic, float, true>(s);
+    return prec == 0 ? capacity_s<kHarmonic, double, false>(s) : capacity_s<kHarmonic, float, true>(s);
+}
+
+hipError_t launch_persistent(int model, int prec, int s, int blocks, const BatchArgs &a,
+                             hipStream_t st) {
+    if (blocks < 1) return hipErrorInvalidValue;
+    if (model == kQuartic)
+        return prec == 0 ? launch_s<kQuartic, double, false>(s, blocks, a, st)
+                         : launch_s<kQuartic, float, true>(s, blocks, a, st);
+    return prec == 0 ? launch_s<kHarmonic, double, false>(s, blocks, a, st)
+                     : launch_s<kHarmonic, float, true>(s, blocks, a, st);
+}
+
+}  // namespace chainrk4

@@ -100,3 +100,20 @@ def test_oracle_is_not_linked_into_the_product():
             if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_batch_calls_reject_bad_arguments_without_a_gpu():
+    lib = L.lib()
+    d = L.BatchDesc(10, 0, 0, 0, 0, 0, 0)
+    assert lib.chain_rk4_batch_workspace_bytes(None, 1, ctypes.byref(d)) == 0
+    hs = (L.H * 1)(None)
+    assert lib.chain_rk4_batch_workspace_bytes(hs, 1, ctypes.byref(d)) == 0
+    assert lib.chain_rk4_batch_workspace_bytes(hs, 0, ctypes.byref(d)) == 0
+    out = L.VP()
+    assert lib.chain_rk4_batch_create(hs, 1, ctypes.byref(d), None, 0, None,
+                                      ctypes.byref(out)) == L.CHAIN_EINVAL
+    assert lib.chain_rk4_batch_create(hs, 1, None, None, 0, None, ctypes.byref(out)) == L.CHAIN_EINVAL
+    assert lib.chain_rk4_batch_step(None, None) == L.CHAIN_EINVAL
+    assert lib.chain_rk4_batch_check(None) == L.CHAIN_EINVAL
+    assert lib.chain_rk4_batch_destroy(None) == L.CHAIN_OK
+    assert lib.chain_rk4_strerror(L.CHAIN_ETIMEOUT) != b"unknown status"

@@ -14,17 +14,20 @@ PROGRAM = r"""
 #include "chain_rk4.h"
 #define F(T, m) printf("%s.%s %zu\n", #T, #m, offsetof(T, m));
 int main(void) {
-  printf("chain_rk4_desc %zu\n", sizeof(chain_rk4_desc));
-  printf("chain_rk4_plan %zu\n", sizeof(chain_rk4_plan));
   %FIELDS%
   return 0;
 }
 """
 
 
+STRUCTS = (("chain_rk4_desc", L.Desc), ("chain_rk4_plan", L.Plan),
+           ("chain_rk4_batch_desc", L.BatchDesc), ("chain_rk4_batch_plan", L.BatchPlan))
+
+
 def test_struct_layouts_match(tmp_path):
     fields = []
-    for cname, cls in (("chain_rk4_desc", L.Desc), ("chain_rk4_plan", L.Plan)):
+    for cname, cls in STRUCTS:
+        fields.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for name, _ in cls._fields_:
             fields.append(f"F({cname}, {name})")
     src = tmp_path / "layout.c"
@@ -33,8 +36,8 @@ def test_struct_layouts_match(tmp_path):
     subprocess.run(["gcc", "-std=c99", f"-I{ROOT}/include", str(src), "-o", str(exe)], check=True)
     out = dict(line.rsplit(" ", 1) for line in subprocess.run(
         [str(exe)], capture_output=True, text=True, check=True).stdout.split("\n") if line)
-    assert int(out["chain_rk4_desc"]) == ctypes.sizeof(L.Desc)
-    assert int(out["chain_rk4_plan"]) == ctypes.sizeof(L.Plan)
-    for cname, cls in (("chain_rk4_desc", L.Desc), ("chain_rk4_plan", L.Plan)):
+    for cname, cls in STRUCTS:
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
+    for cname, cls in STRUCTS:
         for name, _ in cls._fields_:
             assert int(out[f"{cname}.{name}"]) == getattr(cls, name).offset, (cname, name)

@@ -1,0 +1,187 @@
+"""Batches through the C ABI: one persistent launch over many chains.
+
+Every chain of a batch must give the same bits as the chain stepped alone,
+for any grid size (one workgroup up to the full device) and any split of the
+steps into calls; a sample is checked against the CPU oracle (FP64 bar:
+1e-10 max-abs).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1412_0544_amd import Batch, Chain, ChainError
+from paper_1412_0544_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+LENGTHS = [1, 2, 7, 300, 1024, 1025, 2049, 5003, 20011, 65536]
+
+
+def make_chains(lengths, seeds, prec="fp64", model="quartic", dt=0.01):
+    chains = []
+    for n, s in zip(lengths, seeds):
+        dtype = np.float64 if prec == "fp64" else np.float32
+        q0, p0 = workloads.chain_ics(n, s, dtype=dtype)
+        chains.append(Chain(q0, p0, dt, model=model, prec=prec))
+    return chains
+
+
+def snapshot(ch):
+    out = [ch.q.cpu().numpy().copy(), ch.p.cpu().numpy().copy()]
+    cq, cp = ch.carry_tensors()
+    if cq is not None:
+        out += [cq.cpu().numpy().copy(), cp.cpu().numpy().copy()]
+    return out
+
+
+def solo(n, seed, steps, prec="fp64", model="quartic", dt=0.01):
+    dtype = np.float64 if prec == "fp64" else np.float32
+    q0, p0 = workloads.chain_ics(n, seed, dtype=dtype)
+    ch = Chain(q0, p0, dt, model=model, prec=prec, sites_per_lane=8, kdepth=5, resident=False)
+    ch.step(steps)
+    out = snapshot(ch)
+    ch.close()
+    return out
+
+
+@pytest.mark.parametrize("shape", [(0, 0), (8, 12), (4, 16), (16, 8), (4, 2)])
+def test_batch_matches_solo_bitwise(shape):
+    sites, depth = shape
+    steps = [37, 0, 1, 100, 5, 2, 64, 13, 3, 24]
+    chains = make_chains(LENGTHS, range(10, 20))
+    b = Batch(chains, max_steps=100, sites_per_lane=sites, kdepth=depth)
+    b.step(steps)
+    b.check()
+    for ch, n, s, k in zip(chains, LENGTHS, range(10, 20), steps):
+        got = snapshot(ch)
+        want = solo(n, s, k)
+        for x, y in zip(got, want):
+            assert np.array_equal(x, y), (n, k, shape)
+    b.close()
+
+
+def test_batch_against_oracle():
+    steps = [100] * len(LENGTHS)
+    chains = make_chains(LENGTHS, range(30, 40))
+    b = Batch(chains, max_steps=100)
+    b.step(steps)
+    b.check()
+    e = b.energies()
+    for ch, n, s, ek in zip(chains, LENGTHS, range(30, 40), e):
+        q0, p0 = workloads.chain_ics(n, s)
+        qo, po = oracle.rk4(oracle.QUARTIC, q0, p0, 0.01, 100, threads=8)
+        q, p = (t.cpu().numpy() for t in ch.state())
+        assert np.abs(q - qo).max() <= TOL and np.abs(p - po).max() <= TOL, n
+        eo = oracle.energy(oracle.QUARTIC, qo, po)
+        assert abs(ek - eo) <= 1e-12 * abs(eo)
+
+
+def test_grid_size_and_repeats_do_not_change_bits():
+    """Race check: one workgroup, a few, and the full device, repeated."""
+    lengths = [300, 5003, 20011, 65536, 100000]
+    ref = None
+    for grid in (1, 3, 0, 0, 0, 17, 0):
+        chains = make_chains(lengths, range(50, 55))
+        b = Batch(chains, max_steps=60, grid_blocks=grid)
+        b.step([60, 41, 60, 33, 60])
+        b.check()
+        got = [snapshot(c) for c in chains]
+        if ref is None:
+            ref = got
+        else:
+            for a, r in zip(got, ref):
+                for x, y in zip(a, r):
+                    assert np.array_equal(x, y), grid
+        b.close()
+
+
+def test_successive_calls_equal_one_call():
+    lengths = [1000, 9000, 33333]
+    one = make_chains(lengths, range(60, 63))
+    b1 = Batch(one, max_steps=90)
+    b1.step(90)
+    many = make_chains(lengths, range(60, 63))
+    b2 = Batch(many, max_steps=90)
+    for k in (1, 2, 30, 57):
+        b2.step(k)
+    b2.check()
+    for x, y in zip(one, many):
+        assert torch.equal(x.q, y.q) and torch.equal(x.p, y.p)
+
+
+@pytest.mark.parametrize("model", ["quartic", "harmonic"])
+def test_fp32_batch_matches_solo(model):
+    lengths = [64, 1024, 3000, 40000]
+    steps = [20, 7, 33, 12]
+    chains = make_chains(lengths, range(70, 74), prec="fp32_kahan", model=model)
+    b = Batch(chains, max_steps=40)
+    b.step(steps)
+    b.check()
+    for ch, n, s, k in zip(chains, lengths, range(70, 74), steps):
+        got = snapshot(ch)
+        want = solo(n, s, k, prec="fp32_kahan", model=model)
+        for x, y in zip(got, want):
+            assert np.array_equal(x, y)
+
+
+def test_forced_timeout_is_reported_and_kernel_exits():
+    """A spin limit of one poll makes items that must wait give up: the call
+    reports CHAIN_ETIMEOUT and the launch still finishes."""
+    chains = make_chains([200000], [80])
+    b = Batch(chains, max_steps=400, spin_limit=1)
+    b.step(400)
+    assert b.check_status() == L.CHAIN_ETIMEOUT
+    with pytest.raises(ChainError):
+        b.check()
+    b.close()
+    # the same batch shape with the default limit is fine
+    chains = make_chains([200000], [80])
+    b = Batch(chains, max_steps=400)
+    b.step(400)
+    b.check()
+
+
+def test_batch_rejects_bad_arguments():
+    a = make_chains([100], [1], prec="fp64")
+    c = make_chains([100], [1], prec="fp32_kahan")
+    with pytest.raises(ChainError):
+        Batch(a + c, max_steps=10)      # mixed precision
+    with pytest.raises(ChainError):
+        Batch(a + a, max_steps=10)      # same handle twice
+    naive = Chain(np.zeros(10), np.zeros(10), 0.01, method="naive")
+    with pytest.raises(ChainError):
+        Batch([naive], max_steps=10)
+    b = Batch(a, max_steps=10)
+    with pytest.raises(ChainError):
+        b.step([11])
+    with pytest.raises(ChainError):
+        b.step([-1])
+
+
+def test_workload_4096_chains_sampled():
+    """4096 chains, lengths log-uniform in [256, 65536] (seed 4096), ICs per
+    chain from seed 1000 + b, dt = 0.01, 100 steps, one launch: sampled
+    chains against solo runs (bits) and the oracle (1e-10)."""
+    lengths = workloads.batch_lengths(4096)
+    chains = []
+    for i, n in enumerate(lengths):
+        q0, p0 = workloads.chain_ics(int(n), 1000 + i)
+        chains.append(Chain(q0, p0, 0.01))
+    b = Batch(chains, max_steps=100)
+    b.step(100)
+    b.check()
+    rng = np.random.default_rng(1)
+    sample = sorted(set(rng.integers(0, 4096, 12).tolist()) | {int(np.argmin(lengths)),
+                                                              int(np.argmax(lengths))})
+    for i in sample:
+        n = int(lengths[i])
+        got = snapshot(chains[i])
+        want = solo(n, 1000 + i, 100)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+        q0, p0 = workloads.chain_ics(n, 1000 + i)
+        sites = np.unique(np.linspace(0, n - 1, 9).astype(np.int64))
+        qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, 0.01, 100, sites, threads=8)
+        assert np.abs(got[0][sites] - qs).max() <= TOL and np.abs(got[1][sites] - ps).max() <= TOL
