@@ -182,13 +182,20 @@ const char *chain_rk4_last_error(void);
  * CHAIN_FUSED, appear once, and must stay valid while the batch exists; each
  * chain keeps its own dt. Calls that overlap on one batch's workspace race.
  */
+enum chain_batch_flags {
+    CHAIN_BATCH_FENCES = 1  /* hand cluster data between workgroups with
+                               ordinary loads and stores plus agent-scope
+                               cache write-back and invalidation, instead of
+                               device-coherent loads and stores */
+};
+
 typedef struct chain_rk4_batch_desc {
     int64_t max_steps;       /* largest per-chain step count of one step call */
     int32_t sites_per_lane;  /* 0 = default (8), else 4, 8 or 16 */
     int32_t kdepth;          /* steps per pass, 0 = default (12), else 2..16 */
     int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
                                 once; any value >= 1 gives the same results */
-    int32_t flags;           /* must be 0 */
+    int32_t flags;           /* 0, or CHAIN_BATCH_FENCES */
     int32_t spin_limit;      /* polls before a wait for a neighbour gives up,
                                 0 = default (about 4 s); small values force
                                 CHAIN_ETIMEOUT for failure-path tests */

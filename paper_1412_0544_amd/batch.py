@@ -17,14 +17,14 @@ class Batch:
     """A persistent-launch batch over `chains` (one model and precision)."""
 
     def __init__(self, chains: list[Chain], max_steps: int, sites_per_lane: int = 0,
-                 kdepth: int = 0, grid_blocks: int = 0, spin_limit: int = 0,
+                 kdepth: int = 0, grid_blocks: int = 0, spin_limit: int = 0, flags: int = 0,
                  stream: torch.cuda.Stream | None = None):
         if not chains:
             raise ValueError("a batch needs at least one chain")
         self.chains = list(chains)
         self.device = chains[0].device
         self.desc = L.BatchDesc(int(max_steps), int(sites_per_lane), int(kdepth), int(grid_blocks),
-                                0, int(spin_limit), 0)
+                                int(flags), int(spin_limit), 0)
         n = len(chains)
         self._hs = (L.H * n)(*[c.handle for c in chains])
         lib = L.lib()

@@ -125,7 +125,8 @@ int check_batch(chain_rk4 *const *hs, int count, const chain_rk4_batch_desc *d, 
     if (d->kdepth != 0 && (d->kdepth < 2 || d->kdepth > 16))
         return fail(CHAIN_EINVAL, "batch kdepth must be 0 or 2..16");
     if (d->grid_blocks < 0) return fail(CHAIN_EINVAL, "grid_blocks must be >= 0");
-    if (d->flags != 0 || d->reserved != 0) return fail(CHAIN_EINVAL, "flags and reserved must be 0");
+    if ((d->flags & ~CHAIN_BATCH_FENCES) != 0 || d->reserved != 0)
+        return fail(CHAIN_EINVAL, "unknown batch flags, or reserved is not 0");
     if (d->spin_limit < 0) return fail(CHAIN_EINVAL, "spin_limit must be >= 0");
     for (int i = 0; i < count; ++i) {
         if (!hs[i]) return fail(CHAIN_EINVAL, "handle %d is NULL", i);
@@ -330,6 +331,7 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
     a.max_passes = static_cast<int32_t>(max_p);
     a.depth = b->depth;
     a.spin_limit = b->d.spin_limit ? b->d.spin_limit : kSpinLimit;
+    a.fences = (b->d.flags & CHAIN_BATCH_FENCES) ? 1 : 0;
 
     int blocks = b->d.grid_blocks;
     if (blocks == 0) {

@@ -82,6 +82,23 @@ __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&
     stage_sites<M, S, STAGE>(Q, P, q, p, aq, ap, bl0, brS, c);
 }
 
+// Device-coherent element access (memory scope: agent). Stores are written
+// through to the point where every XCD sees them and loads are not served
+// from a stale cache line, so cluster outputs can be handed to a cluster
+// running on another XCD without writing back or invalidating whole caches.
+template <class R>
+using global_ptr = __attribute__((address_space(1))) R *;
+
+template <class R>
+__device__ __forceinline__ R load_coherent(const R *p) {
+    return __hip_atomic_load((global_ptr<R>)(const_cast<R *>(p)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class R>
+__device__ __forceinline__ void store_coherent(R *p, R v) {
+    __hip_atomic_store((global_ptr<R>)(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Registers of one lane's S sites.
 template <class R, bool KAHAN, int S>
 struct LaneState {
@@ -92,12 +109,23 @@ struct LaneState {
 // Load this lane's S sites, starting at unwrapped site s0 of a ring of n
 // sites. `contiguous` (uniform over the cluster) says the cluster's sites
 // need no wrap, so vector loads apply.
-template <class R, bool KAHAN, int S>
+template <class R, bool KAHAN, int S, bool COH = false>
 __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const StateRef &in, int64_t n,
                                           int64_t s0, bool contiguous) {
     const R *qin = static_cast<const R *>(in.q);
     const R *pin = static_cast<const R *>(in.p);
-    if (contiguous) {
+    if constexpr (COH) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int64_t i = contiguous ? s0 + j : wrap_index(s0 + j, n);
+            st.q[j] = load_coherent(qin + i);
+            st.p[j] = load_coherent(pin + i);
+            if constexpr (KAHAN) {
+                st.cq[j] = load_coherent(in.cq + i);
+                st.cp[j] = load_coherent(in.cp + i);
+            }
+        }
+    } else if (contiguous) {
         load_contig<R, S>(st.q, qin + s0);
         load_contig<R, S>(st.p, pin + s0);
         if constexpr (KAHAN) {
@@ -121,13 +149,27 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
 // Store the kept sites of this lane: cluster-local positions
 // [keep_lo, keep_hi) that are also below n (lo is the lane's first local
 // position, s0 its unwrapped site; kept sites never wrap).
-template <class R, bool KAHAN, int S>
+template <class R, bool KAHAN, int S, bool COH = false>
 __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, const StateRef &out,
                                            int64_t n, int64_t s0, int lo, int64_t keep_lo,
                                            int64_t keep_hi) {
     R *qout = static_cast<R *>(out.q);
     R *pout = static_cast<R *>(out.p);
-    if (lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n) {
+    if constexpr (COH) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int local = lo + j;
+            const int64_t g = s0 + j;
+            if (local >= keep_lo && local < keep_hi && g < n) {
+                store_coherent(qout + g, st.q[j]);
+                store_coherent(pout + g, st.p[j]);
+                if constexpr (KAHAN) {
+                    store_coherent(out.cq + g, st.cq[j]);
+                    store_coherent(out.cp + g, st.cp[j]);
+                }
+            }
+        }
+    } else if (lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n) {
         store_contig<R, S>(qout + s0, st.q);
         store_contig<R, S>(pout + s0, st.p);
         if constexpr (KAHAN) {
@@ -157,7 +199,7 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
 // guarantees halo >= 4*ksteps and halo + keep <= 64*S*W, so the stored sites
 // are exact (the wrong values entering at the cluster edges travel one site
 // per stage). All wavefronts of the cluster must call this together.
-template <int M, class R, bool KAHAN, int S, int W, int WPB>
+template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false>
 __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
                                             int64_t e0, int64_t halo, int64_t keep, int ksteps,
                                             double dt, EdgeSlots<R, WPB> *slots, int lane, int wib,
@@ -166,7 +208,7 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     const int lo = (wic * 64 + lane) * S;
     const int64_t s0 = e0 + lo;
     LaneState<R, KAHAN, S> st;
-    load_lane<R, KAHAN, S>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
+    load_lane<R, KAHAN, S, COH>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
     const StepConsts<R> c(dt);
     R Q[S], P[S], aq[S], ap[S];
     for (int k = 0; k < ksteps; ++k) {
@@ -179,7 +221,7 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
         else
             final_update<S>(st.q, st.p, aq, ap, c);
     }
-    store_lane<R, KAHAN, S>(st, out, n, s0, lo, halo, halo + keep);
+    store_lane<R, KAHAN, S, COH>(st, out, n, s0, lo, halo, halo + keep);
 }
 
 // Whole-ring resident run by a block of T threads: thread t owns sites

@@ -107,7 +107,7 @@ struct BatchArgs {
     int32_t max_passes;
     int32_t depth;                 // steps of a full pass
     int32_t spin_limit;            // polls before a wait gives up
-    int32_t pad;
+    int32_t fences;                // hand-off by cache write-back/invalidate
 };
 
 // Blocks of the persistent kernel the device holds at once (0 on error).

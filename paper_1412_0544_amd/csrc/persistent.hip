@@ -48,7 +48,17 @@ __device__ __forceinline__ int pass_steps(const BatchChain &ch, int e, int depth
     return depth;
 }
 
-template <int M, class R, bool KAHAN, int S>
+// Wait until every memory operation this wavefront issued has completed.
+__device__ __forceinline__ void drain_memory() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// COH: cluster data moves through device-coherent loads and stores, and the
+// hand-off only waits for them to complete. Otherwise: ordinary accesses with
+// an agent-scope release (cache write-back) and acquire (invalidate).
+template <int M, class R, bool KAHAN, int S, bool COH>
 __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) {
     constexpr int W = kBatchWaves, WPB = kBatchWaves;
     constexpr int RMAX = kBatchResidentSites;
@@ -88,31 +98,34 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
                 wait_flags(fl + (g == 0 ? G - 1 : g - 1), fl + g, fl + (g == G - 1 ? 0 : g + 1), pass,
                            a.error, a.spin_limit);
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         const int64_t start = 4 * (static_cast<int64_t>(g) * ch.uq + (g < ch.ur ? g : ch.ur));
         const int64_t keep = (g == G - 1) ? ch.n - start : 4 * (ch.uq + (g < ch.ur ? 1 : 0));
         const StateRef &in = (pass & 1) ? ch.back : ch.front;
         const StateRef &out = (pass & 1) ? ch.front : ch.back;
-        run_cluster<M, R, KAHAN, S, W, WPB>(in, out, ch.n, start - a.halo, a.halo, keep,
-                                            pass_steps(ch, pass, a.depth), ch.dt, &slots, lane, wib,
-                                            wib);
+        run_cluster<M, R, KAHAN, S, W, WPB, COH>(in, out, ch.n, start - a.halo, a.halo, keep,
+                                                 pass_steps(ch, pass, a.depth), ch.dt, &slots, lane,
+                                                 wib, wib);
         static_assert(E >= 64, "cluster");
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if constexpr (COH)
+            drain_memory();
+        else
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (threadIdx.x == 0)
             __hip_atomic_store(fl + g, pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-template <int M, class R, bool KAHAN, int S>
+template <int M, class R, bool KAHAN, int S, bool COH>
 int capacity_one() {
     static int cached[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<M, R, KAHAN, S>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<M, R, KAHAN, S, COH>,
                                                          kBatchThreads, 0) != hipSuccess)
             return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -125,23 +138,29 @@ int capacity_one() {
 template <int M, class R, bool KAHAN>
 int capacity_s(int s) {
     switch (s) {
-    case 4: return capacity_one<M, R, KAHAN, 4>();
-    case 8: return capacity_one<M, R, KAHAN, 8>();
-    case 16: return capacity_one<M, R, KAHAN, 16>();
+    case 4: return capacity_one<M, R, KAHAN, 4, true>();
+    case 8: return capacity_one<M, R, KAHAN, 8, true>();
+    case 16: return capacity_one<M, R, KAHAN, 16, true>();
     default: return 0;
     }
 }
 
-template <int M, class R, bool KAHAN>
-hipError_t launch_s(int s, int blocks, const BatchArgs &a, hipStream_t st) {
+template <int M, class R, bool KAHAN, bool COH>
+hipError_t launch_c(int s, int blocks, const BatchArgs &a, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>(blocks)), block(kBatchThreads);
     switch (s) {
-    case 4: persistent_kernel<M, R, KAHAN, 4><<<grid, block, 0, st>>>(a); break;
-    case 8: persistent_kernel<M, R, KAHAN, 8><<<grid, block, 0, st>>>(a); break;
-    case 16: persistent_kernel<M, R, KAHAN, 16><<<grid, block, 0, st>>>(a); break;
+    case 4: persistent_kernel<M, R, KAHAN, 4, COH><<<grid, block, 0, st>>>(a); break;
+    case 8: persistent_kernel<M, R, KAHAN, 8, COH><<<grid, block, 0, st>>>(a); break;
+    case 16: persistent_kernel<M, R, KAHAN, 16, COH><<<grid, block, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t launch_s(int s, int blocks, const BatchArgs &a, hipStream_t st) {
+    return a.fences ? launch_c<M, R, KAHAN, false>(s, blocks, a, st)
+                    : launch_c<M, R, KAHAN, true>(s, blocks, a, st);
 }
 
 }  // namespace
