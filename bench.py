@@ -110,21 +110,23 @@ def fused_launches(plan, steps):
 
 
 def cpu_baseline(n, dt, target_s=10.0):
-    import numpy as np
+    """The oracle (as it stands) on the host cores: the same chain and ICs,
+    as many steps as fit in about `target_s` seconds."""
     import oracle
     import workloads
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     q0, p0 = workloads.chain_ics(n, 0)
+    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 1, threads=threads)      # first touch
     t = time.perf_counter()
-    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 1, threads=threads)
-    one = time.perf_counter() - t
-    steps = max(1, min(200, int(target_s / max(one, 1e-6))))
+    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 2, threads=threads)
+    per_step = (time.perf_counter() - t) / 2
+    steps = max(1, min(400, int(target_s / max(per_step, 1e-6))))
     t = time.perf_counter()
     oracle.rk4(oracle.QUARTIC, q0, p0, dt, steps, threads=threads)
     el = time.perf_counter() - t
     return {"value": n * steps / el, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"quartic chain N={n}, {steps} RK4 steps from seed-0 ICs, "
+            "sample": f"quartic chain N={n}, {steps} RK4 steps from the seed-0 initial state, "
                       f"{threads} OpenMP threads, {el:.1f} s"}
 
 
@@ -141,6 +143,7 @@ def main(argv=None):
     ap.add_argument("--sweep", action="store_true", help="time the full (S, W, k) grid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -219,7 +222,7 @@ def main(argv=None):
         out["autotune_su_per_s"] = sweep
 
     if not args.no_variants:
-        out["variants"] = variants(qd, pd, dt, n, dev, (S, W))
+        out["variants"] = variants(qd, pd, dt, n, dev, (S, W), serve_jobs=args.serve_jobs)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -228,31 +231,167 @@ def main(argv=None):
     return 0
 
 
-def variants(qd, pd, dt, n, dev, sw):
-    """Other rows of the hot path, measured briefly at the same N."""
+def ev_seconds(fn, stream):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / 1e3
+
+
+def variant_precision(n, dt, dev, steps=10_000, every=100):
+    """FP32 state with compensated update vs the FP64 GPU path on the same
+    chain: relative energy drift sampled every `every` steps, and the 100-step
+    state error against the FP64 oracle (sampled sites, from the FP32-rounded
+    initial state)."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    from paper_1412_0544_amd import Chain
+    q32, p32 = workloads.chain_ics_torch(n, 0, dev, torch.float32)
+    out = {"n": n, "steps": steps, "dt": dt}
+    for name, prec, q, p in (("fp64", "fp64", q32.double(), p32.double()),
+                             ("fp32_kahan", "fp32_kahan", q32, p32)):
+        ch = Chain(q, p, dt, prec=prec, device=dev)
+        e0 = ch.energy()
+        drift = []
+        t = 0.0
+        for _ in range(steps // every):
+            t += ev_seconds(lambda: ch.step(every), ch.stream)
+            drift.append((ch.energy() - e0) / e0)
+        out[name] = {"su_per_s": n * steps / t, "rel_drift_final": drift[-1],
+                     "rel_drift_max_abs": float(np.max(np.abs(drift))),
+                     "rel_drift_samples": drift[:: max(1, len(drift) // 20)]}
+        ch.close()
+    # 100-step error against the oracle (FP32-rounded ICs), sampled sites
+    q0 = q32.double().cpu().numpy()
+    p0 = p32.double().cpu().numpy()
+    sites = np.unique(np.linspace(0, n - 1, 48).astype(np.int64))
+    qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, dt, 100, sites)
+    for name, prec, q, p in (("fp64", "fp64", q32.double(), p32.double()),
+                             ("fp32_kahan", "fp32_kahan", q32, p32)):
+        ch = Chain(q, p, dt, prec=prec, device=dev)
+        ch.step(100)
+        cq, cp = ch.carry_tensors()
+        qq = ch.q.double() - (cq.double() if cq is not None else 0)
+        pp = ch.p.double() - (cp.double() if cp is not None else 0)
+        err = max(float(np.abs(qq.cpu().numpy()[sites] - qs).max()),
+                  float(np.abs(pp.cpu().numpy()[sites] - ps).max()))
+        out[name]["err100_vs_oracle"] = err
+        ch.close()
+    return out
+
+
+def variant_batch(dt, dev, steps=2000, count=4096):
+    """4096 chains, lengths log-uniform in [256, 65536], one persistent
+    launch of `steps` steps, FP64 and FP32 with compensated update."""
+    import torch
+    import workloads
+    from paper_1412_0544_amd import Batch, Chain
+    lengths = workloads.batch_lengths(count)
+    tot = int(lengths.sum())
+    out = {"chains": count, "sites": tot, "steps": steps}
+    for prec in ("fp64", "fp32_kahan"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        chains = [Chain(*workloads.chain_ics_torch(int(n_), 1000 + i, dev, dtype), dt, prec=prec,
+                        device=dev) for i, n_ in enumerate(lengths)]
+        b = Batch(chains, max_steps=steps, sites_per_lane=4, kdepth=16)
+        b.step(24)
+        b.check()
+        t = ev_seconds(lambda: b.step(steps), chains[0].stream)
+        b.check()
+        plan = b.plan()
+        out[prec] = {"su_per_s": tot * steps / t, "ms": t * 1e3, "grid_blocks": plan["grid_blocks"],
+                     "resident_chains": plan["resident_chains"],
+                     "clusters": plan["total_clusters"]}
+        b.close()
+        if prec == "fp64":
+            # the same chains, one step call per chain (100 steps each)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c in chains:
+                c.step(100)
+            torch.cuda.synchronize()
+            out["fp64_one_call_per_chain_su_per_s"] = tot * 100 / (time.perf_counter() - t0)
+        for c in chains:
+            c.close()
+    return out
+
+
+def variant_persistent_single(qd, pd, dt, dev, steps=1000):
+    from paper_1412_0544_amd import Batch, Chain
+    ch = Chain(qd, pd, dt, device=dev)
+    b = Batch([ch], max_steps=steps, sites_per_lane=4, kdepth=16)
+    b.step(32)
+    t = ev_seconds(lambda: b.step(steps), ch.stream)
+    b.check()
+    b.close()
+    ch.close()
+    return qd.numel() * steps / t
+
+
+def variant_serving(dt, dev, jobs=60, rho=0.8, rate_su=4e11, budget=4 << 30, quantum=1000,
+                    max_active=64):
+    """Poisson arrivals at load rho of `rate_su`; N log-uniform in [1e3, 4e6],
+    steps uniform in [1e3, 1e5], FP64/FP32 and quartic/harmonic each a coin."""
+    import workloads
+    from paper_1412_0544_amd.serve import GpuExecutor, Server, percentiles
+    mean_work = 4.82e5 * 5.05e4
+    lam = rho * rate_su / mean_work
+    js = workloads.served_jobs(jobs, lam, seed=5)
+    ex = GpuExecutor(device=dev, dt=dt, quantum=quantum, max_active=max_active,
+                     hbm_budget=budget)
+    srv = Server(ex, hbm_budget=budget, max_active=max_active, quantum=quantum)
+    t0 = time.perf_counter()
+    res = srv.run(js)
+    wall = time.perf_counter() - t0
+    done = [r for r in res if r.status == "done"]
+    su = sum(r.n * r.steps for r in done)
+    lat = percentiles([r.latency for r in done])
+    return {"jobs": jobs, "done": len(done), "arrival_rate_per_s": lam, "rho": rho,
+            "hbm_budget_bytes": budget, "quantum": quantum, "max_active": max_active,
+            "latency_s": lat, "queue_s": percentiles([r.queue_s for r in done]),
+            "service_s": percentiles([r.service_s for r in done]),
+            "jobs_per_s": len(done) / wall, "su_per_s": su / wall, "wall_s": wall,
+            "rounds": srv.rounds, "peak_hbm_bytes": srv.peak_used}
+
+
+def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
+    """Other rows of the hot path, each measured at its own configuration."""
     from paper_1412_0544_amd import Chain, autotune
     import workloads
     res = {}
-    # temporal depth k = 1, 2, 4, 8 at the tuned cluster shape
+    log("[bench] variant: temporal depth sweep")
     res["fused_k_su_per_s"] = {
         str(k): autotune.time_shape(qd, pd, dt, (sw[0], sw[1], k), steps=48, device=dev)
         for k in (1, 2, 4, 8)}
-    # the standard implementation: one kernel per stage
+    log("[bench] variant: naive per-stage")
     ch = Chain(qd, pd, dt, method="naive", device=dev)
     ch.step(2)
     _, g, _ = time_jobs(ch, 20, 2, with_energy=False)
     res["naive_su_per_s"] = n * 20 / min(g)
     ch.close()
-    # FP32 state with compensated update
-    res["fp32_kahan_su_per_s"] = autotune.time_shape(
-        qd.float(), pd.float(), dt, (16, 4, 12), prec="fp32_kahan", steps=96, device=dev)
-    # the 1024-site ring resident on chip, 1000 steps per job
+    log("[bench] variant: persistent single chain")
+    res["persistent_single_su_per_s"] = variant_persistent_single(qd, pd, dt, dev)
+    log("[bench] variant: 1024-site ring")
     q0, p0 = workloads.chain_ics(1024, 0)
     ch = Chain(q0, p0, dt, device=dev)
     time_jobs(ch, 1000, 1)
     lat, g, _ = time_jobs(ch, 1000, 5)
     res["ring1024_1000steps_ms"] = {"p50": 1e3 * pct(lat, 50), "gpu_min": 1e3 * min(g)}
     ch.close()
+    log("[bench] variant: FP32 with compensated update, 1e4 steps")
+    res["precision"] = variant_precision(n, dt, dev)
+    log("[bench] variant: 4096-chain batch")
+    res["batch4096"] = variant_batch(dt, dev)
+    if serve_jobs:
+        log(f"[bench] variant: serving {serve_jobs} jobs")
+        res["serving"] = variant_serving(dt, dev, jobs=serve_jobs,
+                                         rate_su=res["batch4096"]["fp64"]["su_per_s"])
     return res
 
 

@@ -191,6 +191,8 @@ enum chain_batch_flags {
 
 typedef struct chain_rk4_batch_desc {
     int64_t max_steps;       /* largest per-chain step count of one step call */
+    int64_t max_clusters;    /* capacity for chain_rk4_batch_rebind: clusters
+                                over all tiled chains (0 = what `hs` needs) */
     int32_t sites_per_lane;  /* 0 = default (8), else 4, 8 or 16 */
     int32_t kdepth;          /* steps per pass, 0 = default (12), else 2..16 */
     int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
@@ -199,7 +201,8 @@ typedef struct chain_rk4_batch_desc {
     int32_t spin_limit;      /* polls before a wait for a neighbour gives up,
                                 0 = default (about 4 s); small values force
                                 CHAIN_ETIMEOUT for failure-path tests */
-    int32_t reserved;        /* must be 0 */
+    int32_t max_chains;      /* capacity for chain_rk4_batch_rebind: chains
+                                (0 = count) */
 } chain_rk4_batch_desc;
 
 typedef struct chain_rk4_batch_plan {
@@ -221,6 +224,19 @@ size_t chain_rk4_batch_workspace_bytes(chain_rk4 *const *hs, int count,
 int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batch_desc *d,
                            void *workspace, size_t ws_bytes, void *stream,
                            chain_rk4_batch **out);
+
+/*
+ * Point an existing batch at another set of handles (same model and
+ * precision; count <= max_chains; their clusters <= max_clusters), reusing
+ * its workspace. Launches already enqueued keep the old set. Returns
+ * CHAIN_ENOMEM if the set exceeds the capacity.
+ */
+int chain_rk4_batch_rebind(chain_rk4_batch *b, chain_rk4 *const *hs, int count);
+
+/* Clusters a chain of n sites occupies in a batch of the given shape
+ * (sites_per_lane and kdepth as in the descriptor, 0 = default); 0 for a ring
+ * kept on chip. Used to size max_clusters. */
+int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdepth);
 
 /* Advance chain j by nsteps[j] (0..max_steps) steps in one persistent launch
  * (asynchronous; nsteps is read before the call returns). */

@@ -15,6 +15,7 @@ CHAIN_QUARTIC, CHAIN_HARMONIC = 0, 1
 CHAIN_FP64, CHAIN_FP32_KAHAN = 0, 1
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT = 1, 2
+CHAIN_BATCH_FENCES = 1
 
 CHAIN_OK = 0
 CHAIN_EINVAL = -1
@@ -42,10 +43,10 @@ class Plan(ctypes.Structure):
 
 
 class BatchDesc(ctypes.Structure):
-    _fields_ = [("max_steps", ctypes.c_int64), ("sites_per_lane", ctypes.c_int32),
-                ("kdepth", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+    _fields_ = [("max_steps", ctypes.c_int64), ("max_clusters", ctypes.c_int64),
+                ("sites_per_lane", ctypes.c_int32), ("kdepth", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32), ("max_chains", ctypes.c_int32)]
 
 
 class BatchPlan(ctypes.Structure):
@@ -86,6 +87,9 @@ def _declare(lib):
                                                   ctypes.POINTER(BatchDesc), VP, ctypes.c_size_t,
                                                   VP, ctypes.POINTER(VP)]),
         "chain_rk4_batch_step": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64)]),
+        "chain_rk4_batch_rebind": (ctypes.c_int, [VP, ctypes.POINTER(H), ctypes.c_int]),
+        "chain_rk4_batch_clusters": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32,
+                                                      ctypes.c_int32]),
         "chain_rk4_batch_check": (ctypes.c_int, [VP]),
         "chain_rk4_batch_energy": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
         "chain_rk4_batch_get_plan": (ctypes.c_int, [VP, ctypes.POINTER(BatchPlan)]),

@@ -18,13 +18,14 @@ class Batch:
 
     def __init__(self, chains: list[Chain], max_steps: int, sites_per_lane: int = 0,
                  kdepth: int = 0, grid_blocks: int = 0, spin_limit: int = 0, flags: int = 0,
+                 max_chains: int = 0, max_clusters: int = 0,
                  stream: torch.cuda.Stream | None = None):
         if not chains:
             raise ValueError("a batch needs at least one chain")
         self.chains = list(chains)
         self.device = chains[0].device
-        self.desc = L.BatchDesc(int(max_steps), int(sites_per_lane), int(kdepth), int(grid_blocks),
-                                int(flags), int(spin_limit), 0)
+        self.desc = L.BatchDesc(int(max_steps), int(max_clusters), int(sites_per_lane), int(kdepth),
+                                int(grid_blocks), int(flags), int(spin_limit), int(max_chains))
         n = len(chains)
         self._hs = (L.H * n)(*[c.handle for c in chains])
         lib = L.lib()
@@ -38,6 +39,20 @@ class Batch:
                                            self.stream.cuda_stream, ctypes.byref(b)),
                 "chain_rk4_batch_create")
         self._b = b
+
+    def rebind(self, chains: list[Chain]) -> "Batch":
+        """Point the batch at another set of chains within its capacity."""
+        n = len(chains)
+        hs = (L.H * max(n, 1))(*[c.handle for c in chains])
+        L.check(L.lib().chain_rk4_batch_rebind(self._b, hs, n), "chain_rk4_batch_rebind")
+        self.chains = list(chains)
+        self._hs = hs
+        return self
+
+    @staticmethod
+    def clusters(n: int, sites_per_lane: int = 0, kdepth: int = 0) -> int:
+        """Clusters a chain of n sites takes in a batch of that shape."""
+        return int(L.lib().chain_rk4_batch_clusters(int(n), int(sites_per_lane), int(kdepth)))
 
     def step(self, nsteps) -> "Batch":
         """Advance chain j by nsteps[j] steps (an int applies to every chain)."""

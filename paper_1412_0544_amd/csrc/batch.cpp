@@ -72,27 +72,66 @@ struct Layout {
     size_t total;
 };
 
-}  // namespace
-
-struct chain_rk4_batch {
-    std::vector<chain_rk4 *> hs;
-    chain_rk4_batch_desc d;
-    int model = 0, prec = 0, sites = 0, depth = 0;
+// Cluster shape of a batch: sites per lane, pass depth, halo, kept sites.
+struct Shape {
+    int sites = 0, depth = 0;
     int64_t halo = 0, tile_max = 0;
-    int64_t total_clusters = 0, max_passes = 0;
-    char *ws = nullptr;
-    Layout L{};
-    hipStream_t stream = nullptr;
-    void *staging = nullptr;       // pinned host copy of the tables
-    hipEvent_t staged = nullptr;   // the last table upload has been read
-    bool staged_pending = false;
-    std::vector<char> resident;    // per chain: kept on chip for a whole launch
-    std::vector<int64_t> clusters, uq, ur;
 };
 
-namespace {
+int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
+    if (sites_per_lane != 0 && sites_per_lane != 4 && sites_per_lane != 8 && sites_per_lane != 16)
+        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16");
+    if (kdepth != 0 && (kdepth < 2 || kdepth > 16))
+        return fail(CHAIN_EINVAL, "batch kdepth must be 0 or 2..16");
+    Shape sh;
+    sh.sites = sites_per_lane ? sites_per_lane : kDefaultBatchSites;
+    sh.depth = kdepth ? kdepth : kDefaultBatchDepth;
+    const int64_t E = 64 * static_cast<int64_t>(sh.sites) * kBatchWaves;
+    // every cluster keeps at least `halo` sites (so only neighbouring
+    // clusters overlap), with room to spare for the 4-site rounding
+    while (E < 16 * static_cast<int64_t>(sh.depth) + 16 && sh.depth > 2) --sh.depth;
+    sh.halo = 4 * static_cast<int64_t>(sh.depth);
+    sh.tile_max = E - 2 * sh.halo;
+    *out = sh;
+    return CHAIN_OK;
+}
 
-Layout batch_layout(int64_t count, int64_t total_clusters, int64_t max_passes) {
+int64_t clusters_of(int64_t n, const Shape &sh) {
+    if (n <= kBatchResidentSites) return 0;
+    int64_t G, uq, ur;
+    split_clusters(n, sh.tile_max, &G, &uq, &ur);
+    return G;
+}
+
+// Validate a handle set against a batch's model and precision.
+int check_handles(chain_rk4 *const *hs, int count, int model, int prec) {
+    if (!hs || count < 1) return fail(CHAIN_EINVAL, "a batch needs count >= 1 handles");
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i]) return fail(CHAIN_EINVAL, "handle %d is NULL", i);
+        if (hs[i]->d.method != CHAIN_FUSED)
+            return fail(CHAIN_EINVAL, "handle %d does not use the fused method", i);
+        if (hs[i]->d.model != model || hs[i]->d.prec != prec)
+            return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
+    }
+    std::vector<chain_rk4 *> sorted(hs, hs + count);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(CHAIN_EINVAL, "a handle appears twice");
+    return CHAIN_OK;
+}
+
+int check_desc(const chain_rk4_batch_desc *d, Shape *sh) {
+    if (!d) return fail(CHAIN_EINVAL, "batch descriptor is NULL");
+    if (d->max_steps < 0) return fail(CHAIN_EINVAL, "max_steps must be >= 0");
+    if (d->grid_blocks < 0) return fail(CHAIN_EINVAL, "grid_blocks must be >= 0");
+    if ((d->flags & ~CHAIN_BATCH_FENCES) != 0) return fail(CHAIN_EINVAL, "unknown batch flags");
+    if (d->spin_limit < 0) return fail(CHAIN_EINVAL, "spin_limit must be >= 0");
+    if (d->max_chains < 0 || d->max_clusters < 0)
+        return fail(CHAIN_EINVAL, "max_chains and max_clusters must be >= 0");
+    return make_shape(d->sites_per_lane, d->kdepth, sh);
+}
+
+Layout batch_layout(int64_t chains, int64_t clusters, int64_t max_passes) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -100,121 +139,122 @@ Layout batch_layout(int64_t count, int64_t total_clusters, int64_t max_passes) {
         off += round_up(b);
         return o;
     };
-    L.flags = take(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(total_clusters, 1)));
+    const size_t nc = static_cast<size_t>(std::max<int64_t>(clusters, 1));
+    L.flags = take(sizeof(int32_t) * nc);
     L.counter = take(sizeof(unsigned long long));
     L.error = take(sizeof(int32_t));
     L.zero_bytes = off;
     const size_t t0 = off;
-    L.chains = take(sizeof(BatchChain) * static_cast<size_t>(count));
-    L.item_chain = take(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(total_clusters, 1)));
-    L.item_cluster = take(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(total_clusters, 1)));
+    L.chains = take(sizeof(BatchChain) * static_cast<size_t>(chains));
+    L.item_chain = take(sizeof(int32_t) * nc);
+    L.item_cluster = take(sizeof(int32_t) * nc);
     L.pass_off = take(sizeof(int64_t) * static_cast<size_t>(max_passes + 2));
     L.table_bytes = off - t0;
     L.total = off;
     return L;
 }
 
-int check_batch(chain_rk4 *const *hs, int count, const chain_rk4_batch_desc *d, int *sites,
-                int *depth) {
-    if (!hs || count < 1) return fail(CHAIN_EINVAL, "batch needs count >= 1 handles");
-    if (!d) return fail(CHAIN_EINVAL, "batch descriptor is NULL");
-    if (d->max_steps < 0) return fail(CHAIN_EINVAL, "max_steps must be >= 0");
-    if (d->sites_per_lane != 0 && d->sites_per_lane != 4 && d->sites_per_lane != 8 &&
-        d->sites_per_lane != 16)
-        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16");
-    if (d->kdepth != 0 && (d->kdepth < 2 || d->kdepth > 16))
-        return fail(CHAIN_EINVAL, "batch kdepth must be 0 or 2..16");
-    if (d->grid_blocks < 0) return fail(CHAIN_EINVAL, "grid_blocks must be >= 0");
-    if ((d->flags & ~CHAIN_BATCH_FENCES) != 0 || d->reserved != 0)
-        return fail(CHAIN_EINVAL, "unknown batch flags, or reserved is not 0");
-    if (d->spin_limit < 0) return fail(CHAIN_EINVAL, "spin_limit must be >= 0");
-    for (int i = 0; i < count; ++i) {
-        if (!hs[i]) return fail(CHAIN_EINVAL, "handle %d is NULL", i);
-        if (hs[i]->d.method != CHAIN_FUSED)
-            return fail(CHAIN_EINVAL, "handle %d does not use the fused method", i);
-        if (hs[i]->d.model != hs[0]->d.model || hs[i]->d.prec != hs[0]->d.prec)
-            return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
-        for (int j = 0; j < i; ++j)
-            if (hs[j] == hs[i]) return fail(CHAIN_EINVAL, "handle %d appears twice", i);
-    }
-    *sites = d->sites_per_lane ? d->sites_per_lane : kDefaultBatchSites;
-    *depth = d->kdepth ? d->kdepth : kDefaultBatchDepth;
-    const int64_t E = 64 * static_cast<int64_t>(*sites) * kBatchWaves;
-    // every cluster must keep at least `halo` sites (so only neighbouring
-    // clusters overlap) with room to spare for the 4-site rounding
-    while (E < 16 * static_cast<int64_t>(*depth) + 16 && *depth > 2) --*depth;
-    return CHAIN_OK;
+// Capacity a descriptor asks for, given the first handle set.
+void capacity(chain_rk4 *const *hs, int count, const chain_rk4_batch_desc *d, const Shape &sh,
+              int64_t *chains, int64_t *clusters, int64_t *passes) {
+    int64_t need = 0;
+    for (int i = 0; i < count; ++i) need += clusters_of(hs[i]->d.n, sh);
+    *chains = std::max<int64_t>(count, d->max_chains);
+    *clusters = std::max<int64_t>(need, d->max_clusters);
+    *passes = make_passes(d->max_steps, sh.depth).count() + 1;
 }
 
-// Shape of every chain and the table sizes.
-void shape(chain_rk4_batch *b) {
-    const int64_t count = static_cast<int64_t>(b->hs.size());
+}  // namespace
+
+struct chain_rk4_batch {
+    std::vector<chain_rk4 *> hs;
+    chain_rk4_batch_desc d{};
+    int model = 0, prec = 0;
+    Shape sh;
+    int64_t cap_chains = 0, cap_clusters = 0, max_passes = 0;
+    char *ws = nullptr;
+    Layout L{};
+    hipStream_t stream = nullptr;
+    void *staging = nullptr;       // pinned host copy of the tables
+    hipEvent_t staged = nullptr;   // the last table upload has been read
+    bool staged_pending = false;
+    // per chain of the current set
+    std::vector<char> resident;
+    std::vector<int64_t> clusters, uq, ur;
+    int64_t total_clusters = 0;
+};
+
+namespace {
+
+void bind(chain_rk4_batch *b, chain_rk4 *const *hs, int count) {
+    b->hs.assign(hs, hs + count);
     b->resident.assign(count, 0);
     b->clusters.assign(count, 0);
     b->uq.assign(count, 0);
     b->ur.assign(count, 0);
     b->total_clusters = 0;
-    for (int64_t i = 0; i < count; ++i) {
-        const int64_t n = b->hs[i]->d.n;
-        if (n <= batch_resident_max(b->prec)) {
+    for (int i = 0; i < count; ++i) {
+        const int64_t n = hs[i]->d.n;
+        if (n <= kBatchResidentSites) {
             b->resident[i] = 1;
             continue;
         }
-        split_clusters(n, b->tile_max, &b->clusters[i], &b->uq[i], &b->ur[i]);
+        split_clusters(n, b->sh.tile_max, &b->clusters[i], &b->uq[i], &b->ur[i]);
         b->total_clusters += b->clusters[i];
     }
-    b->max_passes = make_passes(b->d.max_steps, b->depth).count() + 1;
 }
 
 }  // namespace
 
 extern "C" {
 
+int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdepth) {
+    Shape sh;
+    if (n < 1 || make_shape(sites_per_lane, kdepth, &sh) != CHAIN_OK) return 0;
+    return clusters_of(n, sh);
+}
+
 size_t chain_rk4_batch_workspace_bytes(chain_rk4 *const *hs, int count,
                                        const chain_rk4_batch_desc *d) {
-    int sites = 0, depth = 0;
-    if (check_batch(hs, count, d, &sites, &depth) != CHAIN_OK) return 0;
-    chain_rk4_batch b;
-    b.hs.assign(hs, hs + count);
-    b.d = *d;
-    b.prec = hs[0]->d.prec;
-    b.sites = sites;
-    b.depth = depth;
-    b.halo = 4 * static_cast<int64_t>(depth);
-    b.tile_max = 64 * static_cast<int64_t>(sites) * kBatchWaves - 2 * b.halo;
-    shape(&b);
-    return batch_layout(count, b.total_clusters, b.max_passes).total;
+    Shape sh;
+    if (check_desc(d, &sh) != CHAIN_OK) return 0;
+    if (!hs || count < 1 || !hs[0]) return 0;
+    if (check_handles(hs, count, hs[0]->d.model, hs[0]->d.prec) != CHAIN_OK) return 0;
+    int64_t chains, clusters, passes;
+    capacity(hs, count, d, sh, &chains, &clusters, &passes);
+    return batch_layout(chains, clusters, passes).total;
 }
 
 int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batch_desc *d,
                            void *workspace, size_t ws_bytes, void *stream, chain_rk4_batch **out) {
     if (!out) return fail(CHAIN_EINVAL, "out is NULL");
     *out = nullptr;
-    int sites = 0, depth = 0;
-    int rc = check_batch(hs, count, d, &sites, &depth);
+    Shape sh;
+    int rc = check_desc(d, &sh);
     if (rc != CHAIN_OK) return rc;
+    if (!hs || count < 1 || !hs[0]) return fail(CHAIN_EINVAL, "a batch needs count >= 1 handles");
+    rc = check_handles(hs, count, hs[0]->d.model, hs[0]->d.prec);
+    if (rc != CHAIN_OK) return rc;
+    int64_t chains, clusters, passes;
+    capacity(hs, count, d, sh, &chains, &clusters, &passes);
+    const Layout L = batch_layout(chains, clusters, passes);
+    if (ws_bytes < L.total)
+        return fail(CHAIN_ENOMEM, "batch workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)))
+        return fail(CHAIN_EINVAL, "batch workspace must be non-NULL and 256-byte aligned");
     chain_rk4_batch *b = new (std::nothrow) chain_rk4_batch();
     if (!b) return fail(CHAIN_ENOMEM, "out of host memory");
-    b->hs.assign(hs, hs + count);
     b->d = *d;
     b->model = hs[0]->d.model;
     b->prec = hs[0]->d.prec;
-    b->sites = sites;
-    b->depth = depth;
-    b->halo = 4 * static_cast<int64_t>(depth);
-    b->tile_max = 64 * static_cast<int64_t>(sites) * kBatchWaves - 2 * b->halo;
-    shape(b);
-    b->L = batch_layout(count, b->total_clusters, b->max_passes);
-    if (ws_bytes < b->L.total) {
-        delete b;
-        return fail(CHAIN_ENOMEM, "batch workspace has %zu bytes, needs %zu", ws_bytes, b->L.total);
-    }
-    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1))) {
-        delete b;
-        return fail(CHAIN_EINVAL, "batch workspace must be non-NULL and 256-byte aligned");
-    }
+    b->sh = sh;
+    b->cap_chains = chains;
+    b->cap_clusters = clusters;
+    b->max_passes = passes;
+    b->L = L;
     b->ws = static_cast<char *>(workspace);
     b->stream = static_cast<hipStream_t>(stream);
+    bind(b, hs, count);
     hipError_t e = hipHostMalloc(&b->staging, b->L.table_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -222,6 +262,22 @@ int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batc
         return hip_fail(e, "batch staging buffer");
     }
     *out = b;
+    return CHAIN_OK;
+}
+
+int chain_rk4_batch_rebind(chain_rk4_batch *b, chain_rk4 *const *hs, int count) {
+    if (!b) return fail(CHAIN_EINVAL, "batch is NULL");
+    int rc = check_handles(hs, count, b->model, b->prec);
+    if (rc != CHAIN_OK) return rc;
+    if (count > b->cap_chains)
+        return fail(CHAIN_ENOMEM, "%d chains exceed the batch capacity of %lld", count,
+                    (long long)b->cap_chains);
+    int64_t need = 0;
+    for (int i = 0; i < count; ++i) need += clusters_of(hs[i]->d.n, b->sh);
+    if (need > b->cap_clusters)
+        return fail(CHAIN_ENOMEM, "%lld clusters exceed the batch capacity of %lld",
+                    (long long)need, (long long)b->cap_clusters);
+    bind(b, hs, count);
     return CHAIN_OK;
 }
 
@@ -243,7 +299,7 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
         if (b->resident[i]) {
             res.push_back(i);
         } else {
-            passes[i] = make_passes(nsteps[i], b->depth);
+            passes[i] = make_passes(nsteps[i], b->sh.depth);
             tiled.push_back(i);
         }
     }
@@ -325,17 +381,17 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
     a.counter = reinterpret_cast<unsigned long long *>(b->ws + b->L.counter);
     a.error = reinterpret_cast<int32_t *>(b->ws + b->L.error);
     a.total_items = total_items;
-    a.halo = b->halo;
+    a.halo = b->sh.halo;
     a.n_resident = static_cast<int32_t>(res.size());
     a.n_tiled = static_cast<int32_t>(n_tiled);
     a.max_passes = static_cast<int32_t>(max_p);
-    a.depth = b->depth;
+    a.depth = b->sh.depth;
     a.spin_limit = b->d.spin_limit ? b->d.spin_limit : kSpinLimit;
     a.fences = (b->d.flags & CHAIN_BATCH_FENCES) ? 1 : 0;
 
     int blocks = b->d.grid_blocks;
     if (blocks == 0) {
-        blocks = persistent_capacity(b->model, b->prec, b->sites);
+        blocks = persistent_capacity(b->model, b->prec, b->sh.sites);
         if (blocks <= 0) return fail(CHAIN_EHIP, "occupancy query failed");
     }
     if (blocks > total_items) blocks = static_cast<int>(total_items);
@@ -346,7 +402,7 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
                            b->stream));
     HIP_TRY(hipEventRecord(b->staged, b->stream));
     b->staged_pending = true;
-    e = launch_persistent(b->model, b->prec, b->sites, blocks, a, b->stream);
+    e = launch_persistent(b->model, b->prec, b->sh.sites, blocks, a, b->stream);
     if (e != hipSuccess) return hip_fail(e, "persistent launch");
     // a tiled chain with a single one-step pass ends in its back buffer
     for (int64_t i : tiled) {
@@ -392,12 +448,12 @@ int chain_rk4_batch_energy(chain_rk4_batch *b, double *e_out) {
 int chain_rk4_batch_get_plan(const chain_rk4_batch *b, chain_rk4_batch_plan *out) {
     if (!b || !out) return fail(CHAIN_EINVAL, "batch and out must be non-NULL");
     chain_rk4_batch_plan P{};
-    P.sites_per_lane = b->sites;
-    P.kdepth = b->depth;
+    P.sites_per_lane = b->sh.sites;
+    P.kdepth = b->sh.depth;
     P.waves_per_cluster = kBatchWaves;
-    P.grid_blocks = b->d.grid_blocks ? b->d.grid_blocks : persistent_capacity(b->model, b->prec, b->sites);
-    P.halo = b->halo;
-    P.tile_max = b->tile_max;
+    P.grid_blocks = b->d.grid_blocks ? b->d.grid_blocks : persistent_capacity(b->model, b->prec, b->sh.sites);
+    P.halo = b->sh.halo;
+    P.tile_max = b->sh.tile_max;
     P.total_clusters = b->total_clusters;
     int64_t nres = 0;
     for (char r : b->resident) nres += r;

@@ -104,7 +104,7 @@ def test_oracle_is_not_linked_into_the_product():
 
 def test_batch_calls_reject_bad_arguments_without_a_gpu():
     lib = L.lib()
-    d = L.BatchDesc(10, 0, 0, 0, 0, 0, 0)
+    d = L.BatchDesc(10, 0, 0, 0, 0, 0, 0, 0)
     assert lib.chain_rk4_batch_workspace_bytes(None, 1, ctypes.byref(d)) == 0
     hs = (L.H * 1)(None)
     assert lib.chain_rk4_batch_workspace_bytes(hs, 1, ctypes.byref(d)) == 0
@@ -117,3 +117,13 @@ def test_batch_calls_reject_bad_arguments_without_a_gpu():
     assert lib.chain_rk4_batch_check(None) == L.CHAIN_EINVAL
     assert lib.chain_rk4_batch_destroy(None) == L.CHAIN_OK
     assert lib.chain_rk4_strerror(L.CHAIN_ETIMEOUT) != b"unknown status"
+
+
+def test_batch_cluster_count_helper():
+    lib = L.lib()
+    assert lib.chain_rk4_batch_clusters(1000, 0, 0) == 0        # kept on chip
+    assert lib.chain_rk4_batch_clusters(1025, 0, 0) == 1
+    # default shape: 2048-site clusters keeping at most 2048 - 96 sites
+    assert lib.chain_rk4_batch_clusters(1 << 24, 0, 0) == -(-(1 << 24) // (2048 - 96 - 4))
+    assert lib.chain_rk4_batch_clusters(100, 5, 0) == 0          # invalid shape
+    assert lib.chain_rk4_batch_rebind(None, None, 0) == L.CHAIN_EINVAL

@@ -1,0 +1,98 @@
+"""The serving policy on a simulated clock (no GPU): admission under the HBM
+budget and slot limit, strict arrival order, rejection, cancellation, and
+latency accounting."""
+import math
+
+import pytest
+
+import workloads
+from paper_1412_0544_amd.serve import (Server, SimExecutor, footprint_bytes, percentiles)
+from workloads import Job
+
+
+def jobs_small(count=40, rate=50.0, seed=3):
+    return workloads.served_jobs(count, rate, seed=seed, n_lo=1000, n_hi=200_000,
+                                 steps_lo=100, steps_hi=5000)
+
+
+def test_all_jobs_complete_with_their_steps():
+    jobs = jobs_small()
+    ex = SimExecutor(rate=1e9)
+    srv = Server(ex, hbm_budget=64 << 20, max_active=8, quantum=700)
+    res = srv.run(jobs)
+    for j, r in zip(jobs, res):
+        assert r.status == "done"
+        assert r.energy == j.steps          # the simulated executor reports steps run
+        assert r.finished >= r.admitted >= r.arrival
+        assert r.latency > 0
+    assert not ex.slots                      # everything released
+
+
+def test_budget_and_slots_are_never_exceeded():
+    jobs = jobs_small(80, rate=500.0)
+    ex = SimExecutor(rate=5e8)
+    budget = 20 << 20
+    srv = Server(ex, hbm_budget=budget, max_active=5, quantum=300)
+    srv.run(jobs)
+    assert srv.peak_used <= budget
+    assert ex.max_concurrent <= 5
+    assert srv.used == 0
+
+
+def test_admission_is_in_arrival_order():
+    jobs = jobs_small(60, rate=1000.0)
+    srv = Server(SimExecutor(rate=2e8), hbm_budget=16 << 20, max_active=4, quantum=500)
+    srv.run(jobs)
+    order = sorted(jobs, key=lambda j: (j.arrival, j.jid))
+    assert srv.admission_log == [j.jid for j in order]
+
+
+def test_head_of_line_is_not_overtaken():
+    """A large job waiting for memory at the head of the queue is not
+    overtaken by small jobs that would fit (no starvation)."""
+    blocker = Job(1, 0.0, 300_000, 3000, 0, 0, 2)
+    big = Job(0, 0.0005, 400_000, 200, 0, 0, 1)
+    small = [Job(2 + i, 0.001 * (i + 1), 1000, 100, 0, 0, 3 + i) for i in range(5)]
+    budget = footprint_bytes(400_000, 0) + footprint_bytes(1000, 0) * 2
+    srv = Server(SimExecutor(rate=1e9), hbm_budget=budget, max_active=8, quantum=100)
+    res = srv.run([blocker, big] + small)
+    assert srv.admission_log == [1, 0, 2, 3, 4, 5, 6]
+    assert all(r.status == "done" for r in res)
+    # the small jobs waited behind the big one
+    assert all(r.admitted >= res[1].admitted for r in res[2:])
+
+
+def test_oversized_job_is_rejected():
+    jobs = [Job(0, 0.0, 10_000_000, 100, 0, 0, 1), Job(1, 0.0, 1000, 100, 0, 0, 2)]
+    srv = Server(SimExecutor(), hbm_budget=1 << 20, max_active=4, quantum=100)
+    res = srv.run(jobs)
+    assert res[0].status == "rejected" and res[1].status == "done"
+
+
+def test_cancel_queued_and_running_jobs():
+    jobs = [Job(i, 0.0, 100_000, 20_000, 0, 0, i) for i in range(4)]
+    ex = SimExecutor(rate=1e9)
+    srv = Server(ex, hbm_budget=footprint_bytes(100_000, 0) * 2, max_active=2, quantum=1000)
+    srv.cancel(0)   # will be running
+    srv.cancel(3)   # still queued when it reaches the head
+    res = srv.run(jobs)
+    assert res[0].status == "cancelled" and res[3].status == "cancelled"
+    assert res[1].status == "done" and res[2].status == "done"
+    assert not ex.slots and srv.used == 0
+
+
+def test_throughput_and_percentiles():
+    jobs = jobs_small(50, rate=20.0)
+    ex = SimExecutor(rate=1e9, overhead=0.0)
+    res = Server(ex, hbm_budget=1 << 30, max_active=64, quantum=1000).run(jobs)
+    makespan = max(r.finished for r in res) - min(r.arrival for r in res)
+    su = sum(r.n * r.steps for r in res)
+    assert su / makespan <= 1e9 * (1 + 1e-9)
+    p = percentiles([r.latency for r in res])
+    assert 0 < p["p50"] <= p["p99"]
+    assert math.isnan(percentiles([])["p50"] or math.nan)
+
+
+def test_bad_configuration():
+    with pytest.raises(ValueError):
+        Server(SimExecutor(), hbm_budget=0)

@@ -66,6 +66,37 @@ def chain_ics(n: int, seed: int = 0, dtype=np.float64):
     return q, p
 
 
+def _as_i64(x: int) -> int:
+    x &= 0xFFFFFFFFFFFFFFFF
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def chain_ics_torch(n: int, seed: int, device, dtype=None):
+    """Same values as ``chain_ics``, generated with torch on ``device``.
+
+    The 64-bit arithmetic runs in int64 (wrapping multiply; logical shifts by
+    masking the sign-extended arithmetic shift).
+    """
+    import torch
+
+    dtype = dtype or torch.float64
+    i = torch.arange(n, device=device, dtype=torch.int64)
+
+    def lsr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    def draw(j):
+        z = _as_i64(seed) + (j + 1) * _as_i64(0x9E3779B97F4A7C15)
+        z = (z ^ lsr(z, 30)) * _as_i64(0xBF58476D1CE4E5B9)
+        z = (z ^ lsr(z, 27)) * _as_i64(0x94D049BB133111EB)
+        z = z ^ lsr(z, 31)
+        return lsr(z, 11).to(torch.float64) * _TWO_M53
+
+    q = 2.0 * draw(2 * i) - 1.0
+    p = 2.0 * draw(2 * i + 1) - 1.0
+    return q.to(dtype), p.to(dtype)
+
+
 def mode_ics(n: int, kind: str, amp: float = 0.5, mode: int = 1):
     """Structured initial conditions with closed-form solutions.
 
