@@ -41,6 +41,27 @@ FLOPS_PER_SU = {"quartic": 58, "harmonic": 42}
 BYTES_PER_SITE_PASS = {"fp64": 32, "fp32_kahan": 32}   # FP32: q, p, cq, cp
 
 
+# HBM bytes per fused pass from two rocprofv3 counter runs (FETCH_SIZE and
+# WRITE_SIZE, each scaled by what it reads for a 512 MiB device copy), for
+# the kernel sources with this sha256 and this cluster shape (sites per lane,
+# wavefronts per cluster, halo) on N = 2^24.
+MEASURED_TRAFFIC = {
+    "sha256": "0d6fffeca6428126d0a45004a2d454ebc188261f02009dfb017c3269baeaf8a5",
+    "shape": (8, 4, 48), "n": 1 << 24,
+    "bytes_per_launch": 550842811, "fetch_factor": 0.5000, "write_factor": 1.0000,
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1412_0544_amd", "csrc")
+    for name in sorted(("fused.hip", "cluster.hpp", "rk4_device.hpp", "launch.hpp")):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -140,7 +161,11 @@ def main(argv=None):
     ap.add_argument("--sites", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--kdepth", type=int, default=0)
-    ap.add_argument("--sweep", action="store_true", help="time the full (S, W, k) grid")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the cluster shape with the autotuner (default: the library plan)")
+    ap.add_argument("--sweep", action="store_true", help="autotune over the full (S, W, k) grid")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with device copies of known size (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
@@ -168,7 +193,7 @@ def main(argv=None):
     sweep = {}
     if args.sites and args.waves and args.kdepth:
         S, W, K = args.sites, args.waves, args.kdepth
-    else:
+    elif args.autotune or args.sweep:
         cands = None
         if args.sweep:
             cands = [(s, w, k) for s in autotune.SITES for w in autotune.WAVES
@@ -177,6 +202,9 @@ def main(argv=None):
         (S, W, K), table = autotune.tune(n, q=qd, p=pd, dt=dt, candidates=cands, device=dev,
                                         use_cache=False)
         sweep = {f"s{s}_w{w}_k{k}": v for (s, w, k), v in sorted(table.items())}
+    else:
+        probe = Chain(qd[:1 << 16], pd[:1 << 16], dt, resident=False, device=dev).plan()
+        S, W, K = probe["sites_per_lane"], probe["waves_per_cluster"], probe["kdepth"]
     log(f"[bench] plan S={S} W={W} K={K}")
 
     ch = Chain(qd, pd, dt, sites_per_lane=S, waves_per_cluster=W, kdepth=K, resident=False,
@@ -194,6 +222,11 @@ def main(argv=None):
     rl = roofline(n, js / launches, t_launch)
     rl["launches_per_job"] = launches
     rl["traffic"] = None
+    mt = MEASURED_TRAFFIC
+    if (kernel_sources_sha256() == mt["sha256"] and (S, W, plan["halo"]) == mt["shape"]
+            and n == mt["n"]):
+        rl["traffic"] = mt["bytes_per_launch"]
+        rl["traffic_vs_algorithmic"] = mt["bytes_per_launch"] / rl["algorithmic_per_launch"]["bytes"]
 
     out = {
         "metric": "site-updates/sec (RK4 steps x N / s) + % HBM roofline; p50/p99 job latency",
@@ -223,6 +256,15 @@ def main(argv=None):
 
     if not args.no_variants:
         out["variants"] = variants(qd, pd, dt, n, dev, (S, W), serve_jobs=args.serve_jobs)
+
+    if args.copy_probe:
+        # plain device copies of known size, for scaling the HBM byte counters
+        src = torch.empty(1 << 26, dtype=torch.float64, device=dev)   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 8
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
