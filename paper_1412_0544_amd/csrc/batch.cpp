@@ -20,8 +20,8 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-constexpr int kDefaultBatchSites = 8;
-constexpr int kDefaultBatchDepth = 12;
+constexpr int kDefaultBatchSites = 4;
+constexpr int kDefaultBatchDepth = 16;
 constexpr int kSpinLimit = 1 << 22;  // polls (each with a short sleep) before a wait gives up
 
 // Per-chain pass list of a launch: `head` passes first (0 or 2 entries), then

@@ -62,7 +62,7 @@ size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kDefaultSitesFp64 = 8;
 constexpr int kDefaultSitesFp32 = 16;
 constexpr int kDefaultWaves = 4;
-constexpr int kDefaultDepth = 12;
+constexpr int kDefaultDepth = 16;
 constexpr int kMaxDepth = 16;
 
 bool valid_sites(int s) { return s == 4 || s == 8 || s == 16; }

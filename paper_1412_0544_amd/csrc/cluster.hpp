@@ -115,14 +115,27 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
     const R *qin = static_cast<const R *>(in.q);
     const R *pin = static_cast<const R *>(in.p);
     if constexpr (COH) {
+        if (contiguous) {
+            const R *qb = qin + s0, *pb = pin + s0;
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int64_t i = contiguous ? s0 + j : wrap_index(s0 + j, n);
-            st.q[j] = load_coherent(qin + i);
-            st.p[j] = load_coherent(pin + i);
-            if constexpr (KAHAN) {
-                st.cq[j] = load_coherent(in.cq + i);
-                st.cp[j] = load_coherent(in.cp + i);
+            for (int j = 0; j < S; ++j) {
+                st.q[j] = load_coherent(qb + j);
+                st.p[j] = load_coherent(pb + j);
+                if constexpr (KAHAN) {
+                    st.cq[j] = load_coherent(in.cq + s0 + j);
+                    st.cp[j] = load_coherent(in.cp + s0 + j);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const int64_t i = wrap_index(s0 + j, n);
+                st.q[j] = load_coherent(qin + i);
+                st.p[j] = load_coherent(pin + i);
+                if constexpr (KAHAN) {
+                    st.cq[j] = load_coherent(in.cq + i);
+                    st.cp[j] = load_coherent(in.cp + i);
+                }
             }
         }
     } else if (contiguous) {
@@ -156,16 +169,16 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
     R *qout = static_cast<R *>(out.q);
     R *pout = static_cast<R *>(out.p);
     if constexpr (COH) {
+        R *qb = qout + s0, *pb = pout + s0;
+        const bool all = lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n;
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            const int local = lo + j;
-            const int64_t g = s0 + j;
-            if (local >= keep_lo && local < keep_hi && g < n) {
-                store_coherent(qout + g, st.q[j]);
-                store_coherent(pout + g, st.p[j]);
+            if (all || (lo + j >= keep_lo && lo + j < keep_hi && s0 + j < n)) {
+                store_coherent(qb + j, st.q[j]);
+                store_coherent(pb + j, st.p[j]);
                 if constexpr (KAHAN) {
-                    store_coherent(out.cq + g, st.cq[j]);
-                    store_coherent(out.cp + g, st.cp[j]);
+                    store_coherent(out.cq + s0 + j, st.cq[j]);
+                    store_coherent(out.cp + s0 + j, st.cp[j]);
                 }
             }
         }

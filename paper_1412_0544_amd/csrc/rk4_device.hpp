@@ -11,7 +11,8 @@
 //
 // One RK4 step (Sec. 2.2 Eq. 3-5, classical tableau) per site, h = dt:
 //   stage j evaluates F at the stage argument (Q, P); k_j = (P, F)
-//   acc = k1 + 2 k2 + 2 k3 + k4, accumulated in that order
+//   acc = k1 + 2 k2 + 2 k3 + k4, accumulated in that order (the q part of
+//   k1 is p, so its accumulation starts as fma(2, P2, p) in stage 2)
 //   stage arguments: (Q, P) = (q, p) + a_j h k_j with a = (1/2, 1/2, 1)
 //   final: y = y + (h/6) acc   (FP64: one fma; FP32: Kahan-compensated)
 // Operation order is fixed here; kernels call these helpers only.
@@ -77,9 +78,11 @@ __device__ __forceinline__ void kahan_add(float &y, float &c, float delta) {
 
 // ---------------------------------------------------------------------------
 // Wavefront neighbour exchange (wave64, DPP). from_right(x): lane i receives
-// lane i+1's x; lane 63 keeps its own. from_left(x): lane i receives lane
-// i-1's x; lane 0 keeps its own. The kernels only use the edge lanes' results
-// inside the recomputed halo, so what those lanes keep never reaches output.
+// lane i+1's x; lane 63 receives 0. from_left(x): lane i receives lane i-1's
+// x; lane 0 receives 0. The kernels only use those edge lanes' results inside
+// the recomputed halo (or replace them from LDS), so the zeros never reach
+// output; filling with zero lets the move write a fresh register instead of
+// first copying the source.
 // ---------------------------------------------------------------------------
 constexpr int kDppWaveShl1 = 0x130;  // wave_shl:1
 constexpr int kDppWaveShr1 = 0x138;  // wave_shr:1
@@ -88,7 +91,7 @@ constexpr int kDppWaveRor1 = 0x13C;  // wave_ror:1
 
 template <int Ctrl>
 __device__ __forceinline__ int dpp32(int x) {
-    return __builtin_amdgcn_update_dpp(x, x, Ctrl, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, Ctrl, 0xF, 0xF, true);
 }
 
 template <int Ctrl>
@@ -141,12 +144,12 @@ __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (
         const R F = site_force<M, R>(bl, br, Qj);
         bl = br;
         if (STAGE == 1) {
-            aq[j] = Pj;
+            // k1 = (p, F): its q part is p itself, folded into stage 2
             ap[j] = F;
             Q[j] = fma_r(c.hh, Pj, q[j]);
             P[j] = fma_r(c.hh, F, p[j]);
         } else if (STAGE == 2) {
-            aq[j] = fma_r(static_cast<R>(2), Pj, aq[j]);
+            aq[j] = fma_r(static_cast<R>(2), Pj, p[j]);
             ap[j] = fma_r(static_cast<R>(2), F, ap[j]);
             Q[j] = fma_r(c.hh, Pj, q[j]);
             P[j] = fma_r(c.hh, F, p[j]);
@@ -193,10 +196,10 @@ __device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R 
     const R br = ModelOps<M, R>::bond(Qp - Qj);
     const R F = site_force<M, R>(bl, br, Qj);
     if (STAGE == 1) {
-        aq = Pj; ap = F;
+        ap = F;
         Qn = fma_r(c.hh, Pj, qj); Pn = fma_r(c.hh, F, pj);
     } else if (STAGE == 2) {
-        aq = fma_r(static_cast<R>(2), Pj, aq);
+        aq = fma_r(static_cast<R>(2), Pj, pj);
         ap = fma_r(static_cast<R>(2), F, ap);
         Qn = fma_r(c.hh, Pj, qj); Pn = fma_r(c.hh, F, pj);
     } else if (STAGE == 3) {

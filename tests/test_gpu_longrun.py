@@ -1,0 +1,108 @@
+"""Long runs, checkpoints and the FP32 drift bound, through the C ABI.
+
+Chaotic trajectories decorrelate from the oracle's after some time units
+(rounding differences grow exponentially), so long runs are compared by
+statistics: relative energy drift (final value and the slope of a line fit)
+and the time average of p^2, which must agree within their sampling errors.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1412_0544_amd import Chain
+
+pytestmark = pytest.mark.gpu
+
+
+def drift_series(run_chunk, e0, chunks):
+    out = []
+    for _ in range(chunks):
+        e = run_chunk()
+        out.append((e - e0) / e0)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_long_chaotic_run_statistics_match_oracle(seed):
+    n, dt, chunk, chunks = 1024, 0.01, 1000, 100          # 1e5 steps
+    q0, p0 = workloads.chain_ics(n, seed)
+    e0 = oracle.energy(oracle.QUARTIC, q0, p0)
+
+    ch = Chain(q0, p0, dt)
+    p2_gpu = []
+
+    def gpu_chunk():
+        ch.step(chunk)
+        p2_gpu.append(float((ch.p.double() ** 2).mean()))
+        return ch.energy()
+
+    d_gpu = drift_series(gpu_chunk, e0, chunks)
+    ch.close()
+
+    state = [q0, p0]
+    p2_cpu = []
+
+    def cpu_chunk():
+        state[0], state[1] = oracle.rk4(oracle.QUARTIC, state[0], state[1], dt, chunk)
+        p2_cpu.append(float((state[1] ** 2).mean()))
+        return oracle.energy(oracle.QUARTIC, state[0], state[1])
+
+    d_cpu = drift_series(cpu_chunk, e0, chunks)
+
+    # drift: same sign and size within a factor 2, same slope within a factor 2
+    t = np.arange(1, chunks + 1)
+    s_gpu = np.polyfit(t, d_gpu, 1)[0]
+    s_cpu = np.polyfit(t, d_cpu, 1)[0]
+    assert 0.5 < d_gpu[-1] / d_cpu[-1] < 2.0, (d_gpu[-1], d_cpu[-1])
+    assert 0.5 < s_gpu / s_cpu < 2.0, (s_gpu, s_cpu)
+    assert abs(d_gpu[-1]) < 1e-5
+    # the first chunk is still the same trajectory to rounding level
+    assert abs(d_gpu[0] - d_cpu[0]) < 1e-12
+    # time-averaged <p^2> (equipartition-like observable) within 3 standard errors
+    a, b = np.array(p2_gpu[10:]), np.array(p2_cpu[10:])
+    se = np.sqrt(a.var(ddof=1) / a.size + b.var(ddof=1) / b.size)
+    assert abs(a.mean() - b.mean()) < 3 * se + 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_checkpoint_and_resume_bitwise(prec):
+    n = 50_000
+    dtype = np.float64 if prec == "fp64" else np.float32
+    q0, p0 = workloads.chain_ics(n, 21, dtype=dtype)
+    full = Chain(q0, p0, 0.01, prec=prec)
+    full.step(100)
+    first = Chain(q0, p0, 0.01, prec=prec)
+    first.step(50)
+    cq, cp = first.carry_tensors()
+    saved = [t.clone() for t in (first.q, first.p) + ((cq, cp) if cq is not None else ())]
+    first.close()
+    resumed = Chain(saved[0], saved[1], 0.01, prec=prec)
+    if prec != "fp64":
+        rq, rp = resumed.carry_tensors()
+        rq.copy_(saved[2])
+        rp.copy_(saved[3])
+    resumed.step(50)
+    torch.cuda.synchronize()
+    assert torch.equal(resumed.q, full.q) and torch.equal(resumed.p, full.p)
+    if prec != "fp64":
+        fq, fp = full.carry_tensors()
+        rq, rp = resumed.carry_tensors()
+        assert torch.equal(rq, fq) and torch.equal(rp, fp)
+
+
+def test_fp32_kahan_energy_drift_bound():
+    """10^4 steps of the same chain in FP32 with compensated update and in
+    FP64: the relative energy drifts differ by less than 1e-6."""
+    n, dt, steps = 1 << 20, 0.01, 10_000
+    q, p = workloads.chain_ics_torch(n, 3, "cuda", torch.float32)
+    drifts = {}
+    for prec, qq, pp in (("fp64", q.double(), p.double()), ("fp32_kahan", q, p)):
+        ch = Chain(qq, pp, dt, prec=prec)
+        e0 = ch.energy()
+        ch.step(steps)
+        drifts[prec] = (ch.energy() - e0) / e0
+        ch.close()
+    assert abs(drifts["fp64"]) < 1e-6
+    assert abs(drifts["fp32_kahan"] - drifts["fp64"]) < 1e-6, drifts
