@@ -169,6 +169,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="only sweep N = 2^10..2^26, fused vs per-stage, T = 50, best of 10")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -183,6 +185,12 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.size_sweep:
+        print(json.dumps({"metric": "site-updates/sec vs chain length", "unit": "site-updates/s",
+                          "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+                          "config": {"workload": "quartic chain, dt=0.01, T=50 steps, best of 10"},
+                          "size_sweep": size_sweep(dev)}), flush=True)
+        return 0
     n, dt, js = args.n, 0.01, args.job_steps
     log(f"[bench] generating ICs n={n}")
     q0, p0 = workloads.chain_ics(n, 0)
@@ -400,6 +408,36 @@ def variant_serving(dt, dev, jobs=60, rho=0.8, rate_su=4e11, budget=4 << 30, qua
             "service_s": percentiles([r.service_s for r in done]),
             "jobs_per_s": len(done) / wall, "su_per_s": su / wall, "wall_s": wall,
             "rounds": srv.rounds, "peak_hbm_bytes": srv.peak_used}
+
+
+def size_sweep(dev, dt=0.01, steps=50, trials=10, exps=range(10, 27, 2)):
+    """Fused (library plan) vs the per-stage baseline over chain length, with
+    the paper's protocol: T steps from random initial conditions, the best
+    of M trials, Perf = T / t_wall (Sec. 3.2, Eq. 8)."""
+    import torch
+    import workloads
+    from paper_1412_0544_amd import Chain
+    rows = []
+    for e in exps:
+        n = 1 << e
+        q, p = workloads.chain_ics_torch(n, 0, dev)
+        row = {"n": n, "state_bytes": 16 * n}
+        for method in ("fused", "naive"):
+            ch = Chain(q, p, dt, method=method, device=dev)
+            ch.step(steps)
+            best = min(ev_seconds(lambda: ch.step(steps), ch.stream) for _ in range(trials))
+            row[method] = {"su_per_s": n * steps / best, "steps_per_s": steps / best,
+                           "plan": {k: v for k, v in ch.plan().items()
+                                    if k in ("resident", "sites_per_lane", "waves_per_cluster",
+                                             "kdepth")}}
+            ch.close()
+        row["speedup"] = row["fused"]["su_per_s"] / row["naive"]["su_per_s"]
+        log(f"[bench] N=2^{e}: fused {row['fused']['su_per_s']:.3e}, naive "
+            f"{row['naive']['su_per_s']:.3e}, x{row['speedup']:.1f}")
+        rows.append(row)
+        del q, p
+        torch.cuda.empty_cache()
+    return rows
 
 
 def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):

@@ -5,7 +5,8 @@ CPU-baseline leg are the only callers. Nothing here is shared with the GPU
 library. The arithmetic lives in ``chain_oracle.c`` (plain C, FP64, no FMA);
 this module only marshals numpy arrays into it.
 
-Model ids: 0 = quartic chain, 1 = harmonic chain (see ``chain_oracle.c``).
+Model ids: 0 = quartic chain, 1 = harmonic chain (see ``chain_oracle.c``); the
+Roessler chain (three coordinates per site) has its own calls.
 """
 from __future__ import annotations
 
@@ -24,6 +25,8 @@ _LIB_OVERRIDE = os.environ.get("CHAIN_ORACLE_LIB")
 
 QUARTIC = 0
 HARMONIC = 1
+# The paper's Roessler parameters (Sec. 3.1): a = 0.2, b = 1, c = 9.
+ROESSLER_ABC = (0.2, 1.0, 9.0)
 
 
 def build(force: bool = True, src: str = SRC, out: str = LIB) -> str:
@@ -56,6 +59,12 @@ def _load():
         lib.oracle_rk4_run.restype = ctypes.c_int
         lib.oracle_energy.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp]
         lib.oracle_energy.restype = ctypes.c_double
+        d = ctypes.c_double
+        lib.oracle_roessler_rhs.argtypes = [ctypes.c_int64, dp, dp, dp, d, d, d, dp, dp, dp]
+        lib.oracle_roessler_rhs.restype = None
+        lib.oracle_roessler_run.argtypes = [ctypes.c_int64, d, ctypes.c_int64, dp, dp, dp, d, d, d,
+                                            ctypes.c_int]
+        lib.oracle_roessler_run.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -123,3 +132,41 @@ def rk4_sites(model: int, q, p, dt: float, steps: int, sites, threads: int = 1):
         oq[k] = qw[r]
         op[k] = pw[r]
     return oq, op
+
+
+def roessler_rhs(x, y, z, abc=ROESSLER_ABC):
+    """(dx/dt, dy/dt, dz/dt) of the Roessler chain."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    kx, ky, kz = np.empty_like(x), np.empty_like(x), np.empty_like(x)
+    _load().oracle_roessler_rhs(x.size, _ptr(x), _ptr(y), _ptr(z), *abc, _ptr(kx), _ptr(ky), _ptr(kz))
+    return kx, ky, kz
+
+
+def roessler_rk4(x, y, z, dt: float, steps: int, abc=ROESSLER_ABC, threads: int = 1):
+    """Return (x, y, z) after ``steps`` RK4 steps of the Roessler chain."""
+    x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
+    if not (x.shape == y.shape == z.shape) or x.ndim != 1:
+        raise ValueError("x, y, z must be 1-D arrays of one length")
+    rc = _load().oracle_roessler_run(x.size, float(dt), int(steps), _ptr(x), _ptr(y), _ptr(z),
+                                     *abc, int(threads))
+    if rc != 0:
+        raise MemoryError("oracle_roessler_run failed")
+    return x, y, z
+
+
+def roessler_rk4_sites(x, y, z, dt: float, steps: int, sites, abc=ROESSLER_ABC, threads: int = 1):
+    """Final (x, y, z) of selected sites, each from its own light cone of
+    2 * 4 * steps + 1 sites (see rk4_sites)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    r = 4 * int(steps)
+    sites = np.asarray(sites, dtype=np.int64)
+    if 2 * r + 1 >= n:
+        a, b, c = roessler_rk4(x, y, z, dt, steps, abc, threads)
+        return a[sites], b[sites], c[sites]
+    out = np.empty((3, sites.size))
+    for k, i in enumerate(sites):
+        idx = np.arange(i - r, i + r + 1) % n
+        a, b, c = roessler_rk4(x[idx], y[idx], z[idx], dt, steps, abc, threads)
+        out[:, k] = a[r], b[r], c[r]
+    return out[0], out[1], out[2]

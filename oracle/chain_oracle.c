@@ -18,6 +18,12 @@
  *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
  * Periodic boundary (Sec. 3.1): site 0's left neighbour is site N-1 and site
  * N-1's right neighbour is site 0, for every N >= 1.
+ *
+ * Roessler chain (Sec. 3.1 Eq. 6-7), three coordinates per site:
+ *   dx_i/dt = -y_i - z_i + (x_{i-1} - 2 x_i + x_{i+1})
+ *   dy_i/dt = x_i + a y_i
+ *   dz_i/dt = b + z_i (x_i - c)
+ * with the paper's a = 0.2, b = 1, c = 9 passed in by the caller.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -143,4 +149,84 @@ double oracle_energy(int model, int64_t n, const double *q, const double *p)
         sum = t;
     }
     return sum + comp;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Roessler chain                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Eq. 3 for the Roessler chain: local term (Eq. 6) plus coupling (Eq. 7). */
+static void roessler_rhs(int64_t n, const double *x, const double *y, const double *z,
+                         double a, double b, double c, double *kx, double *ky, double *kz,
+                         int threads)
+{
+    int64_t i;
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (i = 0; i < n; ++i) {
+        double xm = x[left_of(i, n)], xp = x[right_of(i, n)];
+        kx[i] = -y[i] - z[i] + (xm - 2.0 * x[i] + xp);
+        ky[i] = x[i] + a * y[i];
+        kz[i] = b + z[i] * (x[i] - c);
+    }
+}
+
+/* Public: the Roessler right-hand side over the whole chain. */
+void oracle_roessler_rhs(int64_t n, const double *x, const double *y, const double *z,
+                         double a, double b, double c, double *kx, double *ky, double *kz)
+{
+    roessler_rhs(n, x, y, z, a, b, c, kx, ky, kz, 1);
+}
+
+/* Eq. 4 for three components. */
+static void intermediate3(int64_t n, const double *x, const double *y, const double *z,
+                          double a_dt, const double *kx, const double *ky, const double *kz,
+                          double *X, double *Y, double *Z, int threads)
+{
+    int64_t i;
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (i = 0; i < n; ++i) {
+        X[i] = x[i] + a_dt * kx[i];
+        Y[i] = y[i] + a_dt * ky[i];
+        Z[i] = z[i] + a_dt * kz[i];
+    }
+}
+
+/* Public: advance (x, y, z) in place by `steps` classical RK4 steps. */
+int oracle_roessler_run(int64_t n, double dt, int64_t steps, double *x, double *y, double *z,
+                        double a, double b, double c, int threads)
+{
+    double *buf, *k[4][3], *X, *Y, *Z;
+    int64_t s, i;
+    int j, m;
+    if (n < 1 || steps < 0)
+        return -1;
+    if (threads < 1)
+        threads = 1;
+    buf = (double *)malloc(sizeof(double) * (size_t)n * 15);
+    if (!buf)
+        return -1;
+    for (j = 0; j < 4; ++j)
+        for (m = 0; m < 3; ++m)
+            k[j][m] = buf + (size_t)n * (size_t)(3 * j + m);
+    X = buf + 12 * n;
+    Y = buf + 13 * n;
+    Z = buf + 14 * n;
+
+    for (s = 0; s < steps; ++s) {
+        roessler_rhs(n, x, y, z, a, b, c, k[0][0], k[0][1], k[0][2], threads);
+        intermediate3(n, x, y, z, dt / 2.0, k[0][0], k[0][1], k[0][2], X, Y, Z, threads);
+        roessler_rhs(n, X, Y, Z, a, b, c, k[1][0], k[1][1], k[1][2], threads);
+        intermediate3(n, x, y, z, dt / 2.0, k[1][0], k[1][1], k[1][2], X, Y, Z, threads);
+        roessler_rhs(n, X, Y, Z, a, b, c, k[2][0], k[2][1], k[2][2], threads);
+        intermediate3(n, x, y, z, dt, k[2][0], k[2][1], k[2][2], X, Y, Z, threads);
+        roessler_rhs(n, X, Y, Z, a, b, c, k[3][0], k[3][1], k[3][2], threads);
+#pragma omp parallel for num_threads(threads) schedule(static)
+        for (i = 0; i < n; ++i) {
+            x[i] = x[i] + (dt / 6.0) * (k[0][0][i] + 2.0 * k[1][0][i] + 2.0 * k[2][0][i] + k[3][0][i]);
+            y[i] = y[i] + (dt / 6.0) * (k[0][1][i] + 2.0 * k[1][1][i] + 2.0 * k[2][1][i] + k[3][1][i]);
+            z[i] = z[i] + (dt / 6.0) * (k[0][2][i] + 2.0 * k[1][2][i] + 2.0 * k[2][2][i] + k[3][2][i]);
+        }
+    }
+    free(buf);
+    return 0;
 }

@@ -30,13 +30,21 @@ MUTANTS = {
     "energy_bond": ("d * d * d * d / 4.0", "d * d * d * d / 2.0"),
     "energy_kinetic": ("return p * p / 2.0 + q * q / 2.0 + d * d / 2.0;",
                        "return p * p + q * q / 2.0 + d * d / 2.0;"),
+    "roessler_coupling_sign": ("kx[i] = -y[i] - z[i] + (xm - 2.0 * x[i] + xp);",
+                               "kx[i] = -y[i] - z[i] - (xm - 2.0 * x[i] + xp);"),
+    "roessler_coupling_weight": ("(xm - 2.0 * x[i] + xp)", "(xm - x[i] + xp)"),
+    "roessler_y_term": ("ky[i] = x[i] + a * y[i];", "ky[i] = x[i] + a * x[i];"),
+    "roessler_z_term": ("kz[i] = b + z[i] * (x[i] - c);", "kz[i] = b + z[i] * (x[i] + c);"),
+    "roessler_stage3": ("intermediate3(n, x, y, z, dt, k[2][0]", "intermediate3(n, x, y, z, dt / 2.0, k[2][0]"),
+    "roessler_final_z": ("2.0 * k[2][2][i] + k[3][2][i])", "k[2][2][i] + k[3][2][i])"),
 }
 
 
 def _run_pins(lib):
     env = dict(os.environ, CHAIN_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(HERE, "test_oracle_pins.py")],
+                        os.path.join(HERE, "test_oracle_pins.py"),
+                        os.path.join(HERE, "test_oracle_roessler.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     return r.returncode
 
