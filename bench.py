@@ -35,10 +35,14 @@ FP64_VECTOR_TFLOPS = 78.6
 # force 7 ops (bond diff, 2 mul for the cube, q^2, fma, 2 sub) x 4 stages,
 # stage arguments 2 fma x 3 stages, accumulators 3 ops x 2 components,
 # final update 1 fma x 2 components.
-OPS_PER_SU = {"quartic": 42, "harmonic": 30}
-FLOPS_PER_SU = {"quartic": 58, "harmonic": 42}
+# Roessler (three coordinates): right-hand side 7 ops (bond diff, two subs,
+# y + z, two fma, x - c) x 4 stages, stage arguments 3 fma x 3 stages,
+# accumulators 3 ops x 3 stages, final update 3 fma.
+OPS_PER_SU = {"quartic": 42, "harmonic": 30, "roessler": 49}
+FLOPS_PER_SU = {"quartic": 58, "harmonic": 42, "roessler": 75}
 # Bytes per site-update of one pass: read q, p and write q, p once.
 BYTES_PER_SITE_PASS = {"fp64": 32, "fp32_kahan": 32}   # FP32: q, p, cq, cp
+BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 
 
 # HBM bytes per fused pass from two rocprofv3 counter runs (FETCH_SIZE and
@@ -77,7 +81,8 @@ def pct(xs, q):
 
 def roofline(n, ksteps, t_launch, model="quartic", prec="fp64"):
     """Roofline of one fused pass of `ksteps` steps over n sites taking t_launch s."""
-    bytes_alg = BYTES_PER_SITE_PASS[prec] * n
+    bytes_alg = (BYTES_PER_SITE_PASS_ROESSLER if model == "roessler"
+                 else BYTES_PER_SITE_PASS[prec]) * n
     ops_alg = OPS_PER_SU[model] * n * ksteps
     t_hbm = bytes_alg / (HBM_PEAK_GBPS * 1e9)
     t_alu = ops_alg / (VALU_PEAK_TOPS * 1e12)
@@ -171,6 +176,9 @@ def main(argv=None):
     ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only sweep N = 2^10..2^26, fused vs per-stage, T = 50, best of 10")
+    ap.add_argument("--roessler", action="store_true",
+                    help="only the Roessler chain with the paper's protocol (N = 2^20, T = 50 "
+                         "steps, best of 10)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -190,6 +198,13 @@ def main(argv=None):
                           "n_gpus": 1, "data": "synthetic", "dtype": "f64",
                           "config": {"workload": "quartic chain, dt=0.01, T=50 steps, best of 10"},
                           "size_sweep": size_sweep(dev)}), flush=True)
+        return 0
+    if args.roessler:
+        print(json.dumps({"metric": "RK4 steps/s of the Roessler chain (Perf = T / t_wall)",
+                          "unit": "steps/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+                          "config": {"workload": "Roessler chain N=2^20, dt=0.01, T=50 steps, "
+                                                 "best of 10"},
+                          "roessler": variant_roessler(dev)}), flush=True)
         return 0
     n, dt, js = args.n, 0.01, args.job_steps
     log(f"[bench] generating ICs n={n}")
@@ -440,6 +455,68 @@ def size_sweep(dev, dt=0.01, steps=50, trials=10, exps=range(10, 27, 2)):
     return rows
 
 
+def roessler_shapes():
+    return [(s, w, k) for s in (4, 8) for w in (1, 2, 4, 8) for k in (4, 8, 16)
+            if 64 * s * w > 16 * k]
+
+
+def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None):
+    """The paper's performance protocol on its own workload (Sec. 3.2): a
+    Roessler chain of N = 2^20 from random initial conditions, T = 50 steps
+    of dt = 0.01, the best of M = 10 trials, Perf = T / t_wall (Eq. 8). The
+    wall time brackets the step call and a stream synchronisation; the
+    device time (HIP events) is reported beside it. Fused at the library
+    plan (eager and replayed from a graph), at every cluster shape in
+    `shapes`, and the one-kernel-per-stage method."""
+    import torch
+    import workloads
+    from paper_1412_0544_amd import RoesslerChain
+    x0, y0, z0 = (torch.from_numpy(v).to(dev) for v in workloads.roessler_ics(n, 0))
+
+    def measure(**kw):
+        ch = RoesslerChain(x0, y0, z0, dt, device=dev, **kw)
+        ch.step(steps)
+        torch.cuda.synchronize()
+        walls, gpus = [], []
+        for _ in range(trials):
+            t = time.perf_counter()
+            gpus.append(ev_seconds(lambda: ch.step(steps), ch.stream))
+            walls.append(time.perf_counter() - t)
+        plan = ch.plan()
+        ch.close()
+        w, g = min(walls), min(gpus)
+        return {"steps_per_s": steps / w, "su_per_s": n * steps / w,
+                "device_steps_per_s": steps / g, "device_su_per_s": n * steps / g,
+                "plan": {k: plan[k] for k in ("sites_per_lane", "waves_per_cluster", "kdepth",
+                                              "tile", "halo")}}
+
+    out = {"n": n, "steps": steps, "trials": trials, "dt": dt}
+    log("[bench] Roessler: library plan")
+    out["fused"] = measure()
+    out["fused_graph"] = measure(graph=True)
+    log("[bench] Roessler: per-stage baseline")
+    out["naive"] = measure(method="naive")
+    table = {}
+    for s, w, k in shapes or roessler_shapes():
+        table[f"s{s}_w{w}_k{k}"] = measure(sites_per_lane=s, waves_per_cluster=w, kdepth=k,
+                                          graph=True)["device_su_per_s"]
+    out["shapes_device_su_per_s"] = table
+    best = max(table, key=table.get)
+    out["best_shape"] = best
+    out["speedup_fused_vs_naive"] = out["fused"]["steps_per_s"] / out["naive"]["steps_per_s"]
+    # roofline of the library plan's passes (device time over the launches)
+    f = out["fused"]
+    k = f["plan"]["kdepth"]
+    plan = {"resident": 0, "kdepth": k}
+    launches = fused_launches(plan, steps)
+    out["roofline"] = roofline(n, steps / launches, n * steps / f["device_su_per_s"] / launches,
+                               model="roessler")
+    log(f"[bench] Roessler: fused {f['steps_per_s']:.0f} steps/s (device "
+        f"{f['device_steps_per_s']:.0f}), naive {out['naive']['steps_per_s']:.0f}, best shape "
+        f"{best} {table[best]:.3e} SU/s")
+    return out
+
+
 def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     """Other rows of the hot path, each measured at its own configuration."""
     from paper_1412_0544_amd import Chain, autotune
@@ -468,6 +545,8 @@ def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     res["precision"] = variant_precision(n, dt, dev)
     log("[bench] variant: 4096-chain batch")
     res["batch4096"] = variant_batch(dt, dev)
+    log("[bench] variant: Roessler chain, the paper's protocol")
+    res["roessler"] = variant_roessler(dev, dt)
     if serve_jobs:
         log(f"[bench] variant: serving {serve_jobs} jobs")
         res["serving"] = variant_serving(dt, dev, jobs=serve_jobs,

@@ -9,6 +9,10 @@
  *     dq_i/dt = p_i,   dp_i/dt = F_i(q_{i-1}, q_i, q_{i+1})
  *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
  *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
+ * and the paper's own test system, the Roessler chain (Sec. 3.1 Eq. 6-7),
+ * three coordinates per site with a = 0.2, b = 1, c = 9:
+ *   dx_i/dt = -y_i - z_i + (x_{i+1} - 2 x_i + x_{i-1})
+ *   dy_i/dt = x_i + a y_i,   dz_i/dt = b + z_i (x_i - c)
  *
  * Conventions for every call:
  *   - Device pointers are HIP device memory of the current device; host
@@ -39,7 +43,10 @@ typedef struct chain_rk4_batch chain_rk4_batch;
 
 enum chain_model {
     CHAIN_QUARTIC = 0,   /* quartic on-site and bond potentials (formula above) */
-    CHAIN_HARMONIC = 1   /* the linear chain (formula above) */
+    CHAIN_HARMONIC = 1,  /* the linear chain (formula above) */
+    CHAIN_ROESSLER = 2   /* the Roessler chain (formula above): FP64 only,
+                            created with chain_rk4_create3, no energy, no
+                            batches, never kept resident on chip */
 };
 
 enum chain_prec {
@@ -128,6 +135,17 @@ size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d);
 int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace,
                      size_t ws_bytes, void *stream, chain_rk4 **out);
 
+/*
+ * Create a handle over three caller-owned coordinate arrays: x, y, z of the
+ * Roessler chain (d->model == CHAIN_ROESSLER, d->prec == CHAIN_FP64), each
+ * d->n doubles, 16-byte aligned; the other arguments as chain_rk4_create.
+ * For the two-coordinate models z must be NULL and the call is the same as
+ * chain_rk4_create(d, x, y, ...). chain_rk4_create rejects CHAIN_ROESSLER
+ * with CHAIN_EINVAL.
+ */
+int chain_rk4_create3(const chain_rk4_desc *d, void *x, void *y, void *z, void *workspace,
+                      size_t ws_bytes, void *stream, chain_rk4 **out);
+
 /* Enqueue nsteps (>= 0) RK4 steps on the handle's stream (asynchronous). */
 int chain_rk4_step(chain_rk4 *h, int64_t nsteps);
 
@@ -137,7 +155,9 @@ int chain_rk4_step(chain_rk4 *h, int64_t nsteps);
  * harmonic: sum_i p_i^2/2 + q_i^2/2 + (q_{i+1}-q_i)^2/2. For CHAIN_FP32_KAHAN
  * each coordinate enters as (hi - carry) in FP64. The sum order is fixed for
  * a given n, so repeated calls agree bitwise. Synchronises the stream.
- * Returns CHAIN_ENONFINITE (with *e_out set) if the energy is NaN or Inf.
+ * Returns CHAIN_ENONFINITE (with *e_out set) if the energy is NaN or Inf,
+ * CHAIN_EINVAL for a CHAIN_ROESSLER handle (a dissipative system with no
+ * conserved energy).
  */
 int chain_rk4_energy(chain_rk4 *h, double *e_out);
 
@@ -178,8 +198,8 @@ const char *chain_rk4_last_error(void);
  * flags), so passes of different clusters and chains overlap. Every chain
  * gives the same bits as when stepped alone (any handle settings, any grid).
  *
- * All handles of a batch share one model and one precision, use
- * CHAIN_FUSED, appear once, and must stay valid while the batch exists; each
+ * All handles of a batch share one model (CHAIN_QUARTIC or CHAIN_HARMONIC)
+ * and one precision, use CHAIN_FUSED, appear once, and must stay valid while the batch exists; each
  * chain keeps its own dt. Calls that overlap on one batch's workspace race.
  */
 enum chain_batch_flags {

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchainrk4.so")
 
-CHAIN_QUARTIC, CHAIN_HARMONIC = 0, 1
+CHAIN_QUARTIC, CHAIN_HARMONIC, CHAIN_ROESSLER = 0, 1, 2
 CHAIN_FP64, CHAIN_FP32_KAHAN = 0, 1
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT = 1, 2
@@ -74,6 +74,8 @@ def _declare(lib):
         "chain_rk4_workspace_bytes": (ctypes.c_size_t, [D]),
         "chain_rk4_create": (ctypes.c_int, [D, VP, VP, VP, ctypes.c_size_t, VP,
                                             ctypes.POINTER(H)]),
+        "chain_rk4_create3": (ctypes.c_int, [D, VP, VP, VP, VP, ctypes.c_size_t, VP,
+                                             ctypes.POINTER(H)]),
         "chain_rk4_step": (ctypes.c_int, [H, ctypes.c_int64]),
         "chain_rk4_energy": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
         "chain_rk4_set_stream": (ctypes.c_int, [H, VP]),

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libchainrk4.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["fused.hip", "persistent.hip", "naive.hip", "energy.hip", "chain_rk4.cpp", "batch.cpp"]
+SOURCES = ["fused.hip", "persistent.hip", "naive.hip", "energy.hip", "roessler.hip", "chain_rk4.cpp", "batch.cpp"]
 ARCH = "gfx950"
 
 COMMON = [

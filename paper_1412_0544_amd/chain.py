@@ -120,3 +120,61 @@ class Chain:
             self.close()
         except Exception:
             pass
+
+
+class RoesslerChain:
+    """The Roessler chain (three FP64 coordinates per site) advanced by the
+    HIP library; ``x``, ``y``, ``z`` are the device state tensors. There is no
+    energy (the system is dissipative) and no batching."""
+
+    def __init__(self, x0, y0, z0, dt: float, method="fused", sites_per_lane: int = 0,
+                 kdepth: int = 0, waves_per_cluster: int = 0, graph: bool = False,
+                 device="cuda", stream: torch.cuda.Stream | None = None):
+        self.device = torch.device(device)
+        as_dev = lambda a: torch.as_tensor(a).to(device=self.device,  # noqa: E731
+                                                 dtype=torch.float64).contiguous().clone()
+        self.x, self.y, self.z = as_dev(x0), as_dev(y0), as_dev(z0)
+        if self.x.ndim != 1 or self.x.shape != self.y.shape or self.x.shape != self.z.shape:
+            raise ValueError("x0, y0 and z0 must be 1-D of one length")
+        self.desc = L.Desc(self.x.numel(), L.CHAIN_ROESSLER, L.CHAIN_FP64, float(dt),
+                           _code(METHODS, method), int(sites_per_lane), int(kdepth),
+                           int(waves_per_cluster), L.CHAIN_FLAG_GRAPH if graph else 0, 0)
+        lib = L.lib()
+        ws = lib.chain_rk4_workspace_bytes(ctypes.byref(self.desc))
+        if ws == 0:
+            L.check(L.CHAIN_EINVAL, "chain_rk4_workspace_bytes")
+        self._ws, ws_ptr = aligned_empty(ws, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = L.H()
+        L.check(lib.chain_rk4_create3(ctypes.byref(self.desc), self.x.data_ptr(),
+                                      self.y.data_ptr(), self.z.data_ptr(), ws_ptr, ws,
+                                      self.stream.cuda_stream, ctypes.byref(h)),
+                "chain_rk4_create3")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, nsteps: int) -> "RoesslerChain":
+        L.check(L.lib().chain_rk4_step(self._h, int(nsteps)), "chain_rk4_step")
+        return self
+
+    def plan(self) -> dict:
+        P = L.Plan()
+        L.check(L.lib().chain_rk4_get_plan(self._h, ctypes.byref(P)), "chain_rk4_get_plan")
+        return {k: getattr(P, k) for k, _ in L.Plan._fields_}
+
+    def state(self):
+        return self.x, self.y, self.z
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            L.lib().chain_rk4_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

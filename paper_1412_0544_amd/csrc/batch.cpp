@@ -112,6 +112,8 @@ int check_handles(chain_rk4 *const *hs, int count, int model, int prec) {
             return fail(CHAIN_EINVAL, "handle %d does not use the fused method", i);
         if (hs[i]->d.model != model || hs[i]->d.prec != prec)
             return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
+        if (hs[i]->d.model == CHAIN_ROESSLER)
+            return fail(CHAIN_EINVAL, "handle %d: batches take the two-coordinate models only", i);
     }
     std::vector<chain_rk4 *> sorted(hs, hs + count);
     std::sort(sorted.begin(), sorted.end());

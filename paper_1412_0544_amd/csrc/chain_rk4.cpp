@@ -62,6 +62,10 @@ size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kDefaultSitesFp64 = 8;
 constexpr int kDefaultSitesFp32 = 16;
 constexpr int kDefaultWaves = 4;
+// Roessler: nine S-site register arrays per lane instead of six, so fewer
+// sites per lane (the fastest shape at N = 2^20 in a sweep over S, W, k).
+constexpr int kDefaultSitesRoessler = 4;
+constexpr int kDefaultWavesRoessler = 4;
 constexpr int kDefaultDepth = 16;
 constexpr int kMaxDepth = 16;
 
@@ -72,10 +76,12 @@ int check_desc(const chain_rk4_desc *d) {
     if (!d) return fail(CHAIN_EINVAL, "descriptor is NULL");
     if (d->n < 1) return fail(CHAIN_EINVAL, "n must be >= 1 (got %lld)", (long long)d->n);
     if (d->n > (int64_t(1) << 40)) return fail(CHAIN_EINVAL, "n too large");
-    if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC)
+    if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC && d->model != CHAIN_ROESSLER)
         return fail(CHAIN_EINVAL, "unknown model %d", d->model);
     if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN)
         return fail(CHAIN_EINVAL, "unknown precision %d", d->prec);
+    if (d->model == CHAIN_ROESSLER && d->prec != CHAIN_FP64)
+        return fail(CHAIN_EINVAL, "the Roessler chain runs in FP64 only");
     if (!std::isfinite(d->dt)) return fail(CHAIN_EINVAL, "dt must be finite");
     if (d->method != CHAIN_FUSED && d->method != CHAIN_NAIVE)
         return fail(CHAIN_EINVAL, "unknown method %d", d->method);
@@ -94,9 +100,10 @@ int check_desc(const chain_rk4_desc *d) {
 
 // Workspace regions, in order. Unused regions have size 0.
 struct Layout {
-    size_t back_q, back_p;            // fused: back buffer of the ping-pong
+    size_t back_q, back_p, back_z;    // fused: back buffer of the ping-pong
     size_t cq, cp, back_cq, back_cp;  // FP32: carries (front and back)
     size_t naive[10];                 // naive: k1..k3 and two stage arguments
+    size_t naive_z[5];                // naive, Roessler: the same for z
     size_t partials, result;          // energy
     size_t total;
 };
@@ -113,9 +120,11 @@ Layout layout(const chain_rk4_desc *d) {
         return o;
     };
     const bool kahan = d->prec == CHAIN_FP32_KAHAN;
+    const bool three = d->model == CHAIN_ROESSLER;
     if (d->method == CHAIN_FUSED) {
         L.back_q = take(arr);
         L.back_p = take(arr);
+        if (three) L.back_z = take(arr);
     }
     if (kahan) {
         L.cq = take(carr);
@@ -125,8 +134,11 @@ Layout layout(const chain_rk4_desc *d) {
             L.back_cp = take(carr);
         }
     }
-    if (d->method == CHAIN_NAIVE)
+    if (d->method == CHAIN_NAIVE) {
         for (int i = 0; i < 10; ++i) L.naive[i] = take(arr);
+        if (three)
+            for (int i = 0; i < 5; ++i) L.naive_z[i] = take(arr);
+    }
     L.partials = take(round_up(kEnergyMaxBlocks * sizeof(double)));
     L.result = take(kAlign);
     L.total = off;
@@ -137,14 +149,18 @@ Layout layout(const chain_rk4_desc *d) {
 Plan make_plan(const chain_rk4_desc *d) {
     Plan P;
     if (d->method != CHAIN_FUSED) return P;
-    if (!(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites && d->sites_per_lane == 0 &&
-        d->kdepth == 0 && d->waves_per_cluster == 0) {
+    const bool roessler = d->model == CHAIN_ROESSLER;
+    if (!roessler && !(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites &&
+        d->sites_per_lane == 0 && d->kdepth == 0 && d->waves_per_cluster == 0) {
         P.resident = true;
         return P;
     }
     P.sites = d->sites_per_lane ? d->sites_per_lane
-                                : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
-    P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster : kDefaultWaves;
+              : roessler        ? kDefaultSitesRoessler
+              : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
+    P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
+                          : roessler             ? kDefaultWavesRoessler
+                                                 : kDefaultWaves;
     P.depth = d->kdepth ? d->kdepth : kDefaultDepth;
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
     // the kept part of a cluster must stay positive: E > 8*depth
@@ -167,7 +183,9 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
     if (nsteps == 0) return CHAIN_OK;
     if (d.method == CHAIN_NAIVE) {
         for (int64_t i = 0; i < nsteps; ++i) {
-            hipError_t e = launch_naive_step(d.model, d.prec, h->front, h->naive, d.n, d.dt, s);
+            hipError_t e = d.model == CHAIN_ROESSLER
+                               ? launch_naive_roessler_step(h->front, h->naive, d.n, d.dt, s)
+                               : launch_naive_step(d.model, d.prec, h->front, h->naive, d.n, d.dt, s);
             if (e != hipSuccess) return hip_fail(e, "naive step launch");
         }
         return CHAIN_OK;
@@ -198,7 +216,10 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
     StateRef cur = h->front, nxt = h->back;
     for (int k : ks) {
         FusedPass a{cur, nxt, d.n, h->plan.tile, h->plan.halo, h->plan.waves, d.dt, k};
-        hipError_t e = launch_fused(d.model, d.prec, h->plan.sites, h->plan.waves_per_cluster, a, s);
+        hipError_t e =
+            d.model == CHAIN_ROESSLER
+                ? launch_fused_roessler(h->plan.sites, h->plan.waves_per_cluster, a, s)
+                : launch_fused(d.model, d.prec, h->plan.sites, h->plan.waves_per_cluster, a, s);
         if (e != hipSuccess) return hip_fail(e, "fused launch");
         std::swap(cur, nxt);
     }
@@ -206,6 +227,8 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
         const size_t b = static_cast<size_t>(d.n) * elem_bytes(d.prec);
         HIP_TRY(hipMemcpyAsync(h->front.q, cur.q, b, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(h->front.p, cur.p, b, hipMemcpyDeviceToDevice, s));
+        if (d.model == CHAIN_ROESSLER)
+            HIP_TRY(hipMemcpyAsync(h->front.z, cur.z, b, hipMemcpyDeviceToDevice, s));
         if (d.prec == CHAIN_FP32_KAHAN) {
             const size_t cb = static_cast<size_t>(d.n) * sizeof(float);
             HIP_TRY(hipMemcpyAsync(h->front.cq, cur.cq, cb, hipMemcpyDeviceToDevice, s));
@@ -251,15 +274,19 @@ size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d) {
     return layout(d).total;
 }
 
-int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace, size_t ws_bytes,
-                     void *stream, chain_rk4 **out) {
+int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *workspace,
+                      size_t ws_bytes, void *stream, chain_rk4 **out) {
     int rc = check_desc(d);
     if (rc != CHAIN_OK) return rc;
     if (!out) return fail(CHAIN_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!q || !p) return fail(CHAIN_EINVAL, "q and p must be device pointers");
-    if ((reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(p)) & 15)
-        return fail(CHAIN_EINVAL, "q and p must be 16-byte aligned");
+    const bool three = d->model == CHAIN_ROESSLER;
+    if (!q || !p) return fail(CHAIN_EINVAL, "the coordinate arrays must be device pointers");
+    if (three && !z) return fail(CHAIN_EINVAL, "the Roessler chain needs a z array");
+    if (!three && z) return fail(CHAIN_EINVAL, "z must be NULL for a two-coordinate model");
+    if ((reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(p) |
+         reinterpret_cast<uintptr_t>(z)) & 15)
+        return fail(CHAIN_EINVAL, "coordinate arrays must be 16-byte aligned");
     const Layout L = layout(d);
     if (ws_bytes < L.total)
         return fail(CHAIN_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
@@ -277,11 +304,12 @@ int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace,
     h->d = *d;
     h->stream = static_cast<hipStream_t>(stream);
     h->plan = make_plan(d);
-    h->front = StateRef{q, p, nullptr, nullptr};
-    h->back = StateRef{nullptr, nullptr, nullptr, nullptr};
+    h->front = StateRef{q, p, nullptr, nullptr, static_cast<double *>(z)};
+    h->back = StateRef{nullptr, nullptr, nullptr, nullptr, nullptr};
     if (d->method == CHAIN_FUSED) {
         h->back.q = ws + L.back_q;
         h->back.p = ws + L.back_p;
+        if (three) h->back.z = reinterpret_cast<double *>(ws + L.back_z);
     }
     if (d->prec == CHAIN_FP32_KAHAN) {
         h->front.cq = reinterpret_cast<float *>(ws + L.cq);
@@ -296,6 +324,11 @@ int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace,
                             &h->naive.k3q, &h->naive.k3p, &h->naive.yaq, &h->naive.yap,
                             &h->naive.ybq, &h->naive.ybp};
         for (int i = 0; i < 10; ++i) *slots[i] = ws + L.naive[i];
+        if (three) {
+            double **zs[5] = {&h->naive.k1z, &h->naive.k2z, &h->naive.k3z, &h->naive.yaz,
+                              &h->naive.ybz};
+            for (int i = 0; i < 5; ++i) *zs[i] = reinterpret_cast<double *>(ws + L.naive_z[i]);
+        }
     }
     h->partials = reinterpret_cast<double *>(ws + L.partials);
     h->result = reinterpret_cast<double *>(ws + L.result);
@@ -312,6 +345,15 @@ int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace,
     return CHAIN_OK;
 }
 
+int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace, size_t ws_bytes,
+                     void *stream, chain_rk4 **out) {
+    if (d && d->model == CHAIN_ROESSLER) {
+        if (out) *out = nullptr;
+        return fail(CHAIN_EINVAL, "the Roessler chain has three coordinates: use chain_rk4_create3");
+    }
+    return chain_rk4_create3(d, q, p, nullptr, workspace, ws_bytes, stream, out);
+}
+
 int chain_rk4_step(chain_rk4 *h, int64_t nsteps) {
     if (!h) return fail(CHAIN_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(CHAIN_EINVAL, "nsteps must be >= 0");
@@ -322,6 +364,8 @@ int chain_rk4_step(chain_rk4 *h, int64_t nsteps) {
 
 int chain_rk4_energy(chain_rk4 *h, double *e_out) {
     if (!h || !e_out) return fail(CHAIN_EINVAL, "handle and e_out must be non-NULL");
+    if (h->d.model == CHAIN_ROESSLER)
+        return fail(CHAIN_EINVAL, "the Roessler chain has no conserved energy");
     hipError_t e = launch_energy(h->d.model, h->d.prec, h->front, h->d.n, h->partials, h->result,
                                  h->stream);
     if (e != hipSuccess) return hip_fail(e, "energy launch");

@@ -13,6 +13,7 @@ namespace chainrk4 {
 struct StateRef {
     void *q, *p;
     float *cq, *cp;
+    double *z;   // third coordinate of the Roessler chain (q = x, p = y)
 };
 
 // One pass of the fused kernel: every cluster (W wavefronts) owns `tile`
@@ -40,6 +41,7 @@ struct ResidentRun {
 struct NaiveBufs {
     void *k1q, *k1p, *k2q, *k2p, *k3q, *k3p;  // stage slopes
     void *yaq, *yap, *ybq, *ybp;              // stage arguments (ping-pong)
+    double *k1z, *k2z, *k3z, *yaz, *ybz;      // Roessler: third coordinate
 };
 
 constexpr int kResidentThreads = 256;
@@ -52,6 +54,13 @@ hipError_t launch_resident(int model, int prec, const ResidentRun &a, hipStream_
 size_t resident_lds_bytes(int prec, int64_t n);
 hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,
                              double dt, hipStream_t s);
+
+// Roessler chain (FP64): fused cluster pass and the per-stage baseline.
+constexpr int kModelRoessler = 2;
+hipError_t launch_fused_roessler(int sites_per_lane, int waves_per_cluster, const FusedPass &a,
+                                 hipStream_t s);
+hipError_t launch_naive_roessler_step(StateRef y, const NaiveBufs &b, int64_t n, double dt,
+                                      hipStream_t s);
 
 // Energy: per-block FP64 partials, then one fixed-order finishing block.
 constexpr int kEnergyThreads = 256;

@@ -211,6 +211,61 @@ __device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Roessler chain (Sec. 3.1 Eq. 6-7), FP64, three coordinates per site:
+//   dx/dt = (d_i - d_{i-1}) - (y + z),  d_i = x_{i+1} - x_i
+//   dy/dt = x + a y,   dz/dt = b + z (x - c),   a = 0.2, b = 1, c = 9.
+// ---------------------------------------------------------------------------
+struct Roessler {
+    static constexpr double a = 0.2, b = 1.0, c = 9.0;
+    __device__ __forceinline__ static void rhs(double bl, double br, double X, double Y, double Z,
+                                               double &kx, double &ky, double &kz) {
+        kx = (br - bl) - (Y + Z);
+        ky = fma_r(a, Y, X);
+        kz = fma_r(Z, X - c, b);
+    }
+};
+
+// One RK4 stage of the Roessler chain over S consecutive sites (same
+// structure as stage_sites; only x couples to the neighbours).
+template <int S, int STAGE>
+__device__ __forceinline__ void roessler_stage_sites(double (&X)[S], double (&Y)[S], double (&Z)[S],
+                                                     double (&x)[S], double (&y)[S], double (&z)[S],
+                                                     double (&ax)[S], double (&ay)[S],
+                                                     double (&az)[S], double bl0, double brS,
+                                                     const StepConsts<double> &c) {
+    double bl = bl0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const double Xj = (STAGE == 1) ? x[j] : X[j];
+        const double Yj = (STAGE == 1) ? y[j] : Y[j];
+        const double Zj = (STAGE == 1) ? z[j] : Z[j];
+        double br;
+        if (j + 1 < S)
+            br = ((STAGE == 1) ? x[j + 1] : X[j + 1]) - Xj;
+        else
+            br = brS;
+        double kx, ky, kz;
+        Roessler::rhs(bl, br, Xj, Yj, Zj, kx, ky, kz);
+        bl = br;
+        if (STAGE == 1) {
+            ax[j] = kx; ay[j] = ky; az[j] = kz;
+            X[j] = fma_r(c.hh, kx, x[j]); Y[j] = fma_r(c.hh, ky, y[j]); Z[j] = fma_r(c.hh, kz, z[j]);
+        } else if (STAGE == 2) {
+            ax[j] = fma_r(2.0, kx, ax[j]); ay[j] = fma_r(2.0, ky, ay[j]); az[j] = fma_r(2.0, kz, az[j]);
+            X[j] = fma_r(c.hh, kx, x[j]); Y[j] = fma_r(c.hh, ky, y[j]); Z[j] = fma_r(c.hh, kz, z[j]);
+        } else if (STAGE == 3) {
+            ax[j] = fma_r(2.0, kx, ax[j]); ay[j] = fma_r(2.0, ky, ay[j]); az[j] = fma_r(2.0, kz, az[j]);
+            X[j] = fma_r(c.h, kx, x[j]); Y[j] = fma_r(c.h, ky, y[j]); Z[j] = fma_r(c.h, kz, z[j]);
+        } else {
+            ax[j] = ax[j] + kx; ay[j] = ay[j] + ky; az[j] = az[j] + kz;
+            x[j] = fma_r(c.h6, ax[j], x[j]);
+            y[j] = fma_r(c.h6, ay[j], y[j]);
+            z[j] = fma_r(c.h6, az[j], z[j]);
+        }
+    }
+}
+
 // Ring index of an unwrapped site index (any sign, any multiple of n).
 __device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
     if (i >= 0 && i < n) return i;

@@ -133,3 +133,31 @@ def test_batch_cluster_count_helper():
         assert lib.chain_rk4_batch_clusters(n, 8, 12) == expect(n, 8, 12)
     assert lib.chain_rk4_batch_clusters(100, 5, 0) == 0          # invalid shape
     assert lib.chain_rk4_batch_rebind(None, None, 0) == L.CHAIN_EINVAL
+
+
+def test_roessler_arguments_are_validated_without_a_gpu():
+    lib = L.lib()
+    f = lambda d: lib.chain_rk4_workspace_bytes(ctypes.byref(d))
+    n = 1 << 20
+    # fused: three back-buffer arrays; naive: k1..k3 and two stage arguments
+    # for each of the three coordinates
+    assert f(desc(n=n, model=L.CHAIN_ROESSLER)) >= 3 * 8 * n
+    assert f(desc(n=n, model=L.CHAIN_ROESSLER, method=1)) >= 15 * 8 * n
+    assert f(desc(n=n, model=L.CHAIN_ROESSLER, prec=1)) == 0       # FP64 only
+    h = L.H()
+    fake = 1 << 20
+    d = desc(model=L.CHAIN_ROESSLER)
+    ws = f(d)
+    # the two-pointer entry point cannot describe three coordinates
+    assert lib.chain_rk4_create(ctypes.byref(d), fake, fake, fake, ws, None,
+                                ctypes.byref(h)) == L.CHAIN_EINVAL
+    assert b"create3" in lib.chain_rk4_last_error()
+    cases = [
+        (d, fake, fake, None, ws, L.CHAIN_EINVAL),          # z missing
+        (d, fake, fake, fake + 8, ws, L.CHAIN_EINVAL),      # z misaligned
+        (d, fake, fake, fake, ws - 1, L.CHAIN_ENOMEM),
+        (desc(), fake, fake, fake, f(desc()), L.CHAIN_EINVAL),  # z given to a 2-coordinate model
+    ]
+    for dd, x, y, z, nb, want in cases:
+        assert lib.chain_rk4_create3(ctypes.byref(dd), x, y, z, fake, nb, None,
+                                     ctypes.byref(h)) == want

@@ -1,0 +1,135 @@
+"""The Roessler chain (Sec. 3.1 Eq. 6-7) on the GPU against the oracle,
+through the C ABI.
+
+FP64 bar: max-abs state error <= 1e-10 after 100 steps. The fused kernel at
+every cluster shape and depth and the one-kernel-per-stage method give the
+same bits. At the paper's size (N = 2^20) sampled sites are checked against
+the oracle, each from its own light cone.
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1412_0544_amd import ChainError, RoesslerChain
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def gpu_run(ics, dt, steps, **kw):
+    ch = RoesslerChain(*ics, dt, **kw)
+    ch.step(steps)
+    out = tuple(t.cpu().numpy() for t in ch.state())
+    plan = ch.plan()
+    ch.close()
+    return out, plan
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_run(n, seed, dt, steps):
+    return oracle.roessler_rk4(*workloads.roessler_ics(n, seed), dt, steps, threads=8)
+
+
+def maxerr(a, b):
+    return max(float(np.max(np.abs(u - v))) for u, v in zip(a, b))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257, 1000, 5003, 20011])
+@pytest.mark.parametrize("sites,waves,depth", [(4, 1, 1), (8, 2, 3), (16, 1, 8), (4, 8, 16),
+                                               (4, 4, 12), (8, 4, 16), (16, 8, 12)])
+def test_fused_matches_oracle(n, sites, waves, depth):
+    ics = workloads.roessler_ics(n, 1)
+    got, plan = gpu_run(ics, 0.01, 100, sites_per_lane=sites, waves_per_cluster=waves,
+                        kdepth=depth)
+    assert plan["resident"] == 0 and plan["sites_per_lane"] == sites
+    assert maxerr(got, oracle_run(n, 1, 0.01, 100)) <= TOL
+
+
+@pytest.mark.parametrize("n", [1, 5, 1000, 20011])
+def test_naive_matches_oracle_and_fused_bits(n):
+    ics = workloads.roessler_ics(n, 2)
+    naive, _ = gpu_run(ics, 0.01, 100, method="naive")
+    fused, _ = gpu_run(ics, 0.01, 100)
+    assert maxerr(naive, oracle_run(n, 2, 0.01, 100)) <= TOL
+    for a, b in zip(naive, fused):
+        assert np.array_equal(a, b)
+
+
+def test_shapes_depths_and_step_splits_identical_bits():
+    n = 3 * 2048 + 77
+    ics = workloads.roessler_ics(n, 3)
+    ref, _ = gpu_run(ics, 0.01, 37)
+    for s, w, k in [(4, 1, 1), (4, 2, 5), (8, 8, 16), (16, 4, 7), (8, 1, 2)]:
+        got, _ = gpu_run(ics, 0.01, 37, sites_per_lane=s, waves_per_cluster=w, kdepth=k)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), (s, w, k)
+    # 37 steps as 1 + 16 + 20 calls, and replayed from captured graphs
+    for graph in (False, True):
+        ch = RoesslerChain(*ics, 0.01, graph=graph)
+        for k in (1, 16, 20):
+            ch.step(k)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, ch.state()):
+            assert np.array_equal(a, b.cpu().numpy()), graph
+        ch.close()
+
+
+def test_synchronized_chain_and_fixed_point():
+    """Identical sites stay identical (the coupling term vanishes exactly);
+    the fixed point of the single oscillator stays put."""
+    n = 5000
+    ch = RoesslerChain(np.full(n, 1.0), np.full(n, -2.0), np.full(n, 0.3), 0.01)
+    ch.step(500)
+    x, y, z = (t.cpu().numpy() for t in ch.state())
+    assert np.all(x == x[0]) and np.all(y == y[0]) and np.all(z == z[0])
+    ch.close()
+    xo, yo, zo = oracle.roessler_rk4(np.ones(3), np.full(3, -2.0), np.full(3, 0.3), 0.01, 500)
+    assert abs(x[0] - xo[0]) < 1e-11 and abs(y[0] - yo[0]) < 1e-11 and abs(z[0] - zo[0]) < 1e-11
+    a, b, c = oracle.ROESSLER_ABC
+    yf = (-c + np.sqrt(c * c - 4 * a * b)) / (2 * a)
+    ch = RoesslerChain(np.full(n, -a * yf), np.full(n, yf), np.full(n, -yf), 0.01)
+    ch.step(200)
+    x, y, z = (t.cpu().numpy() for t in ch.state())
+    assert np.abs(x + a * yf).max() < 1e-12 and np.abs(y - yf).max() < 1e-12
+    assert np.abs(z + yf).max() < 1e-12
+    ch.close()
+
+
+def test_translation_symmetry_bitwise():
+    n = 10007
+    x0, y0, z0 = workloads.roessler_ics(n, 4)
+    a, _ = gpu_run((x0, y0, z0), 0.01, 64)
+    b, _ = gpu_run(tuple(np.roll(v, 1234) for v in (x0, y0, z0)), 0.01, 64)
+    for u, v in zip(a, b):
+        assert np.array_equal(np.roll(u, 1234), v)
+
+
+def test_paper_size_sampled_sites():
+    """N = 2^20, dt = 0.01, T = 50 steps (the paper's protocol), default
+    plan: sampled sites vs the oracle's light cones."""
+    n = 1 << 20
+    ics = workloads.roessler_ics(n, 0)
+    got, plan = gpu_run(ics, 0.01, 50)
+    tile = plan["tile"]
+    rng = np.random.default_rng(1)
+    sites = np.unique(np.concatenate([[0, 1, n - 1, tile - 1, tile, 2 * tile],
+                                      rng.integers(0, n, 24)]))
+    want = oracle.roessler_rk4_sites(*ics, 0.01, 50, sites)
+    assert maxerr(tuple(g[sites] for g in got), want) <= TOL
+    assert all(np.all(np.isfinite(g)) for g in got)
+
+
+def test_roessler_rejects_energy_and_batches():
+    from paper_1412_0544_amd import Batch
+    ch = RoesslerChain(*workloads.roessler_ics(100, 0), 0.01)
+    import ctypes
+    from paper_1412_0544_amd import _lib as L
+    e = ctypes.c_double()
+    assert L.lib().chain_rk4_energy(ch.handle, ctypes.byref(e)) == L.CHAIN_EINVAL
+    with pytest.raises(ChainError):
+        Batch([ch], max_steps=10)
+    ch.close()

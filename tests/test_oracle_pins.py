@@ -286,3 +286,11 @@ def test_zero_steps_is_identity_and_bad_args_raise():
     assert np.array_equal(q, q0) and np.array_equal(p, p0)
     with pytest.raises(MemoryError):
         oracle.rk4(Q, q0, p0, 0.01, -1)
+
+
+def test_roessler_ics_range_and_interleave():
+    x, y, z = workloads.roessler_ics(3000, 9)
+    for v in (x, y, z):
+        assert v.min() >= -1.0 and v.max() < 1.0 and abs(v.mean()) < 0.1
+    u = workloads.uniform01(9, np.array([15, 16, 17], dtype=np.uint64))
+    assert (x[5], y[5], z[5]) == tuple(2 * u - 1)

@@ -66,6 +66,22 @@ def chain_ics(n: int, seed: int = 0, dtype=np.float64):
     return q, p
 
 
+def roessler_ics(n: int, seed: int = 0):
+    """Random initial (x, y, z) for an n-site Roessler chain (the paper starts
+    from random initial conditions, Sec. 3.2, without saying which): all three
+    uniform on [-1, 1), like the other chains. Site i uses draws 3i, 3i + 1,
+    3i + 2 of stream ``seed``."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    x, y, z = (np.empty(n, dtype=np.float64) for _ in range(3))
+    for a, b in _chunks(n):
+        i = np.arange(a, b, dtype=np.uint64)
+        x[a:b] = 2.0 * uniform01(seed, 3 * i) - 1.0
+        y[a:b] = 2.0 * uniform01(seed, 3 * i + 1) - 1.0
+        z[a:b] = 2.0 * uniform01(seed, 3 * i + 2) - 1.0
+    return x, y, z
+
+
 def _as_i64(x: int) -> int:
     x &= 0xFFFFFFFFFFFFFFFF
     return x - (1 << 64) if x >= (1 << 63) else x
