@@ -5,8 +5,9 @@ CPU-baseline leg are the only callers. Nothing here is shared with the GPU
 library. The arithmetic lives in ``chain_oracle.c`` (plain C, FP64, no FMA);
 this module only marshals numpy arrays into it.
 
-Model ids: 0 = quartic chain, 1 = harmonic chain (see ``chain_oracle.c``); the
-Roessler chain (three coordinates per site) has its own calls.
+Model ids: 0 = quartic chain, 1 = harmonic chain, 3 and 4 = the same with
+second-neighbour bonds (see ``chain_oracle.c``); the Roessler chain (three
+coordinates per site) has its own calls.
 """
 from __future__ import annotations
 
@@ -25,6 +26,13 @@ _LIB_OVERRIDE = os.environ.get("CHAIN_ORACLE_LIB")
 
 QUARTIC = 0
 HARMONIC = 1
+QUARTIC_NNN = 3
+HARMONIC_NNN = 4
+
+
+def coupling_range(model: int) -> int:
+    """Farthest neighbour a site's force reads (1 or 2)."""
+    return 2 if model in (QUARTIC_NNN, HARMONIC_NNN) else 1
 # The paper's Roessler parameters (Sec. 3.1): a = 0.2, b = 1, c = 9.
 ROESSLER_ABC = (0.2, 1.0, 9.0)
 
@@ -109,16 +117,16 @@ def rk4_sites(model: int, q, p, dt: float, steps: int, sites, threads: int = 1):
     """Final (q, p) of selected sites only, each from its own light cone.
 
     After ``steps`` RK4 steps a site depends on the initial state within
-    4 * steps sites of it (one site per stage, Sec. 2.3). On a ring of
-    2 * 4 * steps + 1 sites cut from the chain around site i, those sites are
-    the same, so site i comes out exactly as on the full ring. Used when the
-    full ring is too long for the oracle; chains shorter than the window run
-    whole.
+    4 * range * steps sites of it (``range`` sites per stage, Sec. 2.3 and
+    Sec. 4). On a ring of 2 * 4 * range * steps + 1 sites cut from the chain
+    around site i, those sites are the same, so site i comes out exactly as on
+    the full ring. Used when the full ring is too long for the oracle; chains
+    shorter than the window run whole.
     """
     q = _f64(q)
     p = _f64(p)
     n = q.size
-    r = 4 * int(steps)
+    r = 4 * coupling_range(model) * int(steps)
     w = 2 * r + 1
     sites = np.asarray(sites, dtype=np.int64)
     if w >= n:

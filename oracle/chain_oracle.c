@@ -16,8 +16,14 @@
  * dq_i/dt = p_i, dp_i/dt = F_i):
  *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
  *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
- * Periodic boundary (Sec. 3.1): site 0's left neighbour is site N-1 and site
- * N-1's right neighbour is site 0, for every N >= 1.
+ * Next-nearest-neighbour variants (the generalisation named in Sec. 4): every
+ * site is also bonded to its second neighbours, with the same bond potential:
+ *   quartic NNN:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
+ *                                      + (q_{i+2} - q_i)^3 - (q_i - q_{i-2})^3
+ *   harmonic NNN: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
+ *                            + (q_{i+2} - 2 q_i + q_{i-2})
+ * Periodic boundary (Sec. 3.1): site indices are taken mod N for every
+ * N >= 1 (site 0's left neighbour is site N-1, and so on).
  *
  * Roessler chain (Sec. 3.1 Eq. 6-7), three coordinates per site:
  *   dx_i/dt = -y_i - z_i + (x_{i-1} - 2 x_i + x_{i+1})
@@ -29,10 +35,17 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORACLE_QUARTIC = 0, ORACLE_HARMONIC = 1 };
+enum { ORACLE_QUARTIC = 0, ORACLE_HARMONIC = 1, ORACLE_QUARTIC_NNN = 3, ORACLE_HARMONIC_NNN = 4 };
 
 static int64_t left_of(int64_t i, int64_t n) { return i == 0 ? n - 1 : i - 1; }
 static int64_t right_of(int64_t i, int64_t n) { return i == n - 1 ? 0 : i + 1; }
+/* i + d mod n, for any offset d */
+static int64_t wrap(int64_t i, int64_t d, int64_t n)
+{
+    int64_t j = (i + d) % n;
+    return j < 0 ? j + n : j;
+}
+static int is_nnn(int model) { return model == ORACLE_QUARTIC_NNN || model == ORACLE_HARMONIC_NNN; }
 
 /* The force on one site from its own coordinate and its two neighbours'. */
 static double force_site(int model, double qm, double q, double qp)
@@ -45,14 +58,40 @@ static double force_site(int model, double qm, double q, double qp)
     return -q + (qp - 2.0 * q + qm);
 }
 
-/* Energy density of one site: kinetic + on-site potential + the potential of
- * the bond to the right neighbour. Its gradient gives the force above. */
-static double energy_site(int model, double q, double p, double qp)
+/* The same with the two second-neighbour bonds added. */
+static double force_site_nnn(int model, double qmm, double qm, double q, double qp, double qpp)
 {
-    double d = qp - q;
+    if (model == ORACLE_QUARTIC_NNN) {
+        double dr = qp - q, dl = q - qm;
+        double dr2 = qpp - q, dl2 = q - qmm;
+        return -(q + q * q * q) + dr * dr * dr - dl * dl * dl + dr2 * dr2 * dr2 - dl2 * dl2 * dl2;
+    }
+    return -q + (qp - 2.0 * q + qm) + (qpp - 2.0 * q + qmm);
+}
+
+/* Force on site i of the ring, any model. */
+static double force_at(int model, int64_t n, const double *q, int64_t i)
+{
+    if (is_nnn(model))
+        return force_site_nnn(model, q[wrap(i, -2, n)], q[left_of(i, n)], q[i], q[right_of(i, n)],
+                              q[wrap(i, 2, n)]);
+    return force_site(model, q[left_of(i, n)], q[i], q[right_of(i, n)]);
+}
+
+/* Energy density of one site: kinetic + on-site potential + the potential of
+ * the bond to the right neighbour (and, for the NNN models, of the bond to
+ * the second neighbour on the right). Its gradient gives the force above. */
+static double energy_site(int model, double q, double p, double qp, double qpp)
+{
+    double d = qp - q, d2 = qpp - q;
     if (model == ORACLE_QUARTIC)
         return p * p / 2.0 + q * q / 2.0 + q * q * q * q / 4.0 + d * d * d * d / 4.0;
-    return p * p / 2.0 + q * q / 2.0 + d * d / 2.0;
+    if (model == ORACLE_HARMONIC)
+        return p * p / 2.0 + q * q / 2.0 + d * d / 2.0;
+    if (model == ORACLE_QUARTIC_NNN)
+        return p * p / 2.0 + q * q / 2.0 + q * q * q * q / 4.0 + d * d * d * d / 4.0 +
+               d2 * d2 * d2 * d2 / 4.0;
+    return p * p / 2.0 + q * q / 2.0 + d * d / 2.0 + d2 * d2 / 2.0;
 }
 
 /* Eq. 3: one evaluation of the right-hand side over the whole chain. */
@@ -63,7 +102,7 @@ static void rhs(int model, int64_t n, const double *q, const double *p,
 #pragma omp parallel for num_threads(threads) schedule(static)
     for (i = 0; i < n; ++i) {
         kq[i] = p[i];
-        kp[i] = force_site(model, q[left_of(i, n)], q[i], q[right_of(i, n)]);
+        kp[i] = force_at(model, n, q, i);
     }
 }
 
@@ -85,7 +124,7 @@ void oracle_force(int model, int64_t n, const double *q, double *f)
 {
     int64_t i;
     for (i = 0; i < n; ++i)
-        f[i] = force_site(model, q[left_of(i, n)], q[i], q[right_of(i, n)]);
+        f[i] = force_at(model, n, q, i);
 }
 
 /*
@@ -140,7 +179,7 @@ double oracle_energy(int model, int64_t n, const double *q, const double *p)
     double sum = 0.0, comp = 0.0;
     int64_t i;
     for (i = 0; i < n; ++i) {
-        double e = energy_site(model, q[i], p[i], q[right_of(i, n)]);
+        double e = energy_site(model, q[i], p[i], q[right_of(i, n)], q[wrap(i, 2, n)]);
         double t = sum + e;
         if ((sum >= 0 ? sum : -sum) >= (e >= 0 ? e : -e))
             comp += (sum - t) + e;

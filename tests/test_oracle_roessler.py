@@ -108,3 +108,19 @@ def test_light_cone_sites_equal_full_ring():
     got = oracle.roessler_rk4_sites(x0, y0, z0, 0.01, 12, sites)
     for a, b in zip(got, full):
         assert np.array_equal(a, b[sites])
+
+
+def test_exact_dependence_range_is_one_site_per_stage():
+    """x couples to its neighbours directly in dx/dt, so the error front of a
+    cut-off chain moves one site per stage (Sec. 2.3): four per step."""
+    n, i, dt = 120, 60, 0.5
+    x0, y0, z0 = ics(n, 6)
+    for steps in (1, 2):
+        base = oracle.roessler_rk4(x0, y0, z0, dt, steps)
+        edge = 4 * steps
+        for d in (edge, -edge, edge + 1, -(edge + 1)):
+            v = [x0.copy(), y0.copy(), z0.copy()]
+            v[0][i + d] += 0.1
+            a = oracle.roessler_rk4(*v, dt, steps)
+            moved = any(a[k][i] != base[k][i] for k in range(3))
+            assert moved == (abs(d) <= edge), (steps, d)
