@@ -38,8 +38,11 @@ FP64_VECTOR_TFLOPS = 78.6
 # Roessler (three coordinates): right-hand side 7 ops (bond diff, two subs,
 # y + z, two fma, x - c) x 4 stages, stage arguments 3 fma x 3 stages,
 # accumulators 3 ops x 3 stages, final update 3 fma.
-OPS_PER_SU = {"quartic": 42, "harmonic": 30, "roessler": 49}
-FLOPS_PER_SU = {"quartic": 58, "harmonic": 42, "roessler": 75}
+# Second-neighbour bonds (quartic): the force is 12 ops per stage.
+OPS_PER_SU = {"quartic": 42, "harmonic": 26, "roessler": 49, "quartic_nnn": 62,
+              "harmonic_nnn": 38}
+FLOPS_PER_SU = {"quartic": 58, "harmonic": 38, "roessler": 75, "quartic_nnn": 78,
+                "harmonic_nnn": 50}
 # Bytes per site-update of one pass: read q, p and write q, p once.
 BYTES_PER_SITE_PASS = {"fp64": 32, "fp32_kahan": 32}   # FP32: q, p, cq, cp
 BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
@@ -364,16 +367,20 @@ def variant_batch(dt, dev, steps=2000, count=4096):
         dtype = torch.float64 if prec == "fp64" else torch.float32
         chains = [Chain(*workloads.chain_ics_torch(int(n_), 1000 + i, dev, dtype), dt, prec=prec,
                         device=dev) for i, n_ in enumerate(lengths)]
-        b = Batch(chains, max_steps=steps, sites_per_lane=4, kdepth=16)
-        b.step(24)
-        b.check()
-        t = ev_seconds(lambda: b.step(steps), chains[0].stream)
-        b.check()
-        plan = b.plan()
-        out[prec] = {"su_per_s": tot * steps / t, "ms": t * 1e3, "grid_blocks": plan["grid_blocks"],
-                     "resident_chains": plan["resident_chains"],
-                     "clusters": plan["total_clusters"]}
-        b.close()
+        for depth in (16, 32):
+            b = Batch(chains, max_steps=steps, sites_per_lane=4, kdepth=depth)
+            b.step(24)
+            b.check()
+            t = ev_seconds(lambda: b.step(steps), chains[0].stream)
+            b.check()
+            plan = b.plan()
+            r = {"su_per_s": tot * steps / t, "ms": t * 1e3, "kdepth": depth,
+                 "grid_blocks": plan["grid_blocks"], "resident_chains": plan["resident_chains"],
+                 "clusters": plan["total_clusters"]}
+            b.close()
+            if prec not in out or r["su_per_s"] > out[prec]["su_per_s"]:
+                out[prec] = r
+            out.setdefault(f"{prec}_by_depth", {})[str(depth)] = r["su_per_s"]
         if prec == "fp64":
             # the same chains, one step call per chain (100 steps each)
             torch.cuda.synchronize()
@@ -517,6 +524,30 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None):
     return out
 
 
+def variant_nnn(qd, pd, dt, n, dev, steps=480):
+    """The quartic chain with second-neighbour bonds on the bench chain: the
+    library plan (halo 4 per step) and the per-stage baseline, device time of
+    `steps` steps (best of 3)."""
+    from paper_1412_0544_amd import Chain
+    out = {}
+    for method in ("fused", "naive"):
+        ch = Chain(qd, pd, dt, model="quartic_nnn", method=method, device=dev)
+        ch.step(32)
+        k = steps if method == "fused" else 20
+        best = min(ev_seconds(lambda: ch.step(k), ch.stream) for _ in range(3))
+        plan = ch.plan()
+        ch.close()
+        out[method] = {"su_per_s": n * k / best,
+                       "plan": {x: plan[x] for x in ("sites_per_lane", "waves_per_cluster",
+                                                     "kdepth", "halo", "tile")}}
+    f = out["fused"]
+    launches = fused_launches({"resident": 0, "kdepth": f["plan"]["kdepth"]}, steps)
+    out["roofline"] = roofline(n, steps / launches, n * steps / f["su_per_s"] / launches,
+                               model="quartic_nnn")
+    out["speedup_fused_vs_naive"] = f["su_per_s"] / out["naive"]["su_per_s"]
+    return out
+
+
 def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     """Other rows of the hot path, each measured at its own configuration."""
     from paper_1412_0544_amd import Chain, autotune
@@ -545,6 +576,8 @@ def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     res["precision"] = variant_precision(n, dt, dev)
     log("[bench] variant: 4096-chain batch")
     res["batch4096"] = variant_batch(dt, dev)
+    log("[bench] variant: next-nearest-neighbour coupling")
+    res["quartic_nnn"] = variant_nnn(qd, pd, dt, n, dev)
     log("[bench] variant: Roessler chain, the paper's protocol")
     res["roessler"] = variant_roessler(dev, dt)
     if serve_jobs:

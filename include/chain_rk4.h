@@ -9,6 +9,10 @@
  *     dq_i/dt = p_i,   dp_i/dt = F_i(q_{i-1}, q_i, q_{i+1})
  *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
  *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
+ * the same two with next-nearest-neighbour bonds (the generalisation named in
+ * Sec. 4; every site also bonded to its second neighbours, same potential):
+ *   quartic NNN:  F_i += (q_{i+2} - q_i)^3 - (q_i - q_{i-2})^3
+ *   harmonic NNN: F_i += (q_{i+2} - 2 q_i + q_{i-2})
  * and the paper's own test system, the Roessler chain (Sec. 3.1 Eq. 6-7),
  * three coordinates per site with a = 0.2, b = 1, c = 9:
  *   dx_i/dt = -y_i - z_i + (x_{i+1} - 2 x_i + x_{i-1})
@@ -44,9 +48,13 @@ typedef struct chain_rk4_batch chain_rk4_batch;
 enum chain_model {
     CHAIN_QUARTIC = 0,   /* quartic on-site and bond potentials (formula above) */
     CHAIN_HARMONIC = 1,  /* the linear chain (formula above) */
-    CHAIN_ROESSLER = 2   /* the Roessler chain (formula above): FP64 only,
+    CHAIN_ROESSLER = 2,  /* the Roessler chain (formula above): FP64 only,
                             created with chain_rk4_create3, no energy, no
                             batches, never kept resident on chip */
+    CHAIN_QUARTIC_NNN = 3, /* quartic chain with second-neighbour bonds; no
+                              batches, never kept resident on chip */
+    CHAIN_HARMONIC_NNN = 4 /* harmonic chain with second-neighbour bonds; the
+                              same restrictions */
 };
 
 enum chain_prec {
@@ -58,9 +66,12 @@ enum chain_prec {
 
 enum chain_method {
     CHAIN_FUSED = 0,  /* one pass over memory per `kdepth` steps: each tile is
-                         extended by 4*kdepth sites per side that are recomputed
-                         and discarded (Sec. 2.3, the overlap of s sites per side
-                         per step, carried over several steps) */
+                         extended by reach*kdepth sites per side that are
+                         recomputed and discarded (Sec. 2.3, the overlap per
+                         side per step, carried over several steps). reach is
+                         2 for the quartic and harmonic chains (dq/dt = p is
+                         local, so an edge error advances one site per two
+                         stages), 4 for the NNN and Roessler chains */
     CHAIN_NAIVE = 1   /* the standard implementation: one kernel per RK stage,
                          every stage result goes through memory (Sec. 2.2) */
 };
@@ -92,7 +103,7 @@ typedef struct chain_rk4_desc {
     int32_t sites_per_lane;  /* fused: sites per GPU lane, 0 = default, else
                                 4, 8 or 16 */
     int32_t kdepth;          /* fused: RK4 steps per pass over memory, 0 =
-                                default, else 1..16 */
+                                default, else 1..32 */
     int32_t waves_per_cluster; /* fused: wavefronts that share one cluster
                                 (edge values through LDS), 0 = default,
                                 else 1, 2, 4 or 8 */
@@ -106,7 +117,7 @@ typedef struct chain_rk4_plan {
                                     whole ring stays on chip for all steps */
     int32_t waves_per_cluster, reserved;
     int64_t tile;                /* output sites per cluster and pass */
-    int64_t halo;                /* recomputed sites per side (4 * kdepth) */
+    int64_t halo;                /* recomputed sites per side (reach * kdepth) */
     int64_t waves;               /* clusters per pass */
     double overlap_factor;       /* sites computed / sites kept per pass,
                                     1 + 2*halo/tile (Sec. 2.3) */
@@ -152,7 +163,8 @@ int chain_rk4_step(chain_rk4 *h, int64_t nsteps);
 /*
  * Total energy of the current state, in FP64, written to *e_out (host).
  * Quartic: sum_i p_i^2/2 + q_i^2/2 + q_i^4/4 + (q_{i+1}-q_i)^4/4;
- * harmonic: sum_i p_i^2/2 + q_i^2/2 + (q_{i+1}-q_i)^2/2. For CHAIN_FP32_KAHAN
+ * harmonic: sum_i p_i^2/2 + q_i^2/2 + (q_{i+1}-q_i)^2/2; the NNN models add
+ * (q_{i+2}-q_i)^4/4 or (q_{i+2}-q_i)^2/2 per site. For CHAIN_FP32_KAHAN
  * each coordinate enters as (hi - carry) in FP64. The sum order is fixed for
  * a given n, so repeated calls agree bitwise. Synchronises the stream.
  * Returns CHAIN_ENONFINITE (with *e_out set) if the energy is NaN or Inf,
@@ -192,7 +204,7 @@ const char *chain_rk4_last_error(void);
  * claim work items in a fixed order from a device counter: first one item
  * per short ring (n <= 1024), which stays on chip for all of its steps, then,
  * pass by pass, one item per (chain, cluster), each the same cluster pass as
- * the fused method (a cluster of 64*sites_per_lane*4 sites, 4*kdepth of them
+ * the fused method (a cluster of 64*sites_per_lane*4 sites, 2*kdepth of them
  * recomputed per side, Sec. 2.3). A cluster's pass e starts once its own
  * cluster and its two neighbours have finished pass e-1 (per-cluster progress
  * flags), so passes of different clusters and chains overlap. Every chain
@@ -214,7 +226,7 @@ typedef struct chain_rk4_batch_desc {
     int64_t max_clusters;    /* capacity for chain_rk4_batch_rebind: clusters
                                 over all tiled chains (0 = what `hs` needs) */
     int32_t sites_per_lane;  /* 0 = default (4), else 4, 8 or 16 */
-    int32_t kdepth;          /* steps per pass, 0 = default (16), else 2..16 */
+    int32_t kdepth;          /* steps per pass, 0 = default (16), else 2..32 */
     int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
                                 once; any value >= 1 gives the same results */
     int32_t flags;           /* 0, or CHAIN_BATCH_FENCES */

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchainrk4.so")
 
 CHAIN_QUARTIC, CHAIN_HARMONIC, CHAIN_ROESSLER = 0, 1, 2
+CHAIN_QUARTIC_NNN, CHAIN_HARMONIC_NNN = 3, 4
 CHAIN_FP64, CHAIN_FP32_KAHAN = 0, 1
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT = 1, 2

@@ -23,7 +23,7 @@ _lock = threading.Lock()
 
 SITES = (4, 8, 16)
 WAVES = (1, 2, 4, 8)
-DEPTHS = (1, 2, 4, 6, 8, 12, 16)
+DEPTHS = (1, 2, 4, 6, 8, 12, 16, 24, 32)
 
 
 def default_candidates(prec: str = "fp64"):
@@ -31,7 +31,7 @@ def default_candidates(prec: str = "fp64"):
     out = []
     for s in (8, 16):
         for w in WAVES:
-            for k in (4, 8, 12, 16):
+            for k in (8, 12, 16, 24, 32):
                 if 64 * s * w > 16 * k:
                     out.append((s, w, k))
     return out

@@ -11,7 +11,8 @@ import torch
 
 from . import _lib as L
 
-MODELS = {"quartic": L.CHAIN_QUARTIC, "harmonic": L.CHAIN_HARMONIC}
+MODELS = {"quartic": L.CHAIN_QUARTIC, "harmonic": L.CHAIN_HARMONIC,
+          "quartic_nnn": L.CHAIN_QUARTIC_NNN, "harmonic_nnn": L.CHAIN_HARMONIC_NNN}
 PRECS = {"fp64": L.CHAIN_FP64, "fp32_kahan": L.CHAIN_FP32_KAHAN}
 METHODS = {"fused": L.CHAIN_FUSED, "naive": L.CHAIN_NAIVE}
 

@@ -81,16 +81,18 @@ struct Shape {
 int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
     if (sites_per_lane != 0 && sites_per_lane != 4 && sites_per_lane != 8 && sites_per_lane != 16)
         return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16");
-    if (kdepth != 0 && (kdepth < 2 || kdepth > 16))
-        return fail(CHAIN_EINVAL, "batch kdepth must be 0 or 2..16");
+    if (kdepth != 0 && (kdepth < 2 || kdepth > 32))
+        return fail(CHAIN_EINVAL, "batch kdepth must be 0 or 2..32");
     Shape sh;
     sh.sites = sites_per_lane ? sites_per_lane : kDefaultBatchSites;
     sh.depth = kdepth ? kdepth : kDefaultBatchDepth;
     const int64_t E = 64 * static_cast<int64_t>(sh.sites) * kBatchWaves;
-    // every cluster keeps at least `halo` sites (so only neighbouring
-    // clusters overlap), with room to spare for the 4-site rounding
-    while (E < 16 * static_cast<int64_t>(sh.depth) + 16 && sh.depth > 2) --sh.depth;
-    sh.halo = 4 * static_cast<int64_t>(sh.depth);
+    // A step's wrong edge values travel 2 sites into a cluster of the
+    // quartic or harmonic chain (dq/dt = p is local). Every cluster keeps at
+    // least `halo` sites (so only neighbouring clusters overlap), with room to
+    // spare for the 4-site rounding.
+    while (E < 8 * static_cast<int64_t>(sh.depth) + 16 && sh.depth > 2) --sh.depth;
+    sh.halo = 2 * static_cast<int64_t>(sh.depth);
     sh.tile_max = E - 2 * sh.halo;
     *out = sh;
     return CHAIN_OK;
@@ -112,8 +114,8 @@ int check_handles(chain_rk4 *const *hs, int count, int model, int prec) {
             return fail(CHAIN_EINVAL, "handle %d does not use the fused method", i);
         if (hs[i]->d.model != model || hs[i]->d.prec != prec)
             return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
-        if (hs[i]->d.model == CHAIN_ROESSLER)
-            return fail(CHAIN_EINVAL, "handle %d: batches take the two-coordinate models only", i);
+        if (hs[i]->d.model != CHAIN_QUARTIC && hs[i]->d.model != CHAIN_HARMONIC)
+            return fail(CHAIN_EINVAL, "handle %d: batches take the quartic and harmonic models only", i);
     }
     std::vector<chain_rk4 *> sorted(hs, hs + count);
     std::sort(sorted.begin(), sorted.end());

@@ -66,8 +66,11 @@ constexpr int kDefaultWaves = 4;
 // sites per lane (the fastest shape at N = 2^20 in a sweep over S, W, k).
 constexpr int kDefaultSitesRoessler = 4;
 constexpr int kDefaultWavesRoessler = 4;
-constexpr int kDefaultDepth = 16;
-constexpr int kMaxDepth = 16;
+// Default depth: as many steps as a halo of 64 sites per side covers (32 for
+// the NN chains, 16 for the NNN and Roessler chains; the fastest depth of a
+// sweep over S, W, k at N = 2^24 and N = 2^20).
+constexpr int kDefaultHalo = 64;
+constexpr int kMaxDepth = 32;
 
 bool valid_sites(int s) { return s == 4 || s == 8 || s == 16; }
 bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
@@ -76,7 +79,8 @@ int check_desc(const chain_rk4_desc *d) {
     if (!d) return fail(CHAIN_EINVAL, "descriptor is NULL");
     if (d->n < 1) return fail(CHAIN_EINVAL, "n must be >= 1 (got %lld)", (long long)d->n);
     if (d->n > (int64_t(1) << 40)) return fail(CHAIN_EINVAL, "n too large");
-    if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC && d->model != CHAIN_ROESSLER)
+    if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC && d->model != CHAIN_ROESSLER &&
+        d->model != CHAIN_QUARTIC_NNN && d->model != CHAIN_HARMONIC_NNN)
         return fail(CHAIN_EINVAL, "unknown model %d", d->model);
     if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN)
         return fail(CHAIN_EINVAL, "unknown precision %d", d->prec);
@@ -146,11 +150,27 @@ Layout layout(const chain_rk4_desc *d) {
 }
 
 
+// Sites per side that one step's wrong edge values travel into a cluster
+// (Sec. 2.3: one per stage and coupling range for a field that couples every
+// coordinate, as the Roessler chain's x; for dq/dt = p with coupling only in
+// dp/dt the stage arguments of stages 1 and 2 move q locally, so the front
+// advances one site per two stages).
+int64_t step_reach(int model) {
+    switch (model) {
+    case CHAIN_QUARTIC:
+    case CHAIN_HARMONIC: return 2;
+    case CHAIN_QUARTIC_NNN:
+    case CHAIN_HARMONIC_NNN: return 4;
+    default: return 4;  // CHAIN_ROESSLER
+    }
+}
+
 Plan make_plan(const chain_rk4_desc *d) {
     Plan P;
     if (d->method != CHAIN_FUSED) return P;
     const bool roessler = d->model == CHAIN_ROESSLER;
-    if (!roessler && !(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites &&
+    const bool nn = d->model == CHAIN_QUARTIC || d->model == CHAIN_HARMONIC;
+    if (nn && !(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites &&
         d->sites_per_lane == 0 && d->kdepth == 0 && d->waves_per_cluster == 0) {
         P.resident = true;
         return P;
@@ -161,11 +181,12 @@ Plan make_plan(const chain_rk4_desc *d) {
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
                           : roessler             ? kDefaultWavesRoessler
                                                  : kDefaultWaves;
-    P.depth = d->kdepth ? d->kdepth : kDefaultDepth;
+    const int64_t reach = step_reach(d->model);
+    P.depth = d->kdepth ? d->kdepth : static_cast<int>(kDefaultHalo / reach);
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
-    // the kept part of a cluster must stay positive: E > 8*depth
-    while (E <= 8 * P.depth && P.depth > 1) --P.depth;
-    P.halo = 4 * static_cast<int64_t>(P.depth);
+    // the kept part of a cluster must stay positive: E > 2*halo
+    while (E <= 2 * reach * P.depth && P.depth > 1) --P.depth;
+    P.halo = reach * static_cast<int64_t>(P.depth);
     P.tile = E - 2 * P.halo;
     P.waves = (d->n + P.tile - 1) / P.tile;
     return P;

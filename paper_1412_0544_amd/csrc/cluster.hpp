@@ -4,6 +4,8 @@
 // goes through these two functions, so every launch shape gives the same bits.
 #pragma once
 
+#include <type_traits>
+
 #include "launch.hpp"
 #include "rk4_device.hpp"
 
@@ -54,6 +56,17 @@ struct EdgeSlots {
     R last[2][WPB];
 };
 
+// The same for next-nearest-neighbour coupling: two coordinates per edge.
+template <class R, int WPB>
+struct EdgeSlots2 {
+    R first[2][2][WPB];   // [parity][0: Q_0, 1: Q_1][wavefront]
+    R last[2][2][WPB];    // [parity][0: Q_{S-1}, 1: Q_{S-2}][wavefront]
+};
+
+template <int M, class R, int WPB>
+using SlotsOf = typename std::conditional<coupling_range<M>() == 2, EdgeSlots2<R, WPB>,
+                                          EdgeSlots<R, WPB>>::type;
+
 // One stage for the S sites of this lane. The right neighbour's first
 // coordinate comes in, this lane forms its last bond term, and that term goes
 // to the right neighbour lane as its left bond term. At a wavefront edge
@@ -80,6 +93,66 @@ __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&
         if (lane == 0 && wic > 0) bl0 = ModelOps<M, R>::bond(first - slots->last[parity][wib - 1]);
     }
     stage_sites<M, S, STAGE>(Q, P, q, p, aq, ap, bl0, brS, c);
+}
+
+// The same with next-nearest-neighbour coupling: the right neighbour lane's
+// first two coordinates come in, this lane forms the three bond terms that
+// reach past its last site, and they go to the right neighbour lane as the
+// three that reach past its first site. At a wavefront edge inside the
+// cluster lane 0 forms them itself from the left wavefront's last two
+// coordinates (the same operations on the same values).
+template <int M, int S, int STAGE, int W, int WPB, class R>
+__device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
+                                               R (&aq)[S], R (&ap)[S], const StepConsts<R> &c,
+                                               EdgeSlots2<R, WPB> *slots, int lane, int wib,
+                                               int wic, int parity) {
+    using Ops = ModelOps<M, R>;
+    const R f0 = (STAGE == 1) ? q[0] : Q[0];
+    const R f1 = (STAGE == 1) ? q[1] : Q[1];
+    const R l1 = (STAGE == 1) ? q[S - 2] : Q[S - 2];
+    const R l0 = (STAGE == 1) ? q[S - 1] : Q[S - 1];
+    R r0 = from_right(f0), r1 = from_right(f1);
+    if constexpr (W > 1) {
+        if (lane == 0) {
+            slots->first[parity][0][wib] = f0;
+            slots->first[parity][1][wib] = f1;
+        }
+        if (lane == 63) {
+            slots->last[parity][0][wib] = l0;
+            slots->last[parity][1][wib] = l1;
+        }
+        __syncthreads();
+        if (lane == 63 && wic + 1 < W) {
+            r0 = slots->first[parity][0][wib + 1];
+            r1 = slots->first[parity][1][wib + 1];
+        }
+    }
+    const R b1rS = Ops::bond(r0 - l0);
+    const R b2rS2 = Ops::bond(r0 - l1);
+    const R b2rS1 = Ops::bond(r1 - l0);
+    R b1l0 = from_left(b1rS), b2lm2 = from_left(b2rS2), b2lm1 = from_left(b2rS1);
+    if constexpr (W > 1) {
+        if (lane == 0 && wic > 0) {
+            const R L0 = slots->last[parity][0][wib - 1];
+            const R L1 = slots->last[parity][1][wib - 1];
+            b1l0 = Ops::bond(f0 - L0);
+            b2lm2 = Ops::bond(f0 - L1);
+            b2lm1 = Ops::bond(f1 - L0);
+        }
+    }
+    stage_sites_nnn<M, S, STAGE>(Q, P, q, p, aq, ap, b1l0, b2lm2, b2lm1, b1rS, b2rS2, b2rS1, c);
+}
+
+// Dispatch on the coupling range of the model.
+template <int M, int S, int STAGE, int W, int WPB, class R>
+__device__ __forceinline__ void any_lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
+                                               R (&aq)[S], R (&ap)[S], const StepConsts<R> &c,
+                                               SlotsOf<M, R, WPB> *slots, int lane, int wib,
+                                               int wic, int parity) {
+    if constexpr (coupling_range<M>() == 2)
+        lane_stage_nnn<M, S, STAGE, W, WPB>(Q, P, q, p, aq, ap, c, slots, lane, wib, wic, parity);
+    else
+        lane_stage<M, S, STAGE, W, WPB>(Q, P, q, p, aq, ap, c, slots, lane, wib, wic, parity);
 }
 
 // Device-coherent element access (memory scope: agent). Stores are written
@@ -208,15 +281,17 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
 
 // One cluster pass: the cluster holds sites [e0, e0 + 64*S*W) of the
 // unwrapped ring (wrapped mod n on load), advances them `ksteps` steps and
-// stores the sites at cluster-local positions [halo, halo + keep). The caller
-// guarantees halo >= 4*ksteps and halo + keep <= 64*S*W, so the stored sites
-// are exact (the wrong values entering at the cluster edges travel one site
-// per stage). All wavefronts of the cluster must call this together.
+// stores the sites at cluster-local positions [halo, halo + keep). The wrong
+// values that enter at the cluster edges move 2*range sites per step: dq/dt =
+// p is local, so a coordinate error reaches the force of the next site only
+// every second stage. The caller guarantees halo >= 2*range*ksteps and
+// halo + keep <= 64*S*W, so the stored sites are exact. All wavefronts of
+// the cluster must call this together.
 template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false>
 __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
                                             int64_t e0, int64_t halo, int64_t keep, int ksteps,
-                                            double dt, EdgeSlots<R, WPB> *slots, int lane, int wib,
-                                            int wic) {
+                                            double dt, SlotsOf<M, R, WPB> *slots, int lane,
+                                            int wib, int wic) {
     constexpr int E = 64 * S * W;
     const int lo = (wic * 64 + lane) * S;
     const int64_t s0 = e0 + lo;
@@ -225,10 +300,10 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     const StepConsts<R> c(dt);
     R Q[S], P[S], aq[S], ap[S];
     for (int k = 0; k < ksteps; ++k) {
-        lane_stage<M, S, 1, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
-        lane_stage<M, S, 2, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
-        lane_stage<M, S, 3, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
-        lane_stage<M, S, 4, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
+        any_lane_stage<M, S, 1, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
+        any_lane_stage<M, S, 2, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
+        any_lane_stage<M, S, 3, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
+        any_lane_stage<M, S, 4, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
         if constexpr (KAHAN)
             final_update_kahan<S>(st.q, st.p, st.cq, st.cp, aq, ap, c);
         else

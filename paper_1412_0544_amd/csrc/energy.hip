@@ -1,9 +1,10 @@
 // energy.hip -- total energy of a chain in FP64, and a zero-fill kernel.
 //
 // H = sum_i e_i with e_i the kinetic and on-site energy of site i plus the
-// potential of its bond to site i+1 (the Hamiltonian whose gradient is the
-// force of the model). For the FP32 state with compensated update each
-// coordinate enters as (hi - carry), in FP64. Each block sums a fixed,
+// potential of its bond to site i+1 (and to site i+2 with second-neighbour
+// bonds): the Hamiltonian whose gradient is the force of the model. For the
+// FP32 state with compensated update each coordinate enters as
+// (hi - carry), in FP64. Each block sums a fixed,
 // strided subset of sites and reduces it with a fixed tree; one finishing
 // block sums the partials the same way. The grid depends only on n, so the
 // result is the same bits on every call.
@@ -50,7 +51,13 @@ __global__ __launch_bounds__(kEnergyThreads) void energy_partial(StateRef y, int
         double q, p, qn, pn;
         coords<R, KAHAN>(y, i, q, p);
         coords<R, KAHAN>(y, ip, qn, pn);
-        acc += ModelOps<M, double>::energy(q, p, qn - q);
+        if constexpr (coupling_range<M>() == 2) {
+            double qnn, pnn;
+            coords<R, KAHAN>(y, wrap_index(i + 2, n), qnn, pnn);
+            acc += ModelOps<M, double>::energy2(q, p, qn - q, qnn - q);
+        } else {
+            acc += ModelOps<M, double>::energy(q, p, qn - q);
+        }
     }
     const double s = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -87,14 +94,22 @@ int energy_blocks(int64_t n) {
     return static_cast<int>(nb);
 }
 
+template <int M>
+hipError_t energy_dispatch_prec(int prec, StateRef y, int64_t n, double *partials, double *result,
+                                hipStream_t s) {
+    return prec == 0 ? energy_dispatch<M, double, false>(y, n, partials, result, s)
+                     : energy_dispatch<M, float, true>(y, n, partials, result, s);
+}
+
 hipError_t launch_energy(int model, int prec, StateRef y, int64_t n, double *partials,
                          double *result, hipStream_t s) {
-    if (model == kQuartic) {
-        return prec == 0 ? energy_dispatch<kQuartic, double, false>(y, n, partials, result, s)
-                         : energy_dispatch<kQuartic, float, true>(y, n, partials, result, s);
+    switch (model) {
+    case kQuartic: return energy_dispatch_prec<kQuartic>(prec, y, n, partials, result, s);
+    case kHarmonic: return energy_dispatch_prec<kHarmonic>(prec, y, n, partials, result, s);
+    case kQuarticNNN: return energy_dispatch_prec<kQuarticNNN>(prec, y, n, partials, result, s);
+    case kHarmonicNNN: return energy_dispatch_prec<kHarmonicNNN>(prec, y, n, partials, result, s);
+    default: return hipErrorInvalidValue;
     }
-    return prec == 0 ? energy_dispatch<kHarmonic, double, false>(y, n, partials, result, s)
-                     : energy_dispatch<kHarmonic, float, true>(y, n, partials, result, s);
 }
 
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s) {

@@ -4,10 +4,12 @@
 // Fused kernel (the GPU form of the granular scheme of Sec. 2.3): a cluster is
 // W wavefronts holding E = 64*S*W consecutive sites, S per lane, in
 // registers. The middle `tile` sites are kept; `halo` sites on each side are
-// loaded only to be recomputed and discarded. With halo = 4*ksteps the wrong
-// values that enter at the cluster edges (one site per stage, Sec. 2.3) never
-// reach the kept sites, so one pass over memory advances the chain by
-// `ksteps` steps. Inside a wavefront neighbour values move by DPP lane
+// loaded only to be recomputed and discarded. The wrong values that enter at
+// the cluster edges move one site per stage in general (Sec. 2.3), but only
+// one per two stages here, since dq/dt = p is local: with halo =
+// 2*range*ksteps (range 1, or 2 with second-neighbour bonds) they never reach
+// the kept sites, so one pass over memory advances the chain by `ksteps`
+// steps. Inside a wavefront neighbour values move by DPP lane
 // shifts; between the wavefronts of a cluster only the two edge coordinates
 // go through LDS, with one barrier per stage. Clusters never talk to each
 // other. Input and output are different buffers (ping-pong): clusters
@@ -32,7 +34,7 @@ __global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass
     const int wib = threadIdx.x >> 6;                  // wavefront in block
     const int wic = wib % W;                           // wavefront in cluster
     const int64_t cluster = static_cast<int64_t>(blockIdx.x) * CPB + wib / W;
-    __shared__ EdgeSlots<R, WPB> slots;
+    __shared__ SlotsOf<M, R, WPB> slots;
     // W > 1: a block is exactly one cluster and the grid has no extra blocks,
     // so every wavefront reaches every barrier. W = 1: no barriers.
     if (cluster >= a.waves) return;
@@ -94,13 +96,20 @@ hipError_t resident_dispatch(const ResidentRun &a, hipStream_t st) {
 
 }  // namespace
 
+template <int M>
+hipError_t fused_dispatch_prec(int prec, int s, int w, const FusedPass &a, hipStream_t st) {
+    return prec == 0 ? fused_dispatch_s<M, double, false>(s, w, a, st)
+                     : fused_dispatch_s<M, float, true>(s, w, a, st);
+}
+
 hipError_t launch_fused(int model, int prec, int s, int w, const FusedPass &a, hipStream_t st) {
-    if (model == kQuartic) {
-        return prec == 0 ? fused_dispatch_s<kQuartic, double, false>(s, w, a, st)
-                         : fused_dispatch_s<kQuartic, float, true>(s, w, a, st);
+    switch (model) {
+    case kQuartic: return fused_dispatch_prec<kQuartic>(prec, s, w, a, st);
+    case kHarmonic: return fused_dispatch_prec<kHarmonic>(prec, s, w, a, st);
+    case kQuarticNNN: return fused_dispatch_prec<kQuarticNNN>(prec, s, w, a, st);
+    case kHarmonicNNN: return fused_dispatch_prec<kHarmonicNNN>(prec, s, w, a, st);
+    default: return hipErrorInvalidValue;
     }
-    return prec == 0 ? fused_dispatch_s<kHarmonic, double, false>(s, w, a, st)
-                     : fused_dispatch_s<kHarmonic, float, true>(s, w, a, st);
 }
 
 size_t resident_lds_bytes(int prec, int64_t n) {

@@ -18,7 +18,9 @@ struct StateRef {
 
 // One pass of the fused kernel: every cluster (W wavefronts) owns `tile`
 // output sites and recomputes `halo` sites on each side, advancing
-// `ksteps` <= halo/4 steps. `waves` counts clusters.
+// `ksteps` <= halo / reach steps (reach: sites a step's edge error travels,
+// 2 for the NN chains, 4 for the NNN and Roessler chains). `waves` counts
+// clusters.
 struct FusedPass {
     StateRef in, out;
     int64_t n;
@@ -111,7 +113,7 @@ struct BatchArgs {
     unsigned long long *counter;   // next unclaimed item
     int32_t *error;                // set when a bounded wait expires
     int64_t total_items;
-    int64_t halo;                  // 4 * depth
+    int64_t halo;                  // 2 * depth
     int32_t n_resident, n_tiled;
     int32_t max_passes;
     int32_t depth;                 // steps of a full pass

@@ -28,9 +28,18 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
 
     const R Qj = aq[i];
     const R Pj = ap[i];
-    const R bl = ModelOps<M, R>::bond(Qj - aq[im]);
-    const R br = ModelOps<M, R>::bond(aq[ip] - Qj);
-    const R F = site_force<M, R>(bl, br, Qj);
+    R F;
+    if constexpr (coupling_range<M>() == 2) {
+        const R b1l = ModelOps<M, R>::bond(Qj - aq[im]);
+        const R b1r = ModelOps<M, R>::bond(aq[ip] - Qj);
+        const R b2l = ModelOps<M, R>::bond(Qj - aq[wrap_index(i - 2, n)]);
+        const R b2r = ModelOps<M, R>::bond(aq[wrap_index(i + 2, n)] - Qj);
+        F = site_force2<M, R>(b1l, b1r, b2l, b2r, Qj);
+    } else {
+        const R bl = ModelOps<M, R>::bond(Qj - aq[im]);
+        const R br = ModelOps<M, R>::bond(aq[ip] - Qj);
+        F = site_force<M, R>(bl, br, Qj);
+    }
     const R qj = yq[i];
     const R pj = yp[i];
 
@@ -85,14 +94,22 @@ hipError_t naive_dispatch(StateRef y, const NaiveBufs &b, int64_t n, double dt, 
 
 }  // namespace
 
+template <int M>
+hipError_t naive_dispatch_prec(int prec, StateRef y, const NaiveBufs &b, int64_t n, double dt,
+                               hipStream_t s) {
+    return prec == 0 ? naive_dispatch<M, double, false>(y, b, n, dt, s)
+                     : naive_dispatch<M, float, true>(y, b, n, dt, s);
+}
+
 hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,
                              double dt, hipStream_t s) {
-    if (model == kQuartic) {
-        return prec == 0 ? naive_dispatch<kQuartic, double, false>(y, b, n, dt, s)
-                         : naive_dispatch<kQuartic, float, true>(y, b, n, dt, s);
+    switch (model) {
+    case kQuartic: return naive_dispatch_prec<kQuartic>(prec, y, b, n, dt, s);
+    case kHarmonic: return naive_dispatch_prec<kHarmonic>(prec, y, b, n, dt, s);
+    case kQuarticNNN: return naive_dispatch_prec<kQuarticNNN>(prec, y, b, n, dt, s);
+    case kHarmonicNNN: return naive_dispatch_prec<kHarmonicNNN>(prec, y, b, n, dt, s);
+    default: return hipErrorInvalidValue;
     }
-    return prec == 0 ? naive_dispatch<kHarmonic, double, false>(y, b, n, dt, s)
-                     : naive_dispatch<kHarmonic, float, true>(y, b, n, dt, s);
 }
 
 }  // namespace chainrk4

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
     constexpr int RMAX = kBatchResidentSites;
     constexpr int SPT = RMAX / kBatchThreads;
     constexpr int E = 64 * S * W;
-    __shared__ EdgeSlots<R, WPB> slots;
+    __shared__ SlotsOf<M, R, WPB> slots;
     __shared__ __align__(16) R ring[2 * RMAX];
     __shared__ long long claimed;
     const int lane = threadIdx.x & 63;

@@ -8,6 +8,10 @@
 // quartic:  phi(d) = d^3, U'(q) = q + q^3
 // harmonic: phi(d) = d,   U'(q) = q
 // Every bond term phi(d_i) is computed once and used by both sites it joins.
+// The next-nearest-neighbour models (the generalisation of Sec. 4) add bonds
+// to the second neighbours with the same phi:
+//   F_i = ((phi(d_i) - phi(d_{i-1})) + (phi(e_i) - phi(e_{i-2}))) - U'(q_i),
+//   e_i = q_{i+2} - q_i.
 //
 // One RK4 step (Sec. 2.2 Eq. 3-5, classical tableau) per site, h = dt:
 //   stage j evaluates F at the stage argument (Q, P); k_j = (P, F)
@@ -23,7 +27,11 @@
 
 namespace chainrk4 {
 
-enum Model : int { kQuartic = 0, kHarmonic = 1 };
+enum Model : int { kQuartic = 0, kHarmonic = 1, kQuarticNNN = 3, kHarmonicNNN = 4 };
+
+// Farthest neighbour the force reads.
+template <int M>
+constexpr int coupling_range() { return (M == kQuarticNNN || M == kHarmonicNNN) ? 2 : 1; }
 
 // Fused multiply-add in the working precision (one rounding).
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -52,10 +60,35 @@ struct ModelOps<kHarmonic, R> {
     }
 };
 
+// The NNN models reuse the bond and on-site terms of their NN model.
+template <class R>
+struct ModelOps<kQuarticNNN, R> : ModelOps<kQuartic, R> {
+    // energy density of the site and its two right bonds, in FP64
+    __device__ __forceinline__ static double energy2(double q, double p, double d, double e) {
+        double q2 = q * q, d2 = d * d, e2 = e * e;
+        return 0.5 * (p * p) + 0.5 * q2 + 0.25 * (q2 * q2) + 0.25 * (d2 * d2) + 0.25 * (e2 * e2);
+    }
+};
+
+template <class R>
+struct ModelOps<kHarmonicNNN, R> : ModelOps<kHarmonic, R> {
+    __device__ __forceinline__ static double energy2(double q, double p, double d, double e) {
+        return 0.5 * (p * p) + 0.5 * (q * q) + 0.5 * (d * d) + 0.5 * (e * e);
+    }
+};
+
 // Force on a site from its left bond term, right bond term and coordinate.
 template <int M, class R>
 __device__ __forceinline__ R site_force(R bl, R br, R q) {
     return (br - bl) - ModelOps<M, R>::onsite(q);
+}
+
+// NNN force from the four bond terms that meet at the site:
+// b1l = phi(q_i - q_{i-1}), b1r = phi(q_{i+1} - q_i),
+// b2l = phi(q_i - q_{i-2}), b2r = phi(q_{i+2} - q_i).
+template <int M, class R>
+__device__ __forceinline__ R site_force2(R b1l, R b1r, R b2l, R b2r, R q) {
+    return ((b1r - b1l) + (b2r - b2l)) - ModelOps<M, R>::onsite(q);
 }
 
 // Step constants in the working precision.
@@ -118,6 +151,35 @@ template <class R>
 __device__ __forceinline__ R from_left_ring(R x) { return dpp<kDppWaveRor1>(x); }
 
 // ---------------------------------------------------------------------------
+// The per-site part of stage STAGE once the force F at the stage argument
+// (Q, P) is known: accumulate k_STAGE and form the next stage argument.
+// Stage 1 reads its argument from q, p; Qo, Po receive the next argument.
+// ---------------------------------------------------------------------------
+template <int STAGE, class R>
+__device__ __forceinline__ void site_update(R F, R Pj, R &Qo, R &Po, R qj, R pj, R &aq, R &ap,
+                                            const StepConsts<R> &c) {
+    if (STAGE == 1) {
+        // k1 = (p, F): its q part is p itself, folded into stage 2
+        ap = F;
+        Qo = fma_r(c.hh, Pj, qj);
+        Po = fma_r(c.hh, F, pj);
+    } else if (STAGE == 2) {
+        aq = fma_r(static_cast<R>(2), Pj, pj);
+        ap = fma_r(static_cast<R>(2), F, ap);
+        Qo = fma_r(c.hh, Pj, qj);
+        Po = fma_r(c.hh, F, pj);
+    } else if (STAGE == 3) {
+        aq = fma_r(static_cast<R>(2), Pj, aq);
+        ap = fma_r(static_cast<R>(2), F, ap);
+        Qo = fma_r(c.h, Pj, qj);
+        Po = fma_r(c.h, F, pj);
+    } else {
+        aq = aq + Pj;
+        ap = ap + F;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One RK4 stage over the S consecutive sites a lane holds.
 //   Q, P    stage argument (in), overwritten with the next stage argument
 //   q, p    state at the start of the step; after stage 4, the new state
@@ -143,25 +205,34 @@ __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (
         }
         const R F = site_force<M, R>(bl, br, Qj);
         bl = br;
-        if (STAGE == 1) {
-            // k1 = (p, F): its q part is p itself, folded into stage 2
-            ap[j] = F;
-            Q[j] = fma_r(c.hh, Pj, q[j]);
-            P[j] = fma_r(c.hh, F, p[j]);
-        } else if (STAGE == 2) {
-            aq[j] = fma_r(static_cast<R>(2), Pj, p[j]);
-            ap[j] = fma_r(static_cast<R>(2), F, ap[j]);
-            Q[j] = fma_r(c.hh, Pj, q[j]);
-            P[j] = fma_r(c.hh, F, p[j]);
-        } else if (STAGE == 3) {
-            aq[j] = fma_r(static_cast<R>(2), Pj, aq[j]);
-            ap[j] = fma_r(static_cast<R>(2), F, ap[j]);
-            Q[j] = fma_r(c.h, Pj, q[j]);
-            P[j] = fma_r(c.h, F, p[j]);
-        } else {
-            aq[j] = aq[j] + Pj;
-            ap[j] = ap[j] + F;
-        }
+        site_update<STAGE>(F, Pj, Q[j], P[j], q[j], p[j], aq[j], ap[j], c);
+    }
+}
+
+// One RK4 stage over S consecutive sites of a next-nearest-neighbour chain
+// (S >= 2). The edge bond terms come from the neighbour lanes:
+//   b1l0 = phi(Q_0 - Q_{-1}),  b2lm2 = phi(Q_0 - Q_{-2}),  b2lm1 = phi(Q_1 - Q_{-1}),
+//   b1rS = phi(Q_S - Q_{S-1}), b2rS2 = phi(Q_S - Q_{S-2}), b2rS1 = phi(Q_{S+1} - Q_{S-1}).
+template <int M, int S, int STAGE, class R>
+__device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
+                                                R (&aq)[S], R (&ap)[S], R b1l0, R b2lm2, R b2lm1,
+                                                R b1rS, R b2rS2, R b2rS1, const StepConsts<R> &c) {
+    static_assert(S >= 2, "a lane holds at least two sites");
+    R b1l = b1l0, b2l_lo = b2lm2, b2l_hi = b2lm1;  // phi of bonds (j-1, j), (j-2, j), (j-1, j+1)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const R Qj = (STAGE == 1) ? q[j] : Q[j];
+        const R Pj = (STAGE == 1) ? p[j] : P[j];
+        R b1r, b2r;
+        if (j + 1 < S) b1r = ModelOps<M, R>::bond(((STAGE == 1) ? q[j + 1] : Q[j + 1]) - Qj);
+        else b1r = b1rS;
+        if (j + 2 < S) b2r = ModelOps<M, R>::bond(((STAGE == 1) ? q[j + 2] : Q[j + 2]) - Qj);
+        else b2r = (j + 2 == S) ? b2rS2 : b2rS1;
+        const R F = site_force2<M, R>(b1l, b1r, b2l_lo, b2r, Qj);
+        b1l = b1r;
+        b2l_lo = b2l_hi;
+        b2l_hi = b2r;
+        site_update<STAGE>(F, Pj, Q[j], P[j], q[j], p[j], aq[j], ap[j], c);
     }
 }
 
@@ -195,20 +266,19 @@ __device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R 
     const R bl = ModelOps<M, R>::bond(Qj - Qm);
     const R br = ModelOps<M, R>::bond(Qp - Qj);
     const R F = site_force<M, R>(bl, br, Qj);
-    if (STAGE == 1) {
-        ap = F;
-        Qn = fma_r(c.hh, Pj, qj); Pn = fma_r(c.hh, F, pj);
-    } else if (STAGE == 2) {
-        aq = fma_r(static_cast<R>(2), Pj, pj);
-        ap = fma_r(static_cast<R>(2), F, ap);
-        Qn = fma_r(c.hh, Pj, qj); Pn = fma_r(c.hh, F, pj);
-    } else if (STAGE == 3) {
-        aq = fma_r(static_cast<R>(2), Pj, aq);
-        ap = fma_r(static_cast<R>(2), F, ap);
-        Qn = fma_r(c.h, Pj, qj); Pn = fma_r(c.h, F, pj);
-    } else {
-        aq = aq + Pj; ap = ap + F;
-    }
+    site_update<STAGE>(F, Pj, Qn, Pn, qj, pj, aq, ap, c);
+}
+
+// The same for one site of a next-nearest-neighbour chain (naive kernel).
+template <int M, int STAGE, class R>
+__device__ __forceinline__ void stage_one_nnn(R Qmm, R Qm, R Qj, R Qp, R Qpp, R Pj, R qj, R pj,
+                                              R &aq, R &ap, R &Qn, R &Pn, const StepConsts<R> &c) {
+    const R b1l = ModelOps<M, R>::bond(Qj - Qm);
+    const R b1r = ModelOps<M, R>::bond(Qp - Qj);
+    const R b2l = ModelOps<M, R>::bond(Qj - Qmm);
+    const R b2r = ModelOps<M, R>::bond(Qpp - Qj);
+    const R F = site_force2<M, R>(b1l, b1r, b2l, b2r, Qj);
+    site_update<STAGE>(F, Pj, Qn, Pn, qj, pj, aq, ap, c);
 }
 
 // ---------------------------------------------------------------------------

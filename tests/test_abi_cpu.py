@@ -42,7 +42,7 @@ def test_workspace_bytes():
     assert f(desc(n=1 << 20, method=1)) >= 10 * 8 * (1 << 20)
     for bad in (desc(n=0), desc(model=7), desc(prec=3), desc(dt=float("nan")),
                 desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
-                desc(kdepth=17), desc(kdepth=-1), desc(flags=64), desc(waves_per_cluster=3),
+                desc(kdepth=33), desc(kdepth=-1), desc(model=5), desc(model=2, prec=1), desc(flags=64), desc(waves_per_cluster=3),
                 desc(waves_per_cluster=16), desc(reserved=1)):
         assert f(bad) == 0
     assert lib.chain_rk4_workspace_bytes(None) == 0
@@ -124,7 +124,7 @@ def test_batch_cluster_count_helper():
     assert lib.chain_rk4_batch_clusters(1000, 0, 0) == 0        # kept on chip
 
     def expect(n, sites, depth):
-        keep = 64 * sites * 4 - 8 * depth                          # cluster minus both halos
+        keep = 64 * sites * 4 - 4 * depth                          # cluster minus both halos
         return -(-n // (keep - 4))
 
     # default shape: 4 sites per lane, depth 16
@@ -161,3 +161,19 @@ def test_roessler_arguments_are_validated_without_a_gpu():
     for dd, x, y, z, nb, want in cases:
         assert lib.chain_rk4_create3(ctypes.byref(dd), x, y, z, fake, nb, None,
                                      ctypes.byref(h)) == want
+
+
+def test_nnn_models_validate_like_the_nn_models():
+    lib = L.lib()
+    f = lambda d: lib.chain_rk4_workspace_bytes(ctypes.byref(d))
+    for m in (L.CHAIN_QUARTIC_NNN, L.CHAIN_HARMONIC_NNN):
+        for prec in (0, 1):
+            for method in (0, 1):
+                assert f(desc(model=m, prec=prec, method=method)) == \
+                    f(desc(model=0, prec=prec, method=method))
+    assert f(desc(model=3, kdepth=32)) > 0
+    h = L.H()
+    fake = 1 << 20
+    d = desc(model=L.CHAIN_QUARTIC_NNN)
+    assert lib.chain_rk4_create(ctypes.byref(d), fake, None, fake, f(d), None,
+                                ctypes.byref(h)) == L.CHAIN_EINVAL

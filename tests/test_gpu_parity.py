@@ -50,6 +50,8 @@ def test_fused_tiled_matches_oracle(n, sites, waves, depth):
                             kdepth=depth, resident=False)
     assert plan["resident"] == 0 and plan["sites_per_lane"] == sites
     assert plan["waves_per_cluster"] == waves
+    # a step's edge error reaches 2 sites into the cluster (dq/dt = p is local)
+    assert plan["halo"] == 2 * plan["kdepth"]
     qo, po = oracle_run("quartic", n, 1, 0.01, 100)
     assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
     eo = oracle.energy(oracle.QUARTIC, qo, po)
@@ -88,7 +90,7 @@ def test_tile_shapes_and_depths_identical_bits():
                   resident=False)
     for s in (4, 8, 16):
         for w in (1, 2, 4, 8):
-            for k in (2, 3, 8, 12, 16):
+            for k in (2, 3, 8, 12, 16, 24, 32):
                 got = gpu_run(q0, p0, 0.01, 24, sites_per_lane=s, waves_per_cluster=w, kdepth=k,
                               resident=False)
                 assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (s, w, k)
