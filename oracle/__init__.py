@@ -66,6 +66,10 @@ def _load():
                                        ctypes.c_int64, dp, dp, ctypes.c_int]
         lib.oracle_rk4_run.restype = ctypes.c_int
         lib.oracle_energy.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp]
+        lib.oracle_rk_tableau_run.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                              ctypes.c_int64, dp, dp, ctypes.c_int, dp, dp,
+                                              ctypes.c_int]
+        lib.oracle_rk_tableau_run.restype = ctypes.c_int
         lib.oracle_energy.restype = ctypes.c_double
         d = ctypes.c_double
         lib.oracle_roessler_rhs.argtypes = [ctypes.c_int64, dp, dp, dp, d, d, d, dp, dp, dp]
@@ -103,6 +107,23 @@ def rk4(model: int, q, p, dt: float, steps: int, threads: int = 1):
                                 int(threads))
     if rc != 0:
         raise MemoryError("oracle_rk4_run failed")
+    return q, p
+
+
+def rk_tableau(model: int, q, p, dt: float, steps: int, a, b, threads: int = 1):
+    """(q, p) after ``steps`` steps of the explicit Runge-Kutta method with
+    coefficients ``a`` (s x s, strictly lower triangle used) and weights ``b``."""
+    q = _f64(q).copy()
+    p = _f64(p).copy()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    s = b.size
+    if a.shape != (s, s) or q.shape != p.shape or q.ndim != 1:
+        raise ValueError("a must be s x s for s weights; q and p 1-D of one length")
+    rc = _load().oracle_rk_tableau_run(model, q.size, float(dt), int(steps), _ptr(q), _ptr(p),
+                                       int(s), _ptr(a), _ptr(b), int(threads))
+    if rc != 0:
+        raise MemoryError("oracle_rk_tableau_run failed")
     return q, p
 
 

@@ -171,6 +171,61 @@ int oracle_rk4_run(int model, int64_t n, double dt, int64_t steps,
 }
 
 /*
+ * Public: advance (q, p) in place by `steps` steps of any explicit Runge-Kutta
+ * method (Sec. 2.2 Eq. 3-5 with a general tableau; Sec. 2 notes the technique
+ * applies to every explicit scheme). The method has s stages, coefficients
+ * a (s x s, row-major; only the strictly lower triangle is read) and weights
+ * b (s entries). Stage j evaluates the field at r + dt * sum_{m<j} a[j][m] k_m;
+ * the step ends with r + dt * sum_m b[m] k_m. The models are autonomous, so
+ * the nodes c play no part. Returns 0, or -1 on bad arguments or no memory.
+ */
+int oracle_rk_tableau_run(int model, int64_t n, double dt, int64_t steps, double *q, double *p,
+                          int s, const double *a, const double *b, int threads)
+{
+    double *buf, *kq, *kp, *Q, *P;
+    int64_t t, i;
+    int j, m;
+    if (n < 1 || steps < 0 || s < 1 || s > 16)
+        return -1;
+    if (threads < 1)
+        threads = 1;
+    buf = (double *)malloc(sizeof(double) * (size_t)n * (size_t)(2 * s + 2));
+    if (!buf)
+        return -1;
+    kq = buf;                          /* kq[j * n + i]: q part of k_j */
+    kp = buf + (size_t)n * (size_t)s;  /* kp[j * n + i]: p part of k_j */
+    Q = buf + (size_t)n * (size_t)(2 * s);
+    P = Q + n;
+    for (t = 0; t < steps; ++t) {
+        for (j = 0; j < s; ++j) {
+#pragma omp parallel for num_threads(threads) schedule(static) private(m)
+            for (i = 0; i < n; ++i) {
+                double sq = 0.0, sp = 0.0;
+                for (m = 0; m < j; ++m) {
+                    sq += a[j * s + m] * kq[(size_t)m * n + i];
+                    sp += a[j * s + m] * kp[(size_t)m * n + i];
+                }
+                Q[i] = q[i] + dt * sq;
+                P[i] = p[i] + dt * sp;
+            }
+            rhs(model, n, Q, P, kq + (size_t)j * n, kp + (size_t)j * n, threads);
+        }
+#pragma omp parallel for num_threads(threads) schedule(static) private(m)
+        for (i = 0; i < n; ++i) {
+            double sq = 0.0, sp = 0.0;
+            for (m = 0; m < s; ++m) {
+                sq += b[m] * kq[(size_t)m * n + i];
+                sp += b[m] * kp[(size_t)m * n + i];
+            }
+            q[i] = q[i] + dt * sq;
+            p[i] = p[i] + dt * sp;
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/*
  * Public: total energy H = sum_i e_i, summed in index order with Neumaier's
  * compensated summation (Neumaier 1974).
  */

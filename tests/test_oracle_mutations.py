@@ -45,6 +45,12 @@ MUTANTS = {
     "nnn_wrap": ("return j < 0 ? j + n : j;", "return j < 0 ? 0 : j;"),
     "nnn_energy_second": ("d2 * d2 * d2 * d2 / 4.0", "d2 * d2 * d2 * d2 / 2.0"),
     "nnn_energy_harmonic": ("+ d2 * d2 / 2.0;", "+ d2 * d2;"),
+    "tableau_stage_dt": ("Q[i] = q[i] + dt * sq;", "Q[i] = q[i] + sq;"),
+    "tableau_transposed": ("sq += a[j * s + m] * kq", "sq += a[m * s + j] * kq"),
+    "tableau_momentum_slope": ("sp += a[j * s + m] * kp", "sp += a[j * s + m] * kq"),
+    "tableau_stage_count": ("for (m = 0; m < j; ++m) {", "for (m = 0; m + 1 < j; ++m) {"),
+    "tableau_weights": ("sq += b[m] * kq[(size_t)m * n + i];", "sq += b[0] * kq[(size_t)m * n + i];"),
+    "tableau_final_dt": ("p[i] = p[i] + dt * sp;", "p[i] = p[i] + 0.5 * dt * sp;"),
 }
 
 
@@ -53,7 +59,8 @@ def _run_pins(lib):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(HERE, "test_oracle_pins.py"),
                         os.path.join(HERE, "test_oracle_roessler.py"),
-                        os.path.join(HERE, "test_oracle_nnn.py")],
+                        os.path.join(HERE, "test_oracle_nnn.py"),
+                        os.path.join(HERE, "test_oracle_tableau.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     return r.returncode
 
