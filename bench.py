@@ -53,9 +53,9 @@ BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 # the kernel sources with this sha256 and this cluster shape (sites per lane,
 # wavefronts per cluster, halo) on N = 2^24.
 MEASURED_TRAFFIC = {
-    "sha256": "0d6fffeca6428126d0a45004a2d454ebc188261f02009dfb017c3269baeaf8a5",
-    "shape": (8, 4, 48), "n": 1 << 24,
-    "bytes_per_launch": 550842811, "fetch_factor": 0.5000, "write_factor": 1.0000,
+    "sha256": "f1750eb5b8dd69d82258c1fe1e729689de763d25db5b1f32a94f919898015459",
+    "shape": (8, 4, 64), "n": 1 << 24,
+    "bytes_per_launch": 555327933, "fetch_factor": 0.5000, "write_factor": 1.0000,
 }
 
 
@@ -138,7 +138,7 @@ def fused_launches(plan, steps):
     return m
 
 
-def cpu_baseline(n, dt, target_s=10.0):
+def cpu_baseline(n, dt, target_s=12.0):
     """The oracle (as it stands) on the host cores: the same chain and ICs,
     as many steps as fit in about `target_s` seconds."""
     import oracle
@@ -146,11 +146,11 @@ def cpu_baseline(n, dt, target_s=10.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     q0, p0 = workloads.chain_ics(n, 0)
-    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 1, threads=threads)      # first touch
+    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 2, threads=threads)      # first touch, thread start
     t = time.perf_counter()
-    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 2, threads=threads)
-    per_step = (time.perf_counter() - t) / 2
-    steps = max(1, min(400, int(target_s / max(per_step, 1e-6))))
+    oracle.rk4(oracle.QUARTIC, q0, p0, dt, 4, threads=threads)
+    per_step = (time.perf_counter() - t) / 4
+    steps = max(1, min(2000, int(target_s / max(per_step, 1e-6))))
     t = time.perf_counter()
     oracle.rk4(oracle.QUARTIC, q0, p0, dt, steps, threads=threads)
     el = time.perf_counter() - t
@@ -179,6 +179,8 @@ def main(argv=None):
     ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only sweep N = 2^10..2^26, fused vs per-stage, T = 50, best of 10")
+    ap.add_argument("--tableaus", action="store_true",
+                    help="only the explicit methods by Butcher tableau on the bench chain")
     ap.add_argument("--roessler", action="store_true",
                     help="only the Roessler chain with the paper's protocol (N = 2^20, T = 50 "
                          "steps, best of 10)")
@@ -214,6 +216,12 @@ def main(argv=None):
     q0, p0 = workloads.chain_ics(n, 0)
     qd = torch.from_numpy(q0).to(dev)
     pd = torch.from_numpy(p0).to(dev)
+    if args.tableaus:
+        print(json.dumps({"metric": "site-updates/sec by explicit RK method",
+                          "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
+                          "dtype": "f64", "config": {"workload": "quartic chain N=2^24, dt=0.01"},
+                          "tableaus": variant_tableaus(qd, pd, dt, n, dev)}), flush=True)
+        return 0
 
     from paper_1412_0544_amd import autotune
     sweep = {}
@@ -548,6 +556,38 @@ def variant_nnn(qd, pd, dt, n, dev, steps=480):
     return out
 
 
+def tableau_ops_per_su(a, b, force_ops=OPS_PER_SU["quartic"] - 14):
+    """VALU ops of one site-update of the tableau kernel: per stage the
+    force (`force_ops` / 4 for the quartic chain) plus, from stage 2 on, two
+    fma per earlier stage and two to form the argument; the final
+    combination is two fma per stage plus two."""
+    s = len(b)
+    f = force_ops // 4
+    return s * f + sum(2 * j + 2 for j in range(1, s)) + 2 * s + 2
+
+
+def variant_tableaus(qd, pd, dt, n, dev, steps=192):
+    """Explicit methods by Butcher tableau on the bench chain (library plan,
+    device time of `steps` steps, best of 3): site-updates/s and the VALU
+    roofline of each."""
+    from paper_1412_0544_amd import Chain, tableaus
+    out = {}
+    for name, (a, b) in tableaus.ALL.items():
+        ch = Chain(qd, pd, dt, tableau=(a, b), device=dev)
+        ch.step(16)
+        best = min(ev_seconds(lambda: ch.step(steps), ch.stream) for _ in range(3))
+        plan = ch.plan()
+        ch.close()
+        ops = tableau_ops_per_su(a, b)
+        su = n * steps / best
+        out[name] = {"stages": len(b), "su_per_s": su, "ops_per_su": ops,
+                     "valu_frac": su * ops / (VALU_PEAK_TOPS * 1e12),
+                     "plan": {x: plan[x] for x in ("sites_per_lane", "waves_per_cluster", "kdepth",
+                                                   "halo", "tile")}}
+        log(f"[bench] tableau {name}: {su:.3e} SU/s, {out[name]['valu_frac']:.2f} of VALU peak")
+    return out
+
+
 def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     """Other rows of the hot path, each measured at its own configuration."""
     from paper_1412_0544_amd import Chain, autotune
@@ -576,6 +616,8 @@ def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     res["precision"] = variant_precision(n, dt, dev)
     log("[bench] variant: 4096-chain batch")
     res["batch4096"] = variant_batch(dt, dev)
+    log("[bench] variant: explicit methods by Butcher tableau")
+    res["tableaus"] = variant_tableaus(qd, pd, dt, n, dev)
     log("[bench] variant: next-nearest-neighbour coupling")
     res["quartic_nnn"] = variant_nnn(qd, pd, dt, n, dev)
     log("[bench] variant: Roessler chain, the paper's protocol")

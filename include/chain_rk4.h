@@ -76,6 +76,32 @@ enum chain_method {
                          every stage result goes through memory (Sec. 2.2) */
 };
 
+enum chain_scheme {
+    CHAIN_SCHEME_RK4 = 0,     /* classical RK4 (Sec. 2.2: c = (0, 1/2, 1/2, 1),
+                                 a21 = a32 = 1/2, a43 = 1, b = (1/6, 1/3, 1/3,
+                                 1/6)) on the dedicated kernels */
+    CHAIN_SCHEME_TABLEAU = 1  /* any explicit Runge-Kutta method, given by
+                                 chain_rk4_set_tableau before the first step
+                                 (Sec. 2.2 Eq. 3-5 with general coefficients;
+                                 the paper notes the technique applies to every
+                                 explicit scheme). CHAIN_FUSED only; the
+                                 quartic, harmonic and NNN models */
+};
+
+#define CHAIN_MAX_STAGES 8
+
+/* Butcher tableau of an explicit method with `stages` stages. Stage j
+ * (0-based) evaluates the field at r + dt * sum_{m<j} a[j][m] k_m; the step
+ * ends with r + dt * sum_{m<stages} b[m] k_m. Entries a[j][m] with m >= j or
+ * j >= stages, and b[m] with m >= stages, are ignored. The models are
+ * autonomous, so no nodes c are needed. */
+typedef struct chain_rk4_tableau {
+    int32_t stages;          /* 1..CHAIN_MAX_STAGES */
+    int32_t reserved;        /* must be 0 */
+    double a[CHAIN_MAX_STAGES][CHAIN_MAX_STAGES];
+    double b[CHAIN_MAX_STAGES];
+} chain_rk4_tableau;
+
 enum chain_flags {
     CHAIN_FLAG_GRAPH = 1,        /* replay each distinct step count from a
                                     captured hipGraph instead of launching pass
@@ -108,7 +134,7 @@ typedef struct chain_rk4_desc {
                                 (edge values through LDS), 0 = default,
                                 else 1, 2, 4 or 8 */
     int32_t flags;           /* enum chain_flags, or 0 */
-    int32_t reserved;        /* must be 0 */
+    int32_t scheme;          /* enum chain_scheme (0 = classical RK4) */
 } chain_rk4_desc;
 
 /* Plan chosen for a handle: what one step call launches. */
@@ -188,6 +214,30 @@ int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out);
  */
 int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp);
 
+/*
+ * Give a CHAIN_SCHEME_TABLEAU handle its method (copied; it may be set again
+ * between step calls). Validation: 1 <= stages <= CHAIN_MAX_STAGES, finite
+ * coefficients, and a cluster shape the tableau kernel is built for
+ * (sites_per_lane 4 or 8 for up to 4 stages, 4 beyond; waves_per_cluster 1
+ * or 4). The halo becomes reach * kdepth with reach from
+ * chain_rk4_tableau_reach; a default depth is then 64 / reach steps. Until
+ * a tableau is set, chain_rk4_step returns CHAIN_EINVAL. CHAIN_EINVAL also
+ * for a handle of another scheme.
+ */
+int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t);
+
+/*
+ * Sites per side that one step of the tableau's method carries a change of
+ * the state for the given model (the overlap per step of Sec. 2.3, exact for
+ * the tableau's zero pattern): for dq/dt = p, dp/dt = F(q) with F reaching
+ * R sites (R = 1, or 2 for the NNN models), stage argument Q_j reaches as far
+ * as the momenta P_m it combines (a[j][m] != 0), P_j as far as the forces
+ * F(Q_m) plus R, and the step as far as the stages with b[m] != 0. Classical
+ * RK4: 2 (4 for NNN). Returns -1 for an invalid tableau or model (the
+ * Roessler chain is not covered). No GPU is needed.
+ */
+int64_t chain_rk4_tableau_reach(int32_t model, const chain_rk4_tableau *t);
+
 /* Release a handle (host memory and cached graphs only). NULL is a no-op. */
 int chain_rk4_destroy(chain_rk4 *h);
 
@@ -226,7 +276,7 @@ typedef struct chain_rk4_batch_desc {
     int64_t max_clusters;    /* capacity for chain_rk4_batch_rebind: clusters
                                 over all tiled chains (0 = what `hs` needs) */
     int32_t sites_per_lane;  /* 0 = default (4), else 4, 8 or 16 */
-    int32_t kdepth;          /* steps per pass, 0 = default (16), else 2..32 */
+    int32_t kdepth;          /* steps per pass, 0 = default (32), else 2..32 */
     int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
                                 once; any value >= 1 gives the same results */
     int32_t flags;           /* 0, or CHAIN_BATCH_FENCES */

@@ -17,6 +17,8 @@ CHAIN_FP64, CHAIN_FP32_KAHAN = 0, 1
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT = 1, 2
 CHAIN_BATCH_FENCES = 1
+CHAIN_SCHEME_RK4, CHAIN_SCHEME_TABLEAU = 0, 1
+CHAIN_MAX_STAGES = 8
 
 CHAIN_OK = 0
 CHAIN_EINVAL = -1
@@ -32,7 +34,7 @@ class Desc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("method", ctypes.c_int32),
                 ("sites_per_lane", ctypes.c_int32), ("kdepth", ctypes.c_int32),
                 ("waves_per_cluster", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
@@ -41,6 +43,12 @@ class Plan(ctypes.Structure):
                 ("waves_per_cluster", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tile", ctypes.c_int64), ("halo", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("overlap_factor", ctypes.c_double)]
+
+
+class Tableau(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("a", (ctypes.c_double * CHAIN_MAX_STAGES) * CHAIN_MAX_STAGES),
+                ("b", ctypes.c_double * CHAIN_MAX_STAGES)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -78,6 +86,8 @@ def _declare(lib):
         "chain_rk4_create3": (ctypes.c_int, [D, VP, VP, VP, VP, ctypes.c_size_t, VP,
                                              ctypes.POINTER(H)]),
         "chain_rk4_step": (ctypes.c_int, [H, ctypes.c_int64]),
+        "chain_rk4_set_tableau": (ctypes.c_int, [H, ctypes.POINTER(Tableau)]),
+        "chain_rk4_tableau_reach": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(Tableau)]),
         "chain_rk4_energy": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
         "chain_rk4_set_stream": (ctypes.c_int, [H, VP]),
         "chain_rk4_get_plan": (ctypes.c_int, [H, ctypes.POINTER(Plan)]),

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libchainrk4.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["fused.hip", "persistent.hip", "naive.hip", "energy.hip", "roessler.hip", "chain_rk4.cpp", "batch.cpp"]
+SOURCES = ["fused.hip", "persistent.hip", "naive.hip", "energy.hip", "roessler.hip", "tableau.hip",
+           "chain_rk4.cpp", "batch.cpp"]
 ARCH = "gfx950"
 
 COMMON = [
@@ -51,7 +52,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -34,6 +34,28 @@ def aligned_empty(nbytes: int, device, align: int = 256) -> tuple[torch.Tensor, 
     return buf, buf.data_ptr() + off
 
 
+def make_tableau(a, b) -> L.Tableau:
+    """The C struct of a Butcher tableau from nested sequences."""
+    s = len(b)
+    if s < 1 or s > L.CHAIN_MAX_STAGES or len(a) != s or any(len(r) != s for r in a):
+        raise ValueError(f"a must be s x s and b of length s, 1 <= s <= {L.CHAIN_MAX_STAGES}")
+    t = L.Tableau()
+    t.stages = s
+    for j in range(s):
+        t.b[j] = float(b[j])
+        for m in range(j):
+            t.a[j][m] = float(a[j][m])
+    return t
+
+
+def tableau_reach(model, a, b) -> int:
+    """Sites per side one step of the method reaches for the model."""
+    r = L.lib().chain_rk4_tableau_reach(_code(MODELS, model), ctypes.byref(make_tableau(a, b)))
+    if r < 0:
+        L.check(L.CHAIN_EINVAL, "chain_rk4_tableau_reach")
+    return int(r)
+
+
 class Chain:
     """One periodic chain advanced by the HIP library.
 
@@ -44,7 +66,8 @@ class Chain:
     def __init__(self, q0, p0, dt: float, model="quartic", prec="fp64", method="fused",
                  sites_per_lane: int = 0, kdepth: int = 0, waves_per_cluster: int = 0,
                  graph: bool = False,
-                 resident: bool = True, device="cuda", stream: torch.cuda.Stream | None = None):
+                 resident: bool = True, device="cuda", stream: torch.cuda.Stream | None = None,
+                 tableau=None):
         self.device = torch.device(device)
         dtype = state_dtype(prec)
         self.q = torch.as_tensor(q0).to(device=self.device, dtype=dtype).contiguous().clone()
@@ -52,9 +75,10 @@ class Chain:
         if self.q.ndim != 1 or self.q.shape != self.p.shape:
             raise ValueError("q0 and p0 must be 1-D of one length")
         flags = (L.CHAIN_FLAG_GRAPH if graph else 0) | (0 if resident else L.CHAIN_FLAG_NO_RESIDENT)
+        scheme = L.CHAIN_SCHEME_RK4 if tableau is None else L.CHAIN_SCHEME_TABLEAU
         self.desc = L.Desc(self.q.numel(), _code(MODELS, model), _code(PRECS, prec), float(dt),
                            _code(METHODS, method), int(sites_per_lane), int(kdepth),
-                           int(waves_per_cluster), flags, 0)
+                           int(waves_per_cluster), flags, scheme)
         lib = L.lib()
         ws = lib.chain_rk4_workspace_bytes(ctypes.byref(self.desc))
         if ws == 0:
@@ -66,10 +90,18 @@ class Chain:
                                      ws_ptr, ws, self.stream.cuda_stream, ctypes.byref(h)),
                 "chain_rk4_create")
         self._h = h
+        if tableau is not None:
+            self.set_tableau(*tableau)
 
     @property
     def handle(self):
         return self._h
+
+    def set_tableau(self, a, b) -> None:
+        """Give the chain an explicit Runge-Kutta method: coefficients ``a``
+        (s x s, strictly lower triangle used) and weights ``b`` (s)."""
+        L.check(L.lib().chain_rk4_set_tableau(self._h, ctypes.byref(make_tableau(a, b))),
+                "chain_rk4_set_tableau")
 
     def step(self, nsteps: int) -> "Chain":
         L.check(L.lib().chain_rk4_step(self._h, int(nsteps)), "chain_rk4_step")

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -96,7 +97,14 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->waves_per_cluster != 0 && !valid_waves(d->waves_per_cluster))
         return fail(CHAIN_EINVAL, "waves_per_cluster must be 0, 1, 2, 4 or 8 (got %d)",
                     d->waves_per_cluster);
-    if (d->reserved != 0) return fail(CHAIN_EINVAL, "reserved must be 0");
+    if (d->scheme != CHAIN_SCHEME_RK4 && d->scheme != CHAIN_SCHEME_TABLEAU)
+        return fail(CHAIN_EINVAL, "unknown scheme %d", d->scheme);
+    if (d->scheme == CHAIN_SCHEME_TABLEAU) {
+        if (d->method != CHAIN_FUSED)
+            return fail(CHAIN_EINVAL, "a tableau method runs on the fused path only");
+        if (d->model == CHAIN_ROESSLER)
+            return fail(CHAIN_EINVAL, "a tableau method is not available for the Roessler chain");
+    }
     if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT))
         return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
     return CHAIN_OK;
@@ -165,24 +173,55 @@ int64_t step_reach(int model) {
     }
 }
 
-Plan make_plan(const chain_rk4_desc *d) {
+// Reach of one step of an explicit tableau for dq/dt = p, dp/dt = F(q) with
+// F reaching `range` sites: the stage argument Q_j combines momenta P_m,
+// P_j combines forces F(Q_m); a zero coefficient adds nothing.
+int64_t tableau_reach_of(const TabArgs &t, int64_t range) {
+    int64_t rq[kMaxStages] = {0}, rp[kMaxStages] = {0};
+    for (int j = 1; j < t.stages; ++j)
+        for (int m = 0; m < j; ++m)
+            if (t.a[j][m] != 0.0) {
+                rq[j] = std::max(rq[j], rp[m]);
+                rp[j] = std::max(rp[j], rq[m] + range);
+            }
+    int64_t r = 0;
+    for (int m = 0; m < t.stages; ++m)
+        if (t.b[m] != 0.0) r = std::max(r, std::max(rp[m], rq[m] + range));
+    return r;
+}
+
+int64_t model_range(int model) {
+    return (model == CHAIN_QUARTIC_NNN || model == CHAIN_HARMONIC_NNN) ? 2 : 1;
+}
+
+// Cluster shape of the tableau kernel (see launch_tableau).
+bool tableau_shape_ok(int stages, int sites, int waves) {
+    if (waves != 1 && waves != 4) return false;
+    return stages <= 4 ? (sites == 4 || sites == 8) : sites == 4;
+}
+
+constexpr int kDefaultSitesTableau = 4;
+
+Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0) {
     Plan P;
     if (d->method != CHAIN_FUSED) return P;
     const bool roessler = d->model == CHAIN_ROESSLER;
     const bool nn = d->model == CHAIN_QUARTIC || d->model == CHAIN_HARMONIC;
-    if (nn && !(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites &&
+    const bool tab = d->scheme == CHAIN_SCHEME_TABLEAU;
+    if (nn && !tab && !(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites &&
         d->sites_per_lane == 0 && d->kdepth == 0 && d->waves_per_cluster == 0) {
         P.resident = true;
         return P;
     }
     P.sites = d->sites_per_lane ? d->sites_per_lane
               : roessler        ? kDefaultSitesRoessler
+              : tab             ? kDefaultSitesTableau
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
                           : roessler             ? kDefaultWavesRoessler
                                                  : kDefaultWaves;
-    const int64_t reach = step_reach(d->model);
-    P.depth = d->kdepth ? d->kdepth : static_cast<int>(kDefaultHalo / reach);
+    const int64_t reach = reach_override > 0 ? reach_override : step_reach(d->model);
+    P.depth = d->kdepth ? d->kdepth : static_cast<int>(std::max<int64_t>(1, kDefaultHalo / reach));
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
     // the kept part of a cluster must stay positive: E > 2*halo
     while (E <= 2 * reach * P.depth && P.depth > 1) --P.depth;
@@ -240,6 +279,9 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
         hipError_t e =
             d.model == CHAIN_ROESSLER
                 ? launch_fused_roessler(h->plan.sites, h->plan.waves_per_cluster, a, s)
+            : d.scheme == CHAIN_SCHEME_TABLEAU
+                ? launch_tableau(d.model, d.prec, h->plan.sites, h->plan.waves_per_cluster, a,
+                                 h->tableau, s)
                 : launch_fused(d.model, d.prec, h->plan.sites, h->plan.waves_per_cluster, a, s);
         if (e != hipSuccess) return hip_fail(e, "fused launch");
         std::swap(cur, nxt);
@@ -378,6 +420,8 @@ int chain_rk4_create(const chain_rk4_desc *d, void *q, void *p, void *workspace,
 int chain_rk4_step(chain_rk4 *h, int64_t nsteps) {
     if (!h) return fail(CHAIN_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(CHAIN_EINVAL, "nsteps must be >= 0");
+    if (h->d.scheme == CHAIN_SCHEME_TABLEAU && !h->has_tableau)
+        return fail(CHAIN_EINVAL, "no tableau set (chain_rk4_set_tableau)");
     if (nsteps == 0) return CHAIN_OK;
     if (h->d.flags & CHAIN_FLAG_GRAPH) return step_graph(h, nsteps);
     return enqueue_steps(h, nsteps, h->stream);
@@ -424,6 +468,62 @@ int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp) {
     if (!h || !cq || !cp) return fail(CHAIN_EINVAL, "handle, cq and cp must be non-NULL");
     *cq = h->front.cq;
     *cp = h->front.cp;
+    return CHAIN_OK;
+}
+
+namespace {
+
+int check_tableau(const chain_rk4_tableau *t, TabArgs *out) {
+    if (!t) return fail(CHAIN_EINVAL, "tableau is NULL");
+    if (t->stages < 1 || t->stages > CHAIN_MAX_STAGES)
+        return fail(CHAIN_EINVAL, "stages must be 1..%d (got %d)", CHAIN_MAX_STAGES, t->stages);
+    if (t->reserved != 0) return fail(CHAIN_EINVAL, "tableau reserved must be 0");
+    static_assert(CHAIN_MAX_STAGES == kMaxStages, "stage bound");
+    TabArgs a{};
+    a.stages = t->stages;
+    for (int j = 0; j < t->stages; ++j) {
+        for (int m = 0; m < j; ++m) {
+            if (!std::isfinite(t->a[j][m])) return fail(CHAIN_EINVAL, "a[%d][%d] is not finite", j, m);
+            a.a[j][m] = t->a[j][m];
+        }
+        if (!std::isfinite(t->b[j])) return fail(CHAIN_EINVAL, "b[%d] is not finite", j);
+        a.b[j] = t->b[j];
+    }
+    *out = a;
+    return CHAIN_OK;
+}
+
+}  // namespace
+
+int64_t chain_rk4_tableau_reach(int32_t model, const chain_rk4_tableau *t) {
+    TabArgs a;
+    if (model != CHAIN_QUARTIC && model != CHAIN_HARMONIC && model != CHAIN_QUARTIC_NNN &&
+        model != CHAIN_HARMONIC_NNN)
+        return -1;
+    if (check_tableau(t, &a) != CHAIN_OK) return -1;
+    return tableau_reach_of(a, model_range(model));
+}
+
+int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t) {
+    if (!h) return fail(CHAIN_EINVAL, "handle is NULL");
+    if (h->d.scheme != CHAIN_SCHEME_TABLEAU)
+        return fail(CHAIN_EINVAL, "the handle was not created with CHAIN_SCHEME_TABLEAU");
+    TabArgs a;
+    int rc = check_tableau(t, &a);
+    if (rc != CHAIN_OK) return rc;
+    const int64_t reach = std::max<int64_t>(1, tableau_reach_of(a, model_range(h->d.model)));
+    Plan P = make_plan(&h->d, reach);
+    if (!tableau_shape_ok(a.stages, P.sites, P.waves_per_cluster))
+        return fail(CHAIN_EINVAL,
+                    "the tableau kernel runs sites_per_lane 4 or 8 (4 beyond 4 stages) and "
+                    "waves_per_cluster 1 or 4 (got %d, %d for %d stages)",
+                    P.sites, P.waves_per_cluster, a.stages);
+    if (P.tile < 1) return fail(CHAIN_EINVAL, "the cluster is too small for this tableau's reach");
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->tableau = a;
+    h->plan = P;
+    h->has_tableau = true;
     return CHAIN_OK;
 }
 

@@ -42,4 +42,6 @@ struct chain_rk4 {
     chainrk4::Plan plan;
     hipStream_t capture = nullptr;
     std::map<int64_t, hipGraphExec_t> graphs;
+    bool has_tableau = false;     // CHAIN_SCHEME_TABLEAU: set by chain_rk4_set_tableau
+    chainrk4::TabArgs tableau{};
 };

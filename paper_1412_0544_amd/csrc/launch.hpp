@@ -57,6 +57,19 @@ size_t resident_lds_bytes(int prec, int64_t n);
 hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,
                              double dt, hipStream_t s);
 
+// Explicit Runge-Kutta by Butcher tableau: coefficients a[j][m] (m < j) and
+// weights b[m] of `stages` <= kMaxStages stages.
+constexpr int kMaxStages = 8;
+struct TabArgs {
+    int32_t stages, pad;
+    double a[kMaxStages][kMaxStages];
+    double b[kMaxStages];
+};
+// Cluster shapes the tableau kernel is built for: sites per lane 4 or 8 with
+// up to 4 stages, 4 with up to 8; wavefronts per cluster 1 or 4.
+hipError_t launch_tableau(int model, int prec, int sites_per_lane, int waves_per_cluster,
+                          const FusedPass &a, const TabArgs &t, hipStream_t s);
+
 // Roessler chain (FP64): fused cluster pass and the per-stage baseline.
 constexpr int kModelRoessler = 2;
 hipError_t launch_fused_roessler(int sites_per_lane, int waves_per_cluster, const FusedPass &a,

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_function():
 
 def desc(**kw):
     d = dict(n=1000, model=0, prec=0, dt=0.01, method=0, sites_per_lane=0, kdepth=0,
-             waves_per_cluster=0, flags=0, reserved=0)
+             waves_per_cluster=0, flags=0, scheme=0)
     d.update(kw)
     return L.Desc(**d)
 
@@ -43,7 +43,8 @@ def test_workspace_bytes():
     for bad in (desc(n=0), desc(model=7), desc(prec=3), desc(dt=float("nan")),
                 desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
                 desc(kdepth=33), desc(kdepth=-1), desc(model=5), desc(model=2, prec=1), desc(flags=64), desc(waves_per_cluster=3),
-                desc(waves_per_cluster=16), desc(reserved=1)):
+                desc(waves_per_cluster=16), desc(scheme=7),
+                desc(scheme=1, method=1), desc(scheme=1, model=2)):
         assert f(bad) == 0
     assert lib.chain_rk4_workspace_bytes(None) == 0
 
@@ -127,9 +128,9 @@ def test_batch_cluster_count_helper():
         keep = 64 * sites * 4 - 4 * depth                          # cluster minus both halos
         return -(-n // (keep - 4))
 
-    # default shape: 4 sites per lane, depth 16
+    # default shape: 4 sites per lane, depth 32
     for n in (1025, 5000, 65536, 1 << 24):
-        assert lib.chain_rk4_batch_clusters(n, 0, 0) == expect(n, 4, 16)
+        assert lib.chain_rk4_batch_clusters(n, 0, 0) == expect(n, 4, 32)
         assert lib.chain_rk4_batch_clusters(n, 8, 12) == expect(n, 8, 12)
     assert lib.chain_rk4_batch_clusters(100, 5, 0) == 0          # invalid shape
     assert lib.chain_rk4_batch_rebind(None, None, 0) == L.CHAIN_EINVAL
@@ -177,3 +178,40 @@ def test_nnn_models_validate_like_the_nn_models():
     d = desc(model=L.CHAIN_QUARTIC_NNN)
     assert lib.chain_rk4_create(ctypes.byref(d), fake, None, fake, f(d), None,
                                 ctypes.byref(h)) == L.CHAIN_EINVAL
+
+
+def test_tableau_reach_without_a_gpu():
+    """The library's reach of one step, for literature tableaus written out
+    in the oracle's pin file, equals the reach measured on the oracle there
+    (its exact-reach pin) for the NN and NNN chains."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_oracle_tableau import TABLEAUS, step_reach
+    from paper_1412_0544_amd.chain import make_tableau
+    lib = L.lib()
+    for name, ((a, b), _) in TABLEAUS.items():
+        t = make_tableau(a.tolist(), b.tolist())
+        for model, rng in ((L.CHAIN_QUARTIC, 1), (L.CHAIN_HARMONIC, 1), (L.CHAIN_QUARTIC_NNN, 2)):
+            assert lib.chain_rk4_tableau_reach(model, ctypes.byref(t)) == step_reach(a, b, rng), name
+    (a, b), _ = TABLEAUS["rk4"]
+    t = make_tableau(a.tolist(), b.tolist())
+    assert lib.chain_rk4_tableau_reach(L.CHAIN_QUARTIC, ctypes.byref(t)) == 2
+    assert lib.chain_rk4_tableau_reach(L.CHAIN_ROESSLER, ctypes.byref(t)) == -1
+    t.stages = 9
+    assert lib.chain_rk4_tableau_reach(L.CHAIN_QUARTIC, ctypes.byref(t)) == -1
+    t.stages = 2
+    t.a[1][0] = float("nan")
+    assert lib.chain_rk4_tableau_reach(L.CHAIN_QUARTIC, ctypes.byref(t)) == -1
+    assert lib.chain_rk4_set_tableau(None, ctypes.byref(t)) == L.CHAIN_EINVAL
+
+
+def test_preset_tableaus_are_the_literature_values():
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import numpy as np
+    from test_oracle_tableau import TABLEAUS
+    from paper_1412_0544_amd import tableaus
+    assert set(tableaus.ALL) == set(TABLEAUS)
+    for name, (a, b) in tableaus.ALL.items():
+        (a0, b0), _ = TABLEAUS[name]
+        assert np.array_equal(np.array(a), a0) and np.array_equal(np.array(b), b0), name

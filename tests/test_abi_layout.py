@@ -21,7 +21,8 @@ int main(void) {
 
 
 STRUCTS = (("chain_rk4_desc", L.Desc), ("chain_rk4_plan", L.Plan),
-           ("chain_rk4_batch_desc", L.BatchDesc), ("chain_rk4_batch_plan", L.BatchPlan))
+           ("chain_rk4_batch_desc", L.BatchDesc), ("chain_rk4_batch_plan", L.BatchPlan),
+           ("chain_rk4_tableau", L.Tableau))
 
 
 def test_struct_layouts_match(tmp_path):
