@@ -220,7 +220,8 @@ def main(argv=None):
         print(json.dumps({"metric": "site-updates/sec by explicit RK method",
                           "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
                           "dtype": "f64", "config": {"workload": "quartic chain N=2^24, dt=0.01"},
-                          "tableaus": variant_tableaus(qd, pd, dt, n, dev)}), flush=True)
+                          "tableaus": variant_tableaus(qd, pd, dt, n, dev, sweep=args.sweep)}),
+              flush=True)
         return 0
 
     from paper_1412_0544_amd import autotune
@@ -566,25 +567,38 @@ def tableau_ops_per_su(a, b, force_ops=OPS_PER_SU["quartic"] - 14):
     return s * f + sum(2 * j + 2 for j in range(1, s)) + 2 * s + 2
 
 
-def variant_tableaus(qd, pd, dt, n, dev, steps=192):
+def variant_tableaus(qd, pd, dt, n, dev, steps=192, sweep=False):
     """Explicit methods by Butcher tableau on the bench chain (library plan,
     device time of `steps` steps, best of 3): site-updates/s and the VALU
-    roofline of each."""
+    roofline of each; with `sweep`, also every cluster shape and depth the
+    tableau kernel is built for."""
     from paper_1412_0544_amd import Chain, tableaus
-    out = {}
-    for name, (a, b) in tableaus.ALL.items():
-        ch = Chain(qd, pd, dt, tableau=(a, b), device=dev)
+
+    def timed(a, b, **kw):
+        ch = Chain(qd, pd, dt, tableau=(a, b), device=dev, **kw)
         ch.step(16)
         best = min(ev_seconds(lambda: ch.step(steps), ch.stream) for _ in range(3))
         plan = ch.plan()
         ch.close()
+        return n * steps / best, plan
+
+    out = {}
+    for name, (a, b) in tableaus.ALL.items():
+        su, plan = timed(a, b)
         ops = tableau_ops_per_su(a, b)
-        su = n * steps / best
         out[name] = {"stages": len(b), "su_per_s": su, "ops_per_su": ops,
                      "valu_frac": su * ops / (VALU_PEAK_TOPS * 1e12),
                      "plan": {x: plan[x] for x in ("sites_per_lane", "waves_per_cluster", "kdepth",
                                                    "halo", "tile")}}
         log(f"[bench] tableau {name}: {su:.3e} SU/s, {out[name]['valu_frac']:.2f} of VALU peak")
+        if sweep:
+            table = {}
+            for s_ in ((4, 8) if len(b) <= 4 else (4,)):
+                for w in (1, 4):
+                    for k in (8, 16, 32):
+                        table[f"s{s_}_w{w}_k{k}"] = timed(a, b, sites_per_lane=s_,
+                                                          waves_per_cluster=w, kdepth=k)[0]
+            out[name]["shapes_su_per_s"] = table
     return out
 
 

@@ -220,7 +220,8 @@ int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp);
  * coefficients, and a cluster shape the tableau kernel is built for
  * (sites_per_lane 4 or 8 for up to 4 stages, 4 beyond; waves_per_cluster 1
  * or 4). The halo becomes reach * kdepth with reach from
- * chain_rk4_tableau_reach; a default depth is then 64 / reach steps. Until
+ * chain_rk4_tableau_reach; a default depth is then min(32, 64 / reach)
+ * steps, default sites_per_lane 8 up to 4 stages and 4 beyond. Until
  * a tableau is set, chain_rk4_step returns CHAIN_EINVAL. CHAIN_EINVAL also
  * for a handle of another scheme.
  */

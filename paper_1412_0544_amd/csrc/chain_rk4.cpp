@@ -200,9 +200,11 @@ bool tableau_shape_ok(int stages, int sites, int waves) {
     return stages <= 4 ? (sites == 4 || sites == 8) : sites == 4;
 }
 
-constexpr int kDefaultSitesTableau = 4;
+// Tableau kernel: 8 sites per lane up to 4 stages, 4 beyond (the registers
+// hold every stage's slope); the fastest in a sweep over S, W, k at N = 2^24.
+int default_sites_tableau(int stages) { return stages <= 4 ? 8 : 4; }
 
-Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0) {
+Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages = 4) {
     Plan P;
     if (d->method != CHAIN_FUSED) return P;
     const bool roessler = d->model == CHAIN_ROESSLER;
@@ -215,13 +217,14 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0) {
     }
     P.sites = d->sites_per_lane ? d->sites_per_lane
               : roessler        ? kDefaultSitesRoessler
-              : tab             ? kDefaultSitesTableau
+              : tab             ? default_sites_tableau(stages)
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
                           : roessler             ? kDefaultWavesRoessler
                                                  : kDefaultWaves;
     const int64_t reach = reach_override > 0 ? reach_override : step_reach(d->model);
-    P.depth = d->kdepth ? d->kdepth : static_cast<int>(std::max<int64_t>(1, kDefaultHalo / reach));
+    P.depth = d->kdepth ? d->kdepth
+                        : static_cast<int>(std::min<int64_t>(kMaxDepth, std::max<int64_t>(1, kDefaultHalo / reach)));
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
     // the kept part of a cluster must stay positive: E > 2*halo
     while (E <= 2 * reach * P.depth && P.depth > 1) --P.depth;
@@ -512,7 +515,7 @@ int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t) {
     int rc = check_tableau(t, &a);
     if (rc != CHAIN_OK) return rc;
     const int64_t reach = std::max<int64_t>(1, tableau_reach_of(a, model_range(h->d.model)));
-    Plan P = make_plan(&h->d, reach);
+    Plan P = make_plan(&h->d, reach, a.stages);
     if (!tableau_shape_ok(a.stages, P.sites, P.waves_per_cluster))
         return fail(CHAIN_EINVAL,
                     "the tableau kernel runs sites_per_lane 4 or 8 (4 beyond 4 stages) and "

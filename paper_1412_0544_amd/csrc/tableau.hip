@@ -103,53 +103,48 @@ __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass
     load_lane<R, KAHAN, S>(st, a.in, a.n, s0, e0 >= 0 && e0 + E <= a.n);
     const R dt = static_cast<R>(a.dt);
     const int s = t.stages;
-    R kq[SMAX][S], kp[SMAX][S], Q[S];
+    // kq[m] holds P_m (the q part of k_m) for m >= 1; the q part of k_0 is p
+    R kq[SMAX][S], kp[SMAX][S], Q[S], fq[S], fp[S];
     int parity = 0;
     for (int k = 0; k < a.ksteps; ++k) {
 #pragma unroll
         for (int j = 0; j < SMAX; ++j) {
-            if (j < s) {
-                if (j == 0) {
+            if (j >= s) break;  // uniform: the stage count is a kernel argument
+            if (j == 0) {
+                lane_force<M, S, W, WPB>(st.q, kp[0], &slots, lane, wib, wic, parity);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < S; ++i) {
-                        Q[i] = st.q[i];
-                        kq[0][i] = st.p[i];
+                for (int i = 0; i < S; ++i) {
+                    R sq = static_cast<R>(0), sp = static_cast<R>(0);
+#pragma unroll
+                    for (int m = 0; m < j; ++m) {
+                        const R c = static_cast<R>(t.a[j][m]);
+                        sq = fma_r(c, m == 0 ? st.p[i] : kq[m][i], sq);
+                        sp = fma_r(c, kp[m][i], sp);
                     }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < S; ++i) {
-                        R sq = static_cast<R>(0), sp = static_cast<R>(0);
-#pragma unroll
-                        for (int m = 0; m < j; ++m) {
-                            const R c = static_cast<R>(t.a[j][m]);
-                            sq = fma_r(c, kq[m][i], sq);
-                            sp = fma_r(c, kp[m][i], sp);
-                        }
-                        Q[i] = fma_r(dt, sq, st.q[i]);
-                        kq[j][i] = fma_r(dt, sp, st.p[i]);
-                    }
+                    Q[i] = fma_r(dt, sq, st.q[i]);
+                    kq[j][i] = fma_r(dt, sp, st.p[i]);
                 }
                 lane_force<M, S, W, WPB>(Q, kp[j], &slots, lane, wib, wic, parity);
-                parity ^= 1;
+            }
+            parity ^= 1;
+            // the final combination, accumulated stage by stage in stage order
+            const R bj = static_cast<R>(t.b[j]);
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const R kqj = j == 0 ? st.p[i] : kq[j][i];
+                fq[i] = j == 0 ? bj * kqj : fma_r(bj, kqj, fq[i]);
+                fp[i] = j == 0 ? bj * kp[0][i] : fma_r(bj, kp[j][i], fp[i]);
             }
         }
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-            R sq = static_cast<R>(0), sp = static_cast<R>(0);
-#pragma unroll
-            for (int m = 0; m < SMAX; ++m) {
-                if (m < s) {
-                    const R c = static_cast<R>(t.b[m]);
-                    sq = fma_r(c, kq[m][i], sq);
-                    sp = fma_r(c, kp[m][i], sp);
-                }
-            }
             if constexpr (KAHAN) {
-                kahan_add(st.q[i], st.cq[i], dt * sq);
-                kahan_add(st.p[i], st.cp[i], dt * sp);
+                kahan_add(st.q[i], st.cq[i], dt * fq[i]);
+                kahan_add(st.p[i], st.cp[i], dt * fp[i]);
             } else {
-                st.q[i] = fma_r(dt, sq, st.q[i]);
-                st.p[i] = fma_r(dt, sp, st.p[i]);
+                st.q[i] = fma_r(dt, fq[i], st.q[i]);
+                st.p[i] = fma_r(dt, fp[i], st.p[i]);
             }
         }
     }
