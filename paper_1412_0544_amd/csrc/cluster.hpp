@@ -325,7 +325,7 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
     const int t = threadIdx.x;
     const R *qin = static_cast<const R *>(in.q);
     const R *pin = static_cast<const R *>(in.p);
-    R q[SPT], p[SPT], P[SPT], aq[SPT], ap[SPT];
+    R q[SPT], p[SPT], Q[SPT], P[SPT], aq[SPT], ap[SPT];  // Q: own stage argument
     float cq[KAHAN ? SPT : 1], cp[KAHAN ? SPT : 1];
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
@@ -338,6 +338,7 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
                 cp[j] = in.cp[i];
             }
             buf0[i] = q[j];
+            Q[j] = q[j];
         }
     }
     __syncthreads();
@@ -356,7 +357,7 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
                 if (i < n) {
                     const int im = (i == 0) ? n - 1 : i - 1;
                     const int ip = (i == n - 1) ? 0 : i + 1;
-                    const R Qm = cur[im], Qj = cur[i], Qp = cur[ip];
+                    const R Qm = cur[im], Qj = Q[j], Qp = cur[ip];
                     R Qn = Qj, Pn = P[j];
                     if (stage == 1) {
                         stage_one<M, 1, R>(Qm, Qj, Qp, p[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
@@ -376,6 +377,7 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
                         Qn = q[j];
                     }
                     nxt[i] = Qn;
+                    Q[j] = Qn;
                     if (stage != 4) P[j] = Pn;
                 }
             }

@@ -16,7 +16,9 @@
 // overlap, and updating in place would race.
 //
 // Resident kernel: one workgroup keeps a whole ring of up to 4096 sites on
-// chip (state in registers, stage arguments in LDS) for any number of steps.
+// chip (state in registers, stage arguments in LDS) for any number of steps;
+// 1024 threads from 257 sites on, so each SIMD has four wavefronts to switch
+// between while a stage waits on LDS and the barrier.
 #include "cluster.hpp"
 
 namespace chainrk4 {
@@ -42,11 +44,11 @@ __global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass
                                         a.ksteps, a.dt, &slots, lane, wib, wic);
 }
 
-template <int M, class R, bool KAHAN, int SPT>
-__global__ __launch_bounds__(kResidentThreads) void resident_kernel(ResidentRun a) {
+template <int M, class R, bool KAHAN, int T, int SPT>
+__global__ __launch_bounds__(T) void resident_kernel(ResidentRun a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_resident<M, R, KAHAN, kResidentThreads, SPT>(a.in, a.out, static_cast<int>(a.n), a.nsteps,
-                                                     a.dt, reinterpret_cast<R *>(smem));
+    run_resident<M, R, KAHAN, T, SPT>(a.in, a.out, static_cast<int>(a.n), a.nsteps, a.dt,
+                                      reinterpret_cast<R *>(smem));
 }
 
 template <int M, class R, bool KAHAN, int S, int W>
@@ -82,14 +84,18 @@ hipError_t fused_dispatch_s(int s, int w, const FusedPass &a, hipStream_t st) {
 
 template <int M, class R, bool KAHAN>
 hipError_t resident_dispatch(const ResidentRun &a, hipStream_t st) {
-    const int spt = static_cast<int>((a.n + kResidentThreads - 1) / kResidentThreads);
     const size_t lds = 2 * static_cast<size_t>(a.n) * sizeof(R);
-    const dim3 grid(1), block(kResidentThreads);
-    if (spt <= 1) resident_kernel<M, R, KAHAN, 1><<<grid, block, lds, st>>>(a);
-    else if (spt <= 2) resident_kernel<M, R, KAHAN, 2><<<grid, block, lds, st>>>(a);
-    else if (spt <= 4) resident_kernel<M, R, KAHAN, 4><<<grid, block, lds, st>>>(a);
-    else if (spt <= 8) resident_kernel<M, R, KAHAN, 8><<<grid, block, lds, st>>>(a);
-    else if (spt <= 16) resident_kernel<M, R, KAHAN, 16><<<grid, block, lds, st>>>(a);
+    const dim3 grid(1);
+    if (a.n <= kResidentThreadsSmall) {
+        resident_kernel<M, R, KAHAN, kResidentThreadsSmall, 1>
+            <<<grid, dim3(kResidentThreadsSmall), lds, st>>>(a);
+        return hipGetLastError();
+    }
+    const int spt = static_cast<int>((a.n + kResidentThreads - 1) / kResidentThreads);
+    const dim3 block(kResidentThreads);
+    if (spt <= 1) resident_kernel<M, R, KAHAN, kResidentThreads, 1><<<grid, block, lds, st>>>(a);
+    else if (spt <= 2) resident_kernel<M, R, KAHAN, kResidentThreads, 2><<<grid, block, lds, st>>>(a);
+    else if (spt <= 4) resident_kernel<M, R, KAHAN, kResidentThreads, 4><<<grid, block, lds, st>>>(a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
