@@ -210,7 +210,7 @@ def main(argv=None):
                           "unit": "steps/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
                           "config": {"workload": "Roessler chain N=2^20, dt=0.01, T=50 steps, "
                                                  "best of 10"},
-                          "roessler": variant_roessler(dev)}), flush=True)
+                          "roessler": variant_roessler(dev, sweep=args.sweep)}), flush=True)
         return 0
     n, dt, js = args.n, 0.01, args.job_steps
     log(f"[bench] generating ICs n={n}")
@@ -477,7 +477,7 @@ def roessler_shapes():
             if 64 * s * w > 16 * k]
 
 
-def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None):
+def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, sweep=True):
     """The paper's performance protocol on its own workload (Sec. 3.2): a
     Roessler chain of N = 2^20 from random initial conditions, T = 50 steps
     of dt = 0.01, the best of M = 10 trials, Perf = T / t_wall (Eq. 8). The
@@ -514,12 +514,12 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None):
     log("[bench] Roessler: per-stage baseline")
     out["naive"] = measure(method="naive")
     table = {}
-    for s, w, k in shapes or roessler_shapes():
+    for s, w, k in (shapes or roessler_shapes()) if sweep else ():
         table[f"s{s}_w{w}_k{k}"] = measure(sites_per_lane=s, waves_per_cluster=w, kdepth=k,
                                           graph=True)["device_su_per_s"]
-    out["shapes_device_su_per_s"] = table
-    best = max(table, key=table.get)
-    out["best_shape"] = best
+    if table:
+        out["shapes_device_su_per_s"] = table
+        out["best_shape"] = max(table, key=table.get)
     out["speedup_fused_vs_naive"] = out["fused"]["steps_per_s"] / out["naive"]["steps_per_s"]
     # roofline of the library plan's passes (device time over the launches)
     f = out["fused"]
@@ -529,8 +529,8 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None):
     out["roofline"] = roofline(n, steps / launches, n * steps / f["device_su_per_s"] / launches,
                                model="roessler")
     log(f"[bench] Roessler: fused {f['steps_per_s']:.0f} steps/s (device "
-        f"{f['device_steps_per_s']:.0f}), naive {out['naive']['steps_per_s']:.0f}, best shape "
-        f"{best} {table[best]:.3e} SU/s")
+        f"{f['device_steps_per_s']:.0f}), naive {out['naive']['steps_per_s']:.0f}" +
+        (f", best shape {out['best_shape']} {table[out['best_shape']]:.3e} SU/s" if table else ""))
     return out
 
 
@@ -575,23 +575,26 @@ def variant_tableaus(qd, pd, dt, n, dev, steps=192, sweep=False):
     tableau kernel is built for."""
     from paper_1412_0544_amd import Chain, tableaus
 
-    def timed(a, b, **kw):
+    def timed(a, b, k=steps, **kw):
         ch = Chain(qd, pd, dt, tableau=(a, b), device=dev, **kw)
-        ch.step(16)
-        best = min(ev_seconds(lambda: ch.step(steps), ch.stream) for _ in range(3))
+        ch.step(4)
+        best = min(ev_seconds(lambda: ch.step(k), ch.stream) for _ in range(3))
         plan = ch.plan()
         ch.close()
-        return n * steps / best, plan
+        return n * k / best, plan
 
     out = {}
     for name, (a, b) in tableaus.ALL.items():
         su, plan = timed(a, b)
+        naive, _ = timed(a, b, k=8, method="naive")
         ops = tableau_ops_per_su(a, b)
         out[name] = {"stages": len(b), "su_per_s": su, "ops_per_su": ops,
                      "valu_frac": su * ops / (VALU_PEAK_TOPS * 1e12),
+                     "naive_su_per_s": naive, "speedup_fused_vs_naive": su / naive,
                      "plan": {x: plan[x] for x in ("sites_per_lane", "waves_per_cluster", "kdepth",
                                                    "halo", "tile")}}
-        log(f"[bench] tableau {name}: {su:.3e} SU/s, {out[name]['valu_frac']:.2f} of VALU peak")
+        log(f"[bench] tableau {name}: {su:.3e} SU/s, {out[name]['valu_frac']:.2f} of VALU peak; "
+            f"per-stage {naive:.3e} SU/s")
         if sweep:
             table = {}
             for s_ in ((4, 8) if len(b) <= 4 else (4,)):

@@ -84,8 +84,10 @@ enum chain_scheme {
                                  chain_rk4_set_tableau before the first step
                                  (Sec. 2.2 Eq. 3-5 with general coefficients;
                                  the paper notes the technique applies to every
-                                 explicit scheme). CHAIN_FUSED only; the
-                                 quartic, harmonic and NNN models */
+                                 explicit scheme). The quartic, harmonic
+                                 and NNN models; CHAIN_NAIVE runs one
+                                 kernel per stage with every slope in the
+                                 workspace (18 arrays of n values) */
 };
 
 #define CHAIN_MAX_STAGES 8
@@ -217,9 +219,9 @@ int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp);
 /*
  * Give a CHAIN_SCHEME_TABLEAU handle its method (copied; it may be set again
  * between step calls). Validation: 1 <= stages <= CHAIN_MAX_STAGES, finite
- * coefficients, and a cluster shape the tableau kernel is built for
- * (sites_per_lane 4 or 8 for up to 4 stages, 4 beyond; waves_per_cluster 1
- * or 4). The halo becomes reach * kdepth with reach from
+ * coefficients, and for CHAIN_FUSED a cluster shape the tableau kernel is
+ * built for (sites_per_lane 4 or 8 for up to 4 stages, 4 beyond;
+ * waves_per_cluster 1 or 4). The halo becomes reach * kdepth with reach from
  * chain_rk4_tableau_reach; a default depth is then min(32, 64 / reach)
  * steps, default sites_per_lane 8 up to 4 stages and 4 beyond. Until
  * a tableau is set, chain_rk4_step returns CHAIN_EINVAL. CHAIN_EINVAL also

@@ -100,8 +100,6 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->scheme != CHAIN_SCHEME_RK4 && d->scheme != CHAIN_SCHEME_TABLEAU)
         return fail(CHAIN_EINVAL, "unknown scheme %d", d->scheme);
     if (d->scheme == CHAIN_SCHEME_TABLEAU) {
-        if (d->method != CHAIN_FUSED)
-            return fail(CHAIN_EINVAL, "a tableau method runs on the fused path only");
         if (d->model == CHAIN_ROESSLER)
             return fail(CHAIN_EINVAL, "a tableau method is not available for the Roessler chain");
     }
@@ -116,6 +114,7 @@ struct Layout {
     size_t cq, cp, back_cq, back_cp;  // FP32: carries (front and back)
     size_t naive[10];                 // naive: k1..k3 and two stage arguments
     size_t naive_z[5];                // naive, Roessler: the same for z
+    size_t naive_tab[2 * (kMaxStages - 1) + 4];  // naive tableau: slopes, two arguments
     size_t partials, result;          // energy
     size_t total;
 };
@@ -146,7 +145,9 @@ Layout layout(const chain_rk4_desc *d) {
             L.back_cp = take(carr);
         }
     }
-    if (d->method == CHAIN_NAIVE) {
+    if (d->method == CHAIN_NAIVE && d->scheme == CHAIN_SCHEME_TABLEAU) {
+        for (size_t &o : L.naive_tab) o = take(arr);
+    } else if (d->method == CHAIN_NAIVE) {
         for (int i = 0; i < 10; ++i) L.naive[i] = take(arr);
         if (three)
             for (int i = 0; i < 5; ++i) L.naive_z[i] = take(arr);
@@ -244,6 +245,14 @@ namespace {
 int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
     const chain_rk4_desc &d = h->d;
     if (nsteps == 0) return CHAIN_OK;
+    if (d.method == CHAIN_NAIVE && d.scheme == CHAIN_SCHEME_TABLEAU) {
+        for (int64_t i = 0; i < nsteps; ++i) {
+            hipError_t e = launch_naive_tableau_step(d.model, d.prec, h->front, h->naive_tab, d.n,
+                                                     d.dt, h->tableau, s);
+            if (e != hipSuccess) return hip_fail(e, "naive tableau step launch");
+        }
+        return CHAIN_OK;
+    }
     if (d.method == CHAIN_NAIVE) {
         for (int64_t i = 0; i < nsteps; ++i) {
             hipError_t e = d.model == CHAIN_ROESSLER
@@ -385,7 +394,16 @@ int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *
             h->back.cp = reinterpret_cast<float *>(ws + L.back_cp);
         }
     }
-    if (d->method == CHAIN_NAIVE) {
+    if (d->method == CHAIN_NAIVE && d->scheme == CHAIN_SCHEME_TABLEAU) {
+        NaiveTabBufs &b = h->naive_tab;
+        int k = 0;
+        for (int m = 0; m < kMaxStages - 1; ++m) b.kq[m] = ws + L.naive_tab[k++];
+        for (int m = 0; m < kMaxStages - 1; ++m) b.kp[m] = ws + L.naive_tab[k++];
+        b.qa = ws + L.naive_tab[k++];
+        b.pa = ws + L.naive_tab[k++];
+        b.qb = ws + L.naive_tab[k++];
+        b.pb = ws + L.naive_tab[k++];
+    } else if (d->method == CHAIN_NAIVE) {
         void **slots[10] = {&h->naive.k1q, &h->naive.k1p, &h->naive.k2q, &h->naive.k2p,
                             &h->naive.k3q, &h->naive.k3p, &h->naive.yaq, &h->naive.yap,
                             &h->naive.ybq, &h->naive.ybp};
@@ -516,12 +534,13 @@ int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t) {
     if (rc != CHAIN_OK) return rc;
     const int64_t reach = std::max<int64_t>(1, tableau_reach_of(a, model_range(h->d.model)));
     Plan P = make_plan(&h->d, reach, a.stages);
-    if (!tableau_shape_ok(a.stages, P.sites, P.waves_per_cluster))
+    if (h->d.method == CHAIN_FUSED && !tableau_shape_ok(a.stages, P.sites, P.waves_per_cluster))
         return fail(CHAIN_EINVAL,
                     "the tableau kernel runs sites_per_lane 4 or 8 (4 beyond 4 stages) and "
                     "waves_per_cluster 1 or 4 (got %d, %d for %d stages)",
                     P.sites, P.waves_per_cluster, a.stages);
-    if (P.tile < 1) return fail(CHAIN_EINVAL, "the cluster is too small for this tableau's reach");
+    if (h->d.method == CHAIN_FUSED && P.tile < 1)
+        return fail(CHAIN_EINVAL, "the cluster is too small for this tableau's reach");
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
     h->tableau = a;

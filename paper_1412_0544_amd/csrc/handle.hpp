@@ -44,4 +44,5 @@ struct chain_rk4 {
     std::map<int64_t, hipGraphExec_t> graphs;
     bool has_tableau = false;     // CHAIN_SCHEME_TABLEAU: set by chain_rk4_set_tableau
     chainrk4::TabArgs tableau{};
+    chainrk4::NaiveTabBufs naive_tab{};
 };

@@ -74,6 +74,18 @@ struct TabArgs {
 hipError_t launch_tableau(int model, int prec, int sites_per_lane, int waves_per_cluster,
                           const FusedPass &a, const TabArgs &t, hipStream_t s);
 
+// The per-stage implementation of a tableau method (Sec. 2.2 with general
+// coefficients): kernel j evaluates the slope k_j at its stage argument and
+// forms the next argument (or, for the last stage, the new state in place).
+// Slopes k_m of stages m < s-1 go through memory; the q part of k_0 is p.
+struct NaiveTabBufs {
+    void *kq[kMaxStages - 1];  // P_m, m = 1..s-2 (entry 0 unused)
+    void *kp[kMaxStages - 1];  // F(Q_m), m = 0..s-2
+    void *qa, *pa, *qb, *pb;   // stage arguments (ping-pong)
+};
+hipError_t launch_naive_tableau_step(int model, int prec, StateRef y, const NaiveTabBufs &b,
+                                     int64_t n, double dt, const TabArgs &t, hipStream_t s);
+
 // Roessler chain (FP64): fused cluster pass and the per-stage baseline.
 constexpr int kModelRoessler = 2;
 hipError_t launch_fused_roessler(int sites_per_lane, int waves_per_cluster, const FusedPass &a,

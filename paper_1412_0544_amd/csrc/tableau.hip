@@ -186,7 +186,121 @@ hipError_t tab_dispatch_prec(int prec, int s, int w, const FusedPass &a, const T
                      : tab_dispatch<M, float, true>(s, w, a, t, st);
 }
 
+constexpr int kNaiveTabThreads = 256;
+
+// Stage j of the per-stage implementation at site i: the slope k_j at the
+// stage argument (Qj from `arg`, with its neighbours; Pj), then the next stage
+// argument, or the final combination in place. Same per-site operation order
+// as tableau_kernel, so both give identical bits.
+template <int M, class R, bool KAHAN>
+__global__ __launch_bounds__(kNaiveTabThreads) void naive_tab_stage(StateRef y, NaiveTabBufs b,
+                                                                    const R *argq, const R *argp,
+                                                                    R *nextq, R *nextp, int j,
+                                                                    int64_t n, double dt_,
+                                                                    TabArgs t) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kNaiveTabThreads + threadIdx.x;
+    if (i >= n) return;
+    using Ops = ModelOps<M, R>;
+    const R dt = static_cast<R>(dt_);
+    R *yq = static_cast<R *>(y.q);
+    R *yp = static_cast<R *>(y.p);
+    const R Qj = argq[i];
+    const R Pj = argp[i];
+    R F;
+    if constexpr (coupling_range<M>() == 2) {
+        F = site_force2<M, R>(Ops::bond(Qj - argq[wrap_index(i - 1, n)]),
+                              Ops::bond(argq[wrap_index(i + 1, n)] - Qj),
+                              Ops::bond(Qj - argq[wrap_index(i - 2, n)]),
+                              Ops::bond(argq[wrap_index(i + 2, n)] - Qj), Qj);
+    } else {
+        F = site_force<M, R>(Ops::bond(Qj - argq[wrap_index(i - 1, n)]),
+                             Ops::bond(argq[wrap_index(i + 1, n)] - Qj), Qj);
+    }
+    const R qi = yq[i], pi = yp[i];
+    // slope m at this site: (P_m, F_m); stage j's comes from registers
+    auto kqm = [&](int m) -> R {
+        return m == j ? Pj : (m == 0 ? pi : static_cast<const R *>(b.kq[m])[i]);
+    };
+    auto kpm = [&](int m) -> R { return m == j ? F : static_cast<const R *>(b.kp[m])[i]; };
+    if (j + 1 < t.stages) {
+        if (j > 0) static_cast<R *>(b.kq[j])[i] = Pj;
+        static_cast<R *>(b.kp[j])[i] = F;
+        R sq = static_cast<R>(0), sp = static_cast<R>(0);
+        for (int m = 0; m <= j; ++m) {
+            const R c = static_cast<R>(t.a[j + 1][m]);
+            sq = fma_r(c, kqm(m), sq);
+            sp = fma_r(c, kpm(m), sp);
+        }
+        nextq[i] = fma_r(dt, sq, qi);
+        nextp[i] = fma_r(dt, sp, pi);
+    } else {
+        R fq = static_cast<R>(t.b[0]) * kqm(0);
+        R fp = static_cast<R>(t.b[0]) * kpm(0);
+        for (int m = 1; m < t.stages; ++m) {
+            const R c = static_cast<R>(t.b[m]);
+            fq = fma_r(c, kqm(m), fq);
+            fp = fma_r(c, kpm(m), fp);
+        }
+        if constexpr (KAHAN) {
+            R q1 = qi, p1 = pi;
+            float cq = y.cq[i], cp = y.cp[i];
+            kahan_add(q1, cq, dt * fq);
+            kahan_add(p1, cp, dt * fp);
+            yq[i] = q1;
+            yp[i] = p1;
+            y.cq[i] = cq;
+            y.cp[i] = cp;
+        } else {
+            yq[i] = fma_r(dt, fq, qi);
+            yp[i] = fma_r(dt, fp, pi);
+        }
+    }
+}
+
+template <int M, class R, bool KAHAN>
+hipError_t naive_tab_dispatch(StateRef y, const NaiveTabBufs &b, int64_t n, double dt,
+                              const TabArgs &t, hipStream_t st) {
+    const int64_t blocks = (n + kNaiveTabThreads - 1) / kNaiveTabThreads;
+    if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(blocks)), block(kNaiveTabThreads);
+    const R *aq = static_cast<const R *>(y.q), *ap = static_cast<const R *>(y.p);
+    if (t.stages == 1) {
+        // the only stage would read neighbours of q while writing q: read a copy
+        hipError_t e = hipMemcpyAsync(b.qa, y.q, n * sizeof(R), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        aq = static_cast<const R *>(b.qa);
+    }
+    for (int j = 0; j < t.stages; ++j) {
+        R *nq = static_cast<R *>(j % 2 == 0 ? b.qa : b.qb);
+        R *np = static_cast<R *>(j % 2 == 0 ? b.pa : b.pb);
+        if (t.stages == 1) nq = np = nullptr;
+        naive_tab_stage<M, R, KAHAN><<<grid, block, 0, st>>>(y, b, aq, ap, nq, np, j, n, dt, t);
+        aq = nq;
+        ap = np;
+    }
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t naive_tab_prec(int prec, StateRef y, const NaiveTabBufs &b, int64_t n, double dt,
+                          const TabArgs &t, hipStream_t st) {
+    return prec == 0 ? naive_tab_dispatch<M, double, false>(y, b, n, dt, t, st)
+                     : naive_tab_dispatch<M, float, true>(y, b, n, dt, t, st);
+}
+
 }  // namespace
+
+hipError_t launch_naive_tableau_step(int model, int prec, StateRef y, const NaiveTabBufs &b,
+                                     int64_t n, double dt, const TabArgs &t, hipStream_t st) {
+    if (t.stages < 1 || t.stages > kMaxStages) return hipErrorInvalidValue;
+    switch (model) {
+    case kQuartic: return naive_tab_prec<kQuartic>(prec, y, b, n, dt, t, st);
+    case kHarmonic: return naive_tab_prec<kHarmonic>(prec, y, b, n, dt, t, st);
+    case kQuarticNNN: return naive_tab_prec<kQuarticNNN>(prec, y, b, n, dt, t, st);
+    case kHarmonicNNN: return naive_tab_prec<kHarmonicNNN>(prec, y, b, n, dt, t, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_tableau(int model, int prec, int s, int w, const FusedPass &a, const TabArgs &t,
                           hipStream_t st) {

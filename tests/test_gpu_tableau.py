@@ -157,8 +157,6 @@ def test_errors():
         Chain(q0, p0, 0.01, sites_per_lane=16, tableau=tableau("kutta3"))
     with pytest.raises(ChainError):                        # 6 stages need 4 sites per lane
         Chain(q0, p0, 0.01, sites_per_lane=8, tableau=tableau("dopri5"))
-    with pytest.raises(ChainError):
-        Chain(q0, p0, 0.01, method="naive", tableau=tableau("kutta3"))
 
 
 def test_large_chain_sampled_sites():
@@ -176,3 +174,28 @@ def test_large_chain_sampled_sites():
         idx = np.arange(i - r, i + r + 1) % n
         qw, pw = oracle.rk_tableau(oracle.QUARTIC, q0[idx], p0[idx], 0.01, steps, a, b)
         assert abs(q[i] - qw[r]) <= TOL and abs(p[i] - pw[r]) <= TOL, i
+
+
+@pytest.mark.parametrize("name", sorted(TABLEAUS) + ["euler"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+@pytest.mark.parametrize("n", [1, 3, 5003])
+def test_per_stage_path_gives_the_fused_bits(name, prec, n):
+    """The one-kernel-per-stage implementation of a tableau method (the
+    paper's standard version, Sec. 2.2) and the fused cluster pass give the
+    same bits; for FP64 both match the oracle."""
+    a, b = ([[0.0]], [1.0]) if name == "euler" else tableau(name)
+    dtype = np.float64 if prec == "fp64" else np.float32
+    q0, p0 = workloads.chain_ics(n, 7, dtype=dtype)
+    outs = []
+    for method in ("fused", "naive"):
+        ch = Chain(q0, p0, 0.01, prec=prec, method=method, tableau=(a, b))
+        ch.step(23)
+        cq, cp = ch.carry_tensors()
+        outs.append([t.cpu().numpy().copy() for t in
+                     (ch.q, ch.p) + ((cq, cp) if cq is not None else ())])
+        ch.close()
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    if prec == "fp64":
+        qo, po = oracle.rk_tableau(oracle.QUARTIC, q0, p0, 0.01, 23, np.array(a), np.array(b))
+        assert maxerr(outs[0][0], qo) <= TOL and maxerr(outs[0][1], po) <= TOL
