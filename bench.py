@@ -180,6 +180,8 @@ def main(argv=None):
     ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only sweep N = 2^10..2^26, fused vs per-stage, T = 50, best of 10")
+    ap.add_argument("--plan-sweep", action="store_true",
+                    help="only the cluster-shape study over N = 2^10..2^26 (S, W, k)")
     ap.add_argument("--tableaus", action="store_true",
                     help="only the explicit methods by Butcher tableau on the bench chain")
     ap.add_argument("--roessler", action="store_true",
@@ -204,6 +206,12 @@ def main(argv=None):
                           "n_gpus": 1, "data": "synthetic", "dtype": "f64",
                           "config": {"workload": "quartic chain, dt=0.01, T=50 steps, best of 10"},
                           "size_sweep": size_sweep(dev)}), flush=True)
+        return 0
+    if args.plan_sweep:
+        print(json.dumps({"metric": "site-updates/sec by cluster shape and chain length",
+                          "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": "quartic chain, dt=0.01, 64 steps, best of 3"},
+                          "plan_sweep": plan_sweep(dev)}), flush=True)
         return 0
     if args.roessler:
         print(json.dumps({"metric": "RK4 steps/s of the Roessler chain (Perf = T / t_wall)",
@@ -239,7 +247,7 @@ def main(argv=None):
                                         use_cache=False)
         sweep = {f"s{s}_w{w}_k{k}": v for (s, w, k), v in sorted(table.items())}
     else:
-        probe = Chain(qd[:1 << 16], pd[:1 << 16], dt, resident=False, device=dev).plan()
+        probe = Chain(qd, pd, dt, resident=False, device=dev).plan()
         S, W, K = probe["sites_per_lane"], probe["waves_per_cluster"], probe["kdepth"]
     log(f"[bench] plan S={S} W={W} K={K}")
 
@@ -534,6 +542,38 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, 
     return out
 
 
+def variant_short_rings(dt, dev, steps=1000, jobs=5):
+    """Short rings, 1000-step jobs: the ring kept resident in one workgroup
+    (all steps in one launch) against the tiled plan (one launch per pass),
+    eager and replayed from a graph; p50 wall time of a job (step call plus
+    stream synchronisation)."""
+    import torch
+    import workloads
+    from paper_1412_0544_amd import Chain
+    out = {}
+    for n in (256, 1024, 4096):
+        q0, p0 = workloads.chain_ics(n, 0)
+        row = {}
+        for name, kw in (("resident", {"resident": True}), ("tiled", {}),
+                         ("tiled_graph", {"graph": True})):
+            ch = Chain(q0, p0, dt, device=dev, **kw)
+            ch.step(steps)
+            torch.cuda.synchronize()
+            lat = []
+            for _ in range(jobs):
+                t = time.perf_counter()
+                ch.step(steps)
+                ch.stream.synchronize()
+                lat.append(time.perf_counter() - t)
+            plan = ch.plan()
+            ch.close()
+            row[name] = {"p50_ms": 1e3 * pct(lat, 50),
+                         "plan": {x: plan[x] for x in ("resident", "sites_per_lane",
+                                                       "waves_per_cluster", "kdepth")}}
+        out[str(n)] = row
+    return out
+
+
 def variant_nnn(qd, pd, dt, n, dev, steps=480):
     """The quartic chain with second-neighbour bonds on the bench chain: the
     library plan (halo 4 per step) and the per-stage baseline, device time of
@@ -606,6 +646,47 @@ def variant_tableaus(qd, pd, dt, n, dev, steps=192, sweep=False):
     return out
 
 
+def plan_sweep(dev, dt=0.01, steps=64, exps=range(10, 27, 2), precs=("fp64", "fp32_kahan")):
+    """Cluster shape by chain length (the granularity study of Sec. 2.3 and
+    Sec. 3.2.1, over S, W, k and N): device time of `steps` steps, best of 3,
+    replayed from a captured graph so that launch overhead counts as little
+    as it can; the resident ring where it applies."""
+    import torch
+    import workloads
+    from paper_1412_0544_amd import Chain
+    out = {}
+    for prec in precs:
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        rows = []
+        for e in exps:
+            n = 1 << e
+            q, p = workloads.chain_ics_torch(n, 0, dev, dtype)
+            table = {}
+
+            def timed(**kw):
+                ch = Chain(q, p, dt, prec=prec, device=dev, graph=True, **kw)
+                ch.step(steps)
+                best = min(ev_seconds(lambda: ch.step(steps), ch.stream) for _ in range(3))
+                ch.close()
+                return n * steps / best
+
+            if n <= 4096:
+                table["resident"] = timed(resident=True)
+            for s_ in (4, 8, 16):
+                for w in (1, 2, 4, 8):
+                    for k in (4, 8, 16, 32):
+                        if 64 * s_ * w > 4 * k + 16:
+                            table[f"s{s_}_w{w}_k{k}"] = timed(sites_per_lane=s_, waves_per_cluster=w,
+                                                              kdepth=k, resident=False)
+            best = max(table, key=table.get)
+            rows.append({"n": n, "best": best, "best_su_per_s": table[best], "table": table})
+            log(f"[bench] plan sweep {prec} N=2^{e}: best {best} {table[best]:.3e} SU/s")
+            del q, p
+            torch.cuda.empty_cache()
+        out[prec] = rows
+    return out
+
+
 def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     """Other rows of the hot path, each measured at its own configuration."""
     from paper_1412_0544_amd import Chain, autotune
@@ -630,6 +711,8 @@ def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
     lat, g, _ = time_jobs(ch, 1000, 5)
     res["ring1024_1000steps_ms"] = {"p50": 1e3 * pct(lat, 50), "gpu_min": 1e3 * min(g)}
     ch.close()
+    log("[bench] variant: short rings, resident vs tiled")
+    res["short_rings_1000steps_ms"] = variant_short_rings(dt, dev)
     log("[bench] variant: FP32 with compensated update, 1e4 steps")
     res["precision"] = variant_precision(n, dt, dev)
     log("[bench] variant: 4096-chain batch")

@@ -108,8 +108,16 @@ enum chain_flags {
     CHAIN_FLAG_GRAPH = 1,        /* replay each distinct step count from a
                                     captured hipGraph instead of launching pass
                                     by pass */
-    CHAIN_FLAG_NO_RESIDENT = 2   /* never keep a short ring resident on chip;
-                                    always run the tiled passes */
+    CHAIN_FLAG_NO_RESIDENT = 2,  /* always run the tiled passes (the default
+                                    since the tiled plan measured faster at
+                                    every length; kept for compatibility) */
+    CHAIN_FLAG_RESIDENT = 4      /* keep a quartic or harmonic ring of at most
+                                    4096 sites resident on chip in one
+                                    workgroup for all steps of a call (one
+                                    launch per call, stage arguments in
+                                    LDS); CHAIN_EINVAL for longer rings,
+                                    other models or schemes, or together
+                                    with CHAIN_FLAG_NO_RESIDENT */
 };
 
 typedef enum chain_status {

@@ -66,7 +66,8 @@ class Chain:
     def __init__(self, q0, p0, dt: float, model="quartic", prec="fp64", method="fused",
                  sites_per_lane: int = 0, kdepth: int = 0, waves_per_cluster: int = 0,
                  graph: bool = False,
-                 resident: bool = True, device="cuda", stream: torch.cuda.Stream | None = None,
+                 resident: bool | None = None, device="cuda",
+                 stream: torch.cuda.Stream | None = None,
                  tableau=None):
         self.device = torch.device(device)
         dtype = state_dtype(prec)
@@ -74,7 +75,10 @@ class Chain:
         self.p = torch.as_tensor(p0).to(device=self.device, dtype=dtype).contiguous().clone()
         if self.q.ndim != 1 or self.q.shape != self.p.shape:
             raise ValueError("q0 and p0 must be 1-D of one length")
-        flags = (L.CHAIN_FLAG_GRAPH if graph else 0) | (0 if resident else L.CHAIN_FLAG_NO_RESIDENT)
+        # resident: None = the library plan (tiled), True = the ring stays in
+        # one workgroup for all steps of a call, False = tiled
+        flags = ((L.CHAIN_FLAG_GRAPH if graph else 0) |
+                 {None: 0, True: L.CHAIN_FLAG_RESIDENT, False: L.CHAIN_FLAG_NO_RESIDENT}[resident])
         scheme = L.CHAIN_SCHEME_RK4 if tableau is None else L.CHAIN_SCHEME_TABLEAU
         self.desc = L.Desc(self.q.numel(), _code(MODELS, model), _code(PRECS, prec), float(dt),
                            _code(METHODS, method), int(sites_per_lane), int(kdepth),

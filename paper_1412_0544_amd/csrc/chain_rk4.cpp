@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -63,6 +64,31 @@ size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kDefaultSitesFp64 = 8;
 constexpr int kDefaultSitesFp32 = 16;
 constexpr int kDefaultWaves = 4;
+
+// Cluster shape of the quartic and harmonic chains by chain length: the
+// fastest (S, W) at depth 32 of a sweep over S = 4, 8, 16, W = 1, 2, 4, 8,
+// k = 4..32 and N = 2^10..2^26 on MI355X (the granularity study of
+// Sec. 2.3 and 3.2.1). Short chains want many small one-wavefront clusters
+// (no barriers, every CU busy); long ones want few halos per site.
+struct ShapeRow {
+    int64_t max_n;
+    int sites, waves;
+};
+constexpr ShapeRow kShapeFp64[] = {
+    {int64_t(1) << 17, 4, 1}, {int64_t(1) << 21, 8, 1}, {INT64_MAX, 8, 4}};
+constexpr ShapeRow kShapeFp32[] = {{int64_t(1) << 19, 4, 1},
+                                   {int64_t(1) << 21, 8, 1},
+                                   {int64_t(1) << 23, 4, 8},
+                                   {INT64_MAX, 8, 8}};
+
+ShapeRow shape_for(int prec, int64_t n) {
+    const ShapeRow *rows = prec == CHAIN_FP64 ? kShapeFp64 : kShapeFp32;
+    const size_t count = prec == CHAIN_FP64 ? sizeof kShapeFp64 / sizeof kShapeFp64[0]
+                                            : sizeof kShapeFp32 / sizeof kShapeFp32[0];
+    for (size_t i = 0; i < count; ++i)
+        if (n <= rows[i].max_n) return rows[i];
+    return rows[count - 1];
+}
 // Roessler: nine S-site register arrays per lane instead of six, so fewer
 // sites per lane (the fastest shape at N = 2^20 in a sweep over S, W, k).
 constexpr int kDefaultSitesRoessler = 4;
@@ -103,8 +129,18 @@ int check_desc(const chain_rk4_desc *d) {
         if (d->model == CHAIN_ROESSLER)
             return fail(CHAIN_EINVAL, "a tableau method is not available for the Roessler chain");
     }
-    if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT))
+    if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT | CHAIN_FLAG_RESIDENT))
         return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
+    if (d->flags & CHAIN_FLAG_RESIDENT) {
+        if (d->flags & CHAIN_FLAG_NO_RESIDENT)
+            return fail(CHAIN_EINVAL, "CHAIN_FLAG_RESIDENT and CHAIN_FLAG_NO_RESIDENT exclude each other");
+        if (d->n > kResidentMaxSites)
+            return fail(CHAIN_EINVAL, "a resident ring holds at most %d sites", kResidentMaxSites);
+        if ((d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC) ||
+            d->scheme != CHAIN_SCHEME_RK4 || d->method != CHAIN_FUSED)
+            return fail(CHAIN_EINVAL, "resident rings run the classical RK4 of the quartic and "
+                                      "harmonic chains on the fused path only");
+    }
     return CHAIN_OK;
 }
 
@@ -211,17 +247,19 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages =
     const bool roessler = d->model == CHAIN_ROESSLER;
     const bool nn = d->model == CHAIN_QUARTIC || d->model == CHAIN_HARMONIC;
     const bool tab = d->scheme == CHAIN_SCHEME_TABLEAU;
-    if (nn && !tab && !(d->flags & CHAIN_FLAG_NO_RESIDENT) && d->n <= kResidentMaxSites &&
-        d->sites_per_lane == 0 && d->kdepth == 0 && d->waves_per_cluster == 0) {
+    if (d->flags & CHAIN_FLAG_RESIDENT) {  // validated: NN model, classical RK4, short ring
         P.resident = true;
         return P;
     }
+    const ShapeRow row = shape_for(d->prec, d->n);
     P.sites = d->sites_per_lane ? d->sites_per_lane
               : roessler        ? kDefaultSitesRoessler
               : tab             ? default_sites_tableau(stages)
+              : nn              ? row.sites
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
                           : roessler             ? kDefaultWavesRoessler
+                          : nn && !tab           ? row.waves
                                                  : kDefaultWaves;
     const int64_t reach = reach_override > 0 ? reach_override : step_reach(d->model);
     P.depth = d->kdepth ? d->kdepth

@@ -74,7 +74,7 @@ def test_harmonic_fused_matches_oracle(n):
 def test_resident_naive_and_tiled_identical_bits(n, model):
     q0, p0 = workloads.chain_ics(n, 3)
     ref = gpu_run(q0, p0, 0.01, 37, model=model, sites_per_lane=8, kdepth=5, resident=False)
-    res = gpu_run(q0, p0, 0.01, 37, model=model)
+    res = gpu_run(q0, p0, 0.01, 37, model=model, resident=True)
     assert res[3]["resident"] == 1
     nav = gpu_run(q0, p0, 0.01, 37, model=model, method="naive")
     for other in (res, nav):
@@ -101,8 +101,11 @@ def test_tile_shapes_and_depths_identical_bits():
 def test_ring_1024_1000_steps(seed):
     """The 1024-site ring, dt = 0.01, 1000 steps, resident on chip."""
     q0, p0 = workloads.chain_ics(1024, seed)
-    q, p, e, plan = gpu_run(q0, p0, 0.01, 1000)
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 1000, resident=True)
     assert plan["resident"] == 1
+    q2, p2, e2, plan2 = gpu_run(q0, p0, 0.01, 1000)               # library plan: tiled
+    assert plan2["resident"] == 0
+    assert np.array_equal(q2, q) and np.array_equal(p2, p) and e2 == e
     qo, po = oracle_run("quartic", 1024, seed, 0.01, 1000)
     assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
     eo = oracle.energy(oracle.QUARTIC, qo, po)
@@ -262,7 +265,7 @@ def test_fp32_paths_identical_bits():
     for kw in (dict(sites_per_lane=16, kdepth=4, resident=False),
                dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1, resident=False),
                dict(sites_per_lane=4, kdepth=12, waves_per_cluster=8, resident=False),
-               dict(method="naive"), dict()):
+               dict(method="naive"), dict(resident=True), dict()):
         ch = Chain(q0, p0, 0.01, prec="fp32_kahan", **kw)
         ch.step(30)
         cq, cp = ch.carry_tensors()
