@@ -118,10 +118,6 @@ hipError_t launch_fused(int model, int prec, int s, int w, const FusedPass &a, h
     }
 }
 
-size_t resident_lds_bytes(int prec, int64_t n) {
-    return 2 * static_cast<size_t>(n) * (prec == 0 ? sizeof(double) : sizeof(float));
-}
-
 hipError_t launch_resident(int model, int prec, const ResidentRun &a, hipStream_t st) {
     if (a.n < 1 || a.n > kResidentMaxSites) return hipErrorInvalidValue;
     if (model == kQuartic) {

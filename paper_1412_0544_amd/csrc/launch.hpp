@@ -57,7 +57,6 @@ constexpr int kFusedThreads = 256;        // 4 one-wavefront clusters per block
 hipError_t launch_fused(int model, int prec, int sites_per_lane, int waves_per_cluster,
                         const FusedPass &a, hipStream_t s);
 hipError_t launch_resident(int model, int prec, const ResidentRun &a, hipStream_t s);
-size_t resident_lds_bytes(int prec, int64_t n);
 hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,
                              double dt, hipStream_t s);
 

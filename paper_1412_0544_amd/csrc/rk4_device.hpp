@@ -119,8 +119,6 @@ __device__ __forceinline__ void kahan_add(float &y, float &c, float delta) {
 // ---------------------------------------------------------------------------
 constexpr int kDppWaveShl1 = 0x130;  // wave_shl:1
 constexpr int kDppWaveShr1 = 0x138;  // wave_shr:1
-constexpr int kDppWaveRol1 = 0x134;  // wave_rol:1
-constexpr int kDppWaveRor1 = 0x13C;  // wave_ror:1
 
 template <int Ctrl>
 __device__ __forceinline__ int dpp32(int x) {
@@ -144,11 +142,6 @@ template <class R>
 __device__ __forceinline__ R from_right(R x) { return dpp<kDppWaveShl1>(x); }
 template <class R>
 __device__ __forceinline__ R from_left(R x) { return dpp<kDppWaveShr1>(x); }
-// Rotations (lane 63 <-> lane 0) for a ring held by exactly one wavefront.
-template <class R>
-__device__ __forceinline__ R from_right_ring(R x) { return dpp<kDppWaveRol1>(x); }
-template <class R>
-__device__ __forceinline__ R from_left_ring(R x) { return dpp<kDppWaveRor1>(x); }
 
 // ---------------------------------------------------------------------------
 // The per-site part of stage STAGE once the force F at the stage argument
@@ -266,18 +259,6 @@ __device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R 
     const R bl = ModelOps<M, R>::bond(Qj - Qm);
     const R br = ModelOps<M, R>::bond(Qp - Qj);
     const R F = site_force<M, R>(bl, br, Qj);
-    site_update<STAGE>(F, Pj, Qn, Pn, qj, pj, aq, ap, c);
-}
-
-// The same for one site of a next-nearest-neighbour chain (naive kernel).
-template <int M, int STAGE, class R>
-__device__ __forceinline__ void stage_one_nnn(R Qmm, R Qm, R Qj, R Qp, R Qpp, R Pj, R qj, R pj,
-                                              R &aq, R &ap, R &Qn, R &Pn, const StepConsts<R> &c) {
-    const R b1l = ModelOps<M, R>::bond(Qj - Qm);
-    const R b1r = ModelOps<M, R>::bond(Qp - Qj);
-    const R b2l = ModelOps<M, R>::bond(Qj - Qmm);
-    const R b2r = ModelOps<M, R>::bond(Qpp - Qj);
-    const R F = site_force2<M, R>(b1l, b1r, b2l, b2r, Qj);
     site_update<STAGE>(F, Pj, Qn, Pn, qj, pj, aq, ap, c);
 }
 
