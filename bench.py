@@ -53,9 +53,9 @@ BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 # the kernel sources with this sha256 and this cluster shape (sites per lane,
 # wavefronts per cluster, halo) on N = 2^24.
 MEASURED_TRAFFIC = {
-    "sha256": "f1750eb5b8dd69d82258c1fe1e729689de763d25db5b1f32a94f919898015459",
+    "sha256": "a6e4977bd50c7b70cbf662c9022eedb190a4dcfb137c398f654c1178e1dd65da",
     "shape": (8, 4, 64), "n": 1 << 24,
-    "bytes_per_launch": 555327933, "fetch_factor": 0.5000, "write_factor": 1.0000,
+    "bytes_per_launch": 555308115, "fetch_factor": 0.5000, "write_factor": 1.0000,
 }
 
 
@@ -182,6 +182,8 @@ def main(argv=None):
                     help="only sweep N = 2^10..2^26, fused vs per-stage, T = 50, best of 10")
     ap.add_argument("--plan-sweep", action="store_true",
                     help="only the cluster-shape study over N = 2^10..2^26 (S, W, k)")
+    ap.add_argument("--nnn", action="store_true",
+                    help="only the quartic chain with second-neighbour bonds on the bench chain")
     ap.add_argument("--tableaus", action="store_true",
                     help="only the explicit methods by Butcher tableau on the bench chain")
     ap.add_argument("--roessler", action="store_true",
@@ -225,6 +227,12 @@ def main(argv=None):
     q0, p0 = workloads.chain_ics(n, 0)
     qd = torch.from_numpy(q0).to(dev)
     pd = torch.from_numpy(p0).to(dev)
+    if args.nnn:
+        print(json.dumps({"metric": "site-updates/sec, second-neighbour bonds",
+                          "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
+                          "dtype": "f64", "config": {"workload": "quartic NNN chain N=2^24, dt=0.01"},
+                          "quartic_nnn": variant_nnn(qd, pd, dt, n, dev)}), flush=True)
+        return 0
     if args.tableaus:
         print(json.dumps({"metric": "site-updates/sec by explicit RK method",
                           "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
