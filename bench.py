@@ -53,9 +53,9 @@ BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 # the kernel sources with this sha256 and this cluster shape (sites per lane,
 # wavefronts per cluster, halo) on N = 2^24.
 MEASURED_TRAFFIC = {
-    "sha256": "a6e4977bd50c7b70cbf662c9022eedb190a4dcfb137c398f654c1178e1dd65da",
+    "sha256": "359b0ed04907d491d88b3de0f651e9984393cb213c8977228795d040fec0c7e9",
     "shape": (8, 4, 64), "n": 1 << 24,
-    "bytes_per_launch": 555308115, "fetch_factor": 0.5000, "write_factor": 1.0000,
+    "bytes_per_launch": 555252619, "fetch_factor": 0.5000, "write_factor": 1.0000,
 }
 
 
@@ -680,9 +680,9 @@ def plan_sweep(dev, dt=0.01, steps=64, exps=range(10, 27, 2), precs=("fp64", "fp
 
             if n <= 4096:
                 table["resident"] = timed(resident=True)
-            for s_ in (4, 8, 16):
+            for s_ in (2, 4, 8, 16):
                 for w in (1, 2, 4, 8):
-                    for k in (4, 8, 16, 32):
+                    for k in (4, 8, 16, 24, 32):
                         if 64 * s_ * w > 4 * k + 16:
                             table[f"s{s_}_w{w}_k{k}"] = timed(sites_per_lane=s_, waves_per_cluster=w,
                                                               kdepth=k, resident=False)

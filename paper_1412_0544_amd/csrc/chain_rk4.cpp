@@ -66,20 +66,24 @@ constexpr int kDefaultSitesFp32 = 16;
 constexpr int kDefaultWaves = 4;
 
 // Cluster shape of the quartic and harmonic chains by chain length: the
-// fastest (S, W) at depth 32 of a sweep over S = 4, 8, 16, W = 1, 2, 4, 8,
-// k = 4..32 and N = 2^10..2^26 on MI355X (the granularity study of
-// Sec. 2.3 and 3.2.1). Short chains want many small one-wavefront clusters
-// (no barriers, every CU busy); long ones want few halos per site.
+// fastest (S, W, k) of two sweeps over S = 2..16, W = 1..8, k = 4..32 and
+// N = 2^10..2^26 on MI355X (the granularity study of Sec. 2.3 and 3.2.1).
+// Short chains want many small one-wavefront clusters (no barriers, every
+// CU busy, few instructions per wavefront and step); long ones want few halo
+// sites per kept site.
 struct ShapeRow {
     int64_t max_n;
-    int sites, waves;
+    int sites, waves, depth;
 };
-constexpr ShapeRow kShapeFp64[] = {
-    {int64_t(1) << 17, 4, 1}, {int64_t(1) << 21, 8, 1}, {INT64_MAX, 8, 4}};
-constexpr ShapeRow kShapeFp32[] = {{int64_t(1) << 19, 4, 1},
-                                   {int64_t(1) << 21, 8, 1},
-                                   {int64_t(1) << 23, 4, 8},
-                                   {INT64_MAX, 8, 8}};
+constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 17, 2, 1, 16},
+                                   {int64_t(1) << 19, 4, 1, 32},
+                                   {int64_t(1) << 21, 8, 1, 32},
+                                   {INT64_MAX, 8, 4, 32}};
+constexpr ShapeRow kShapeFp32[] = {{int64_t(1) << 17, 2, 1, 16},
+                                   {int64_t(1) << 19, 4, 1, 32},
+                                   {int64_t(1) << 21, 8, 1, 32},
+                                   {int64_t(1) << 23, 4, 8, 32},
+                                   {INT64_MAX, 8, 8, 32}};
 
 ShapeRow shape_for(int prec, int64_t n) {
     const ShapeRow *rows = prec == CHAIN_FP64 ? kShapeFp64 : kShapeFp32;
@@ -99,7 +103,7 @@ constexpr int kDefaultWavesRoessler = 4;
 constexpr int kDefaultHalo = 64;
 constexpr int kMaxDepth = 32;
 
-bool valid_sites(int s) { return s == 4 || s == 8 || s == 16; }
+bool valid_sites(int s) { return s == 2 || s == 4 || s == 8 || s == 16; }
 bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
 
 int check_desc(const chain_rk4_desc *d) {
@@ -117,7 +121,9 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->method != CHAIN_FUSED && d->method != CHAIN_NAIVE)
         return fail(CHAIN_EINVAL, "unknown method %d", d->method);
     if (d->sites_per_lane != 0 && !valid_sites(d->sites_per_lane))
-        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16 (got %d)", d->sites_per_lane);
+        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 2, 4, 8 or 16 (got %d)", d->sites_per_lane);
+    if (d->sites_per_lane == 2 && d->model == CHAIN_ROESSLER)
+        return fail(CHAIN_EINVAL, "the Roessler kernel takes sites_per_lane 4, 8 or 16");
     if (d->kdepth < 0 || d->kdepth > kMaxDepth)
         return fail(CHAIN_EINVAL, "kdepth must be in 0..%d (got %d)", kMaxDepth, d->kdepth);
     if (d->waves_per_cluster != 0 && !valid_waves(d->waves_per_cluster))
@@ -262,8 +268,11 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages =
                           : nn && !tab           ? row.waves
                                                  : kDefaultWaves;
     const int64_t reach = reach_override > 0 ? reach_override : step_reach(d->model);
-    P.depth = d->kdepth ? d->kdepth
-                        : static_cast<int>(std::min<int64_t>(kMaxDepth, std::max<int64_t>(1, kDefaultHalo / reach)));
+    const bool table_shape = nn && !tab && !d->sites_per_lane && !d->waves_per_cluster;
+    P.depth = d->kdepth      ? d->kdepth
+              : table_shape ? row.depth
+                            : static_cast<int>(std::min<int64_t>(
+                                  kMaxDepth, std::max<int64_t>(1, kDefaultHalo / reach)));
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
     // the kept part of a cluster must stay positive: E > 2*halo
     while (E <= 2 * reach * P.depth && P.depth > 1) --P.depth;

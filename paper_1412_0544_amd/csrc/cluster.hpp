@@ -11,9 +11,11 @@
 
 namespace chainrk4 {
 
+// Contiguous loads and stores of a lane's S sites with the widest vector
+// access S allows (the caller guarantees the alignment of that width).
 template <class R, int S>
 __device__ __forceinline__ void load_contig(R (&dst)[S], const R *__restrict__ src) {
-    if constexpr (sizeof(R) == 8) {
+    if constexpr (sizeof(R) == 8 && S % 2 == 0) {
         const double2 *v = reinterpret_cast<const double2 *>(src);
 #pragma unroll
         for (int m = 0; m < S / 2; ++m) {
@@ -21,7 +23,7 @@ __device__ __forceinline__ void load_contig(R (&dst)[S], const R *__restrict__ s
             dst[2 * m] = t.x;
             dst[2 * m + 1] = t.y;
         }
-    } else {
+    } else if constexpr (sizeof(R) == 4 && S % 4 == 0) {
         const float4 *v = reinterpret_cast<const float4 *>(src);
 #pragma unroll
         for (int m = 0; m < S / 4; ++m) {
@@ -31,20 +33,38 @@ __device__ __forceinline__ void load_contig(R (&dst)[S], const R *__restrict__ s
             dst[4 * m + 2] = t.z;
             dst[4 * m + 3] = t.w;
         }
+    } else if constexpr (sizeof(R) == 4 && S % 2 == 0) {
+        const float2 *v = reinterpret_cast<const float2 *>(src);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) {
+            float2 t = v[m];
+            dst[2 * m] = t.x;
+            dst[2 * m + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < S; ++m) dst[m] = src[m];
     }
 }
 
 template <class R, int S>
 __device__ __forceinline__ void store_contig(R *__restrict__ dst, const R (&src)[S]) {
-    if constexpr (sizeof(R) == 8) {
+    if constexpr (sizeof(R) == 8 && S % 2 == 0) {
         double2 *v = reinterpret_cast<double2 *>(dst);
 #pragma unroll
         for (int m = 0; m < S / 2; ++m) v[m] = make_double2(src[2 * m], src[2 * m + 1]);
-    } else {
+    } else if constexpr (sizeof(R) == 4 && S % 4 == 0) {
         float4 *v = reinterpret_cast<float4 *>(dst);
 #pragma unroll
         for (int m = 0; m < S / 4; ++m)
             v[m] = make_float4(src[4 * m], src[4 * m + 1], src[4 * m + 2], src[4 * m + 3]);
+    } else if constexpr (sizeof(R) == 4 && S % 2 == 0) {
+        float2 *v = reinterpret_cast<float2 *>(dst);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) v[m] = make_float2(src[2 * m], src[2 * m + 1]);
+    } else {
+#pragma unroll
+        for (int m = 0; m < S; ++m) dst[m] = src[m];
     }
 }
 

@@ -75,6 +75,7 @@ hipError_t fused_dispatch_w(int w, const FusedPass &a, hipStream_t st) {
 template <int M, class R, bool KAHAN>
 hipError_t fused_dispatch_s(int s, int w, const FusedPass &a, hipStream_t st) {
     switch (s) {
+    case 2: return fused_dispatch_w<M, R, KAHAN, 2>(w, a, st);
     case 4: return fused_dispatch_w<M, R, KAHAN, 4>(w, a, st);
     case 8: return fused_dispatch_w<M, R, KAHAN, 8>(w, a, st);
     case 16: return fused_dispatch_w<M, R, KAHAN, 16>(w, a, st);

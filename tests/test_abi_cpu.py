@@ -45,7 +45,7 @@ def test_workspace_bytes():
     assert f(desc(n=1 << 20, method=1, scheme=1)) >= 18 * 8 * (1 << 20)
     for bad in (desc(n=0), desc(model=7), desc(prec=3), desc(dt=float("nan")),
                 desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
-                desc(kdepth=33), desc(kdepth=-1), desc(model=5), desc(model=2, prec=1), desc(flags=64), desc(waves_per_cluster=3),
+                desc(kdepth=33), desc(kdepth=-1), desc(sites_per_lane=2, model=2), desc(sites_per_lane=1), desc(model=5), desc(model=2, prec=1), desc(flags=64), desc(waves_per_cluster=3),
                 desc(waves_per_cluster=16), desc(scheme=7), desc(scheme=1, model=2),
                 desc(flags=4, n=4097), desc(flags=6), desc(flags=4, model=3),
                 desc(flags=4, scheme=1), desc(flags=4, method=1)):

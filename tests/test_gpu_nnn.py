@@ -45,7 +45,8 @@ def maxerr(a, b):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 64, 257, 1000, 5003, 20011])
 @pytest.mark.parametrize("sites,waves,depth", [(4, 1, 1), (8, 2, 3), (16, 1, 8), (8, 4, 16),
-                                               (4, 8, 4), (16, 8, 12), (8, 4, 32)])
+                                               (4, 8, 4), (16, 8, 12), (8, 4, 32), (2, 1, 4),
+                                               (2, 4, 8)])
 def test_quartic_nnn_fused_matches_oracle(n, sites, waves, depth):
     q0, p0 = workloads.chain_ics(n, 1)
     q, p, e, plan, _ = gpu_run(q0, p0, 0.01, 100, model="quartic_nnn", sites_per_lane=sites,
@@ -73,7 +74,8 @@ def test_every_path_identical_bits(model, n):
     q0, p0 = workloads.chain_ics(n, 3)
     ref = gpu_run(q0, p0, 0.01, 37, model=model)
     outs = [gpu_run(q0, p0, 0.01, 37, model=model, method="naive")]
-    for s, w, k in [(4, 1, 2), (8, 1, 5), (16, 2, 3), (4, 8, 16), (8, 4, 24), (16, 4, 32)]:
+    for s, w, k in [(4, 1, 2), (8, 1, 5), (16, 2, 3), (4, 8, 16), (8, 4, 24), (16, 4, 32),
+                    (2, 1, 3), (2, 8, 16)]:
         outs.append(gpu_run(q0, p0, 0.01, 37, model=model, sites_per_lane=s,
                             waves_per_cluster=w, kdepth=k))
     for o in outs:

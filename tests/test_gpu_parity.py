@@ -43,7 +43,8 @@ def maxerr(a, b):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257, 1000, 5003, 20011])
 @pytest.mark.parametrize("sites,waves,depth", [(4, 1, 1), (8, 2, 3), (16, 1, 8), (8, 4, 16),
-                                               (4, 8, 4), (8, 4, 12), (16, 8, 12)])
+                                               (4, 8, 4), (8, 4, 12), (16, 8, 12), (2, 1, 5),
+                                               (2, 4, 16), (8, 4, 32)])
 def test_fused_tiled_matches_oracle(n, sites, waves, depth):
     q0, p0 = workloads.chain_ics(n, 1)
     q, p, e, plan = gpu_run(q0, p0, 0.01, 100, sites_per_lane=sites, waves_per_cluster=waves,
@@ -88,7 +89,7 @@ def test_tile_shapes_and_depths_identical_bits():
     q0, p0 = workloads.chain_ics(n, 4)
     ref = gpu_run(q0, p0, 0.01, 24, sites_per_lane=4, waves_per_cluster=1, kdepth=1,
                   resident=False)
-    for s in (4, 8, 16):
+    for s in (2, 4, 8, 16):
         for w in (1, 2, 4, 8):
             for k in (2, 3, 8, 12, 16, 24, 32):
                 got = gpu_run(q0, p0, 0.01, 24, sites_per_lane=s, waves_per_cluster=w, kdepth=k,
@@ -265,6 +266,8 @@ def test_fp32_paths_identical_bits():
     for kw in (dict(sites_per_lane=16, kdepth=4, resident=False),
                dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1, resident=False),
                dict(sites_per_lane=4, kdepth=12, waves_per_cluster=8, resident=False),
+               dict(sites_per_lane=2, kdepth=5, waves_per_cluster=2),
+               dict(sites_per_lane=2, kdepth=9, waves_per_cluster=1),
                dict(method="naive"), dict(resident=True), dict()):
         ch = Chain(q0, p0, 0.01, prec="fp32_kahan", **kw)
         ch.step(30)
