@@ -386,10 +386,11 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
 
 def variant_batch(dt, dev, steps=2000, count=4096):
     """4096 chains, lengths log-uniform in [256, 65536], one persistent
-    launch of `steps` steps, FP64 and FP32 with compensated update."""
+    launch of `steps` steps, FP64 and FP32 with compensated update, at the
+    shape the batch autotuner picks."""
     import torch
     import workloads
-    from paper_1412_0544_amd import Batch, Chain
+    from paper_1412_0544_amd import Batch, Chain, autotune
     lengths = workloads.batch_lengths(count)
     tot = int(lengths.sum())
     out = {"chains": count, "sites": tot, "steps": steps}
@@ -397,20 +398,20 @@ def variant_batch(dt, dev, steps=2000, count=4096):
         dtype = torch.float64 if prec == "fp64" else torch.float32
         chains = [Chain(*workloads.chain_ics_torch(int(n_), 1000 + i, dev, dtype), dt, prec=prec,
                         device=dev) for i, n_ in enumerate(lengths)]
-        for depth in (16, 32):
-            b = Batch(chains, max_steps=steps, sites_per_lane=4, kdepth=depth)
-            b.step(24)
-            b.check()
-            t = ev_seconds(lambda: b.step(steps), chains[0].stream)
-            b.check()
-            plan = b.plan()
-            r = {"su_per_s": tot * steps / t, "ms": t * 1e3, "kdepth": depth,
-                 "grid_blocks": plan["grid_blocks"], "resident_chains": plan["resident_chains"],
-                 "clusters": plan["total_clusters"]}
-            b.close()
-            if prec not in out or r["su_per_s"] > out[prec]["su_per_s"]:
-                out[prec] = r
-            out.setdefault(f"{prec}_by_depth", {})[str(depth)] = r["su_per_s"]
+        # the batch autotuner picks (sites per lane, depth) on these chains
+        (S, K), table = autotune.tune_batch(chains, use_cache=False)
+        out[f"{prec}_autotune_su_per_s"] = {f"s{s_}_k{k_}": v for (s_, k_), v in table.items()}
+        b = Batch(chains, max_steps=steps, sites_per_lane=S, kdepth=K)
+        b.step(24)
+        b.check()
+        t = ev_seconds(lambda: b.step(steps), chains[0].stream)
+        b.check()
+        plan = b.plan()
+        out[prec] = {"su_per_s": tot * steps / t, "ms": t * 1e3, "sites_per_lane": S,
+                     "kdepth": K, "grid_blocks": plan["grid_blocks"],
+                     "resident_chains": plan["resident_chains"],
+                     "clusters": plan["total_clusters"]}
+        b.close()
         if prec == "fp64":
             # the same chains, one step call per chain (100 steps each)
             torch.cuda.synchronize()

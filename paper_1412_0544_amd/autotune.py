@@ -1,4 +1,5 @@
-"""Autotuner for the fused kernel's cluster shape.
+"""Autotuner for the fused kernel's cluster shape, and for the shape of a
+persistent batch.
 
 The paper picks its cluster size G from a performance study over G
 (Sec. 2.3, Sec. 3.2.1). On the GPU the cluster is 64*S*W sites (S sites per
@@ -120,5 +121,76 @@ def tune(n: int, model: str = "quartic", prec: str = "fp64", dt: float = 0.01,
         entries = _load()
         entries[k_] = {"best": list(best),
                        "table": {",".join(map(str, s)): v for s, v in table.items()}}
+        _store(entries)
+    return best, table
+
+
+BATCH_CANDIDATES = ((4, 16), (4, 32), (8, 16), (8, 32))
+
+
+def _snapshot(chains):
+    out = []
+    for c in chains:
+        cq, cp = c.carry_tensors()
+        out.append([t.clone() for t in (c.q, c.p) + ((cq, cp) if cq is not None else ())])
+    return out
+
+
+def _restore(chains, snap):
+    for c, saved in zip(chains, snap):
+        cq, cp = c.carry_tensors()
+        for dst, src in zip((c.q, c.p) + ((cq, cp) if cq is not None else ()), saved):
+            dst.copy_(src)
+
+
+def batch_key(chains) -> str:
+    c = chains[0]
+    name = torch.cuda.get_device_name(c.device).replace(" ", "_")
+    total = sum(x.q.numel() for x in chains)
+    return (f"{name}|batch|{c.desc.model}|{c.desc.prec}|{len(chains)}|{bucket(total)}")
+
+
+def tune_batch(chains, steps: int = 64, reps: int = 2, candidates=BATCH_CANDIDATES,
+               use_cache: bool = True):
+    """Return (best (sites_per_lane, kdepth), {shape: SU/s}) for a persistent
+    batch over `chains`: each candidate runs `steps` steps `reps` times on the
+    chains' own state (saved before and restored after, so the chains end as
+    they started), timed on the device."""
+    from .batch import Batch
+    k_ = batch_key(chains)
+    with _lock:
+        if use_cache:
+            hit = _load().get(k_)
+            if hit:
+                return tuple(hit["best"]), {tuple(map(int, s.split(","))): v
+                                            for s, v in hit["table"].items()}
+    total = sum(x.q.numel() for x in chains)
+    snap = _snapshot(chains)
+    stream = chains[0].stream
+    table = {}
+    try:
+        for s, k in candidates:
+            b = Batch(chains, max_steps=steps, sites_per_lane=s, kdepth=k, stream=stream)
+            try:
+                best = 0.0
+                for _ in range(reps + 1):           # the first run warms up
+                    a = torch.cuda.Event(enable_timing=True)
+                    e = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    b.step(steps)
+                    e.record(stream)
+                    b.check()
+                    best = max(best, total * steps / (a.elapsed_time(e) / 1e3))
+                table[(s, k)] = best
+            finally:
+                b.close()
+    finally:
+        _restore(chains, snap)
+        torch.cuda.synchronize(chains[0].device)
+    best = max(table, key=table.get)
+    with _lock:
+        entries = _load()
+        entries[k_] = {"best": list(best), "table": {",".join(map(str, s)): v
+                                                     for s, v in table.items()}}
         _store(entries)
     return best, table

@@ -186,3 +186,26 @@ def test_workload_4096_chains_sampled():
         sites = np.unique(np.linspace(0, n - 1, 9).astype(np.int64))
         qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, 0.01, 100, sites, threads=8)
         assert np.abs(got[0][sites] - qs).max() <= TOL and np.abs(got[1][sites] - ps).max() <= TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_batch_autotuner_leaves_the_chains_as_they_were(prec, tmp_path, monkeypatch):
+    """The batch autotuner times its candidates on the chains' own state and
+    restores it bit for bit; the shape it returns is one of its candidates,
+    and a second call is served from its cache."""
+    from paper_1412_0544_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    dtype = np.float64 if prec == "fp64" else np.float32
+    chains = [Chain(*workloads.chain_ics(n, 30 + i, dtype=dtype), 0.01, prec=prec)
+              for i, n in enumerate((700, 3000, 20000, 90000))]
+    before = [[t.clone() for t in (c.q, c.p) + tuple(x for x in c.carry_tensors()
+                                                    if x is not None)] for c in chains]
+    best, table = autotune.tune_batch(chains, steps=16, reps=1)
+    assert best in autotune.BATCH_CANDIDATES and set(table) == set(autotune.BATCH_CANDIDATES)
+    for c, saved in zip(chains, before):
+        now = (c.q, c.p) + tuple(x for x in c.carry_tensors() if x is not None)
+        for a, b in zip(now, saved):
+            assert torch.equal(a, b)
+    assert autotune.tune_batch(chains)[0] == best          # cached
+    for c in chains:
+        c.close()
