@@ -150,7 +150,7 @@ def batch_key(chains) -> str:
     return (f"{name}|batch|{c.desc.model}|{c.desc.prec}|{len(chains)}|{bucket(total)}")
 
 
-def tune_batch(chains, steps: int = 64, reps: int = 2, candidates=BATCH_CANDIDATES,
+def tune_batch(chains, steps: int = 256, reps: int = 2, candidates=BATCH_CANDIDATES,
                use_cache: bool = True):
     """Return (best (sites_per_lane, kdepth), {shape: SU/s}) for a persistent
     batch over `chains`: each candidate runs `steps` steps `reps` times on the

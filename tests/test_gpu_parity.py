@@ -277,3 +277,29 @@ def test_fp32_paths_identical_bits():
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
+
+
+def test_chain_longer_than_two_to_the_31():
+    """N = 2^31 + 12345 sites (34 GB of state): 64-bit site indexing in every
+    kernel of the default plan. Sampled sites, including those around 2^31
+    and both ring ends, against the oracle on windows cut from the same
+    initial state (whose values are drawn per site index)."""
+    n, steps = (1 << 31) + 12345, 10
+    q0, p0 = workloads.chain_ics_torch(n, 9, "cuda")
+    ch = Chain(q0, p0, 0.01)
+    del q0, p0
+    torch.cuda.empty_cache()
+    ch.step(steps)
+    e = ch.energy()
+    assert np.isfinite(e)
+    r = 4 * steps
+    sites = [0, 1, (1 << 31) - 1, 1 << 31, (1 << 31) + 1, n - 2, n - 1, 987654321]
+    idx = torch.tensor(sites, device="cuda")
+    qg, pg = ch.q[idx].cpu().numpy(), ch.p[idx].cpu().numpy()
+    ch.close()
+    for k, i in enumerate(sites):
+        w = (np.arange(i - r, i + r + 1) % n).astype(np.uint64)
+        qw = 2.0 * workloads.uniform01(9, 2 * w) - 1.0
+        pw = 2.0 * workloads.uniform01(9, 2 * w + 1) - 1.0
+        qo, po = oracle.rk4(oracle.QUARTIC, qw, pw, 0.01, steps)
+        assert abs(qg[k] - qo[r]) <= TOL and abs(pg[k] - po[r]) <= TOL, i

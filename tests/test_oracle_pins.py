@@ -294,3 +294,16 @@ def test_roessler_ics_range_and_interleave():
         assert v.min() >= -1.0 and v.max() < 1.0 and abs(v.mean()) < 0.1
     u = workloads.uniform01(9, np.array([15, 16, 17], dtype=np.uint64))
     assert (x[5], y[5], z[5]) == tuple(2 * u - 1)
+
+
+def test_device_ic_generator_matches_host_on_cpu():
+    """The torch version of the initial-state generator (used to make long
+    chains on the device) gives the host generator's bits, across its chunk
+    boundaries and in FP32."""
+    import torch
+    for n, chunk in ((1000, 64), (4097, 1 << 26), (1, 1)):
+        q, p = workloads.chain_ics_torch(n, 11, "cpu", chunk=chunk)
+        q0, p0 = workloads.chain_ics(n, 11)
+        assert np.array_equal(q.numpy(), q0) and np.array_equal(p.numpy(), p0)
+    q, _ = workloads.chain_ics_torch(300, 2, "cpu", torch.float32, chunk=7)
+    assert np.array_equal(q.numpy(), workloads.chain_ics(300, 2, dtype=np.float32)[0])

@@ -87,8 +87,9 @@ def _as_i64(x: int) -> int:
     return x - (1 << 64) if x >= (1 << 63) else x
 
 
-def chain_ics_torch(n: int, seed: int, device, dtype=None):
-    """Same values as ``chain_ics``, generated with torch on ``device``.
+def chain_ics_torch(n: int, seed: int, device, dtype=None, chunk: int = 1 << 26):
+    """Same values as ``chain_ics``, generated with torch on ``device``, in
+    chunks of ``chunk`` sites (so very long chains need no large temporaries).
 
     The 64-bit arithmetic runs in int64 (wrapping multiply; logical shifts by
     masking the sign-extended arithmetic shift).
@@ -96,7 +97,6 @@ def chain_ics_torch(n: int, seed: int, device, dtype=None):
     import torch
 
     dtype = dtype or torch.float64
-    i = torch.arange(n, device=device, dtype=torch.int64)
 
     def lsr(z, k):
         return (z >> k) & ((1 << (64 - k)) - 1)
@@ -108,9 +108,14 @@ def chain_ics_torch(n: int, seed: int, device, dtype=None):
         z = z ^ lsr(z, 31)
         return lsr(z, 11).to(torch.float64) * _TWO_M53
 
-    q = 2.0 * draw(2 * i) - 1.0
-    p = 2.0 * draw(2 * i + 1) - 1.0
-    return q.to(dtype), p.to(dtype)
+    q = torch.empty(n, device=device, dtype=dtype)
+    p = torch.empty(n, device=device, dtype=dtype)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        i = torch.arange(a, b, device=device, dtype=torch.int64)
+        q[a:b] = (2.0 * draw(2 * i) - 1.0).to(dtype)
+        p[a:b] = (2.0 * draw(2 * i + 1) - 1.0).to(dtype)
+    return q, p
 
 
 def mode_ics(n: int, kind: str, amp: float = 0.5, mode: int = 1):
