@@ -391,6 +391,7 @@ def variant_batch(dt, dev, steps=2000, count=4096):
     import torch
     import workloads
     from paper_1412_0544_amd import Batch, Chain, autotune
+    from paper_1412_0544_amd import _lib as L
     lengths = workloads.batch_lengths(count)
     tot = int(lengths.sum())
     out = {"chains": count, "sites": tot, "steps": steps}
@@ -411,6 +412,15 @@ def variant_batch(dt, dev, steps=2000, count=4096):
                      "kdepth": K, "grid_blocks": plan["grid_blocks"],
                      "resident_chains": plan["resident_chains"],
                      "clusters": plan["total_clusters"]}
+        b.close()
+        # the same with the rings of <= 1024 sites kept on chip for all steps
+        b = Batch(chains, max_steps=steps, sites_per_lane=S, kdepth=K,
+                  flags=L.CHAIN_BATCH_RESIDENT_RINGS)
+        b.step(24)
+        b.check()
+        t = ev_seconds(lambda: b.step(steps), chains[0].stream)
+        b.check()
+        out[f"{prec}_resident_rings_su_per_s"] = tot * steps / t
         b.close()
         if prec == "fp64":
             # the same chains, one step call per chain (100 steps each)

@@ -263,9 +263,10 @@ const char *chain_rk4_last_error(void);
  * Batches: many independent chains advanced by ONE persistent launch.
  *
  * The launch holds as many workgroups as the device keeps resident. They
- * claim work items in a fixed order from a device counter: first one item
- * per short ring (n <= 1024), which stays on chip for all of its steps, then,
- * pass by pass, one item per (chain, cluster), each the same cluster pass as
+ * claim work items in a fixed order from a device counter: with
+ * CHAIN_BATCH_RESIDENT_RINGS, first one item per short ring (n <= 1024), which
+ * stays on chip for all of its steps; then, pass by pass, one item per
+ * (chain, cluster), each the same cluster pass as
  * the fused method (a cluster of 64*sites_per_lane*4 sites, 2*kdepth of them
  * recomputed per side, Sec. 2.3). A cluster's pass e starts once its own
  * cluster and its two neighbours have finished pass e-1 (per-cluster progress
@@ -277,10 +278,15 @@ const char *chain_rk4_last_error(void);
  * chain keeps its own dt. Calls that overlap on one batch's workspace race.
  */
 enum chain_batch_flags {
-    CHAIN_BATCH_FENCES = 1  /* hand cluster data between workgroups with
-                               ordinary loads and stores plus agent-scope
-                               cache write-back and invalidation, instead of
-                               device-coherent loads and stores */
+    CHAIN_BATCH_FENCES = 1,         /* hand cluster data between workgroups with
+                                       ordinary loads and stores plus agent-scope
+                                       cache write-back and invalidation, instead
+                                       of device-coherent loads and stores */
+    CHAIN_BATCH_RESIDENT_RINGS = 2  /* keep rings of at most 1024 sites on chip
+                                       for all their steps (one item each, first);
+                                       without it every chain is tiled, and the
+                                       launch uses a kernel without the resident
+                                       path (fewer registers, more wavefronts) */
 };
 
 typedef struct chain_rk4_batch_desc {
@@ -328,8 +334,9 @@ int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batc
 int chain_rk4_batch_rebind(chain_rk4_batch *b, chain_rk4 *const *hs, int count);
 
 /* Clusters a chain of n sites occupies in a batch of the given shape
- * (sites_per_lane and kdepth as in the descriptor, 0 = default); 0 for a ring
- * kept on chip. Used to size max_clusters. */
+ * (sites_per_lane and kdepth as in the descriptor, 0 = default) when it is
+ * tiled; a ring kept on chip (CHAIN_BATCH_RESIDENT_RINGS) takes none. 0 for
+ * invalid arguments. Used to size max_clusters. */
 int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdepth);
 
 /* Advance chain j by nsteps[j] (0..max_steps) steps in one persistent launch

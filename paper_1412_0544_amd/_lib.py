@@ -16,7 +16,7 @@ CHAIN_QUARTIC_NNN, CHAIN_HARMONIC_NNN = 3, 4
 CHAIN_FP64, CHAIN_FP32_KAHAN = 0, 1
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT, CHAIN_FLAG_RESIDENT = 1, 2, 4
-CHAIN_BATCH_FENCES = 1
+CHAIN_BATCH_FENCES, CHAIN_BATCH_RESIDENT_RINGS = 1, 2
 CHAIN_SCHEME_RK4, CHAIN_SCHEME_TABLEAU = 0, 1
 CHAIN_MAX_STAGES = 8
 

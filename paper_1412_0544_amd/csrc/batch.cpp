@@ -76,6 +76,7 @@ struct Layout {
 struct Shape {
     int sites = 0, depth = 0;
     int64_t halo = 0, tile_max = 0;
+    bool resident_rings = false;   // CHAIN_BATCH_RESIDENT_RINGS
 };
 
 int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
@@ -99,7 +100,7 @@ int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
 }
 
 int64_t clusters_of(int64_t n, const Shape &sh) {
-    if (n <= kBatchResidentSites) return 0;
+    if (sh.resident_rings && n <= kBatchResidentSites) return 0;
     int64_t G, uq, ur;
     split_clusters(n, sh.tile_max, &G, &uq, &ur);
     return G;
@@ -128,11 +129,14 @@ int check_desc(const chain_rk4_batch_desc *d, Shape *sh) {
     if (!d) return fail(CHAIN_EINVAL, "batch descriptor is NULL");
     if (d->max_steps < 0) return fail(CHAIN_EINVAL, "max_steps must be >= 0");
     if (d->grid_blocks < 0) return fail(CHAIN_EINVAL, "grid_blocks must be >= 0");
-    if ((d->flags & ~CHAIN_BATCH_FENCES) != 0) return fail(CHAIN_EINVAL, "unknown batch flags");
+    if ((d->flags & ~(CHAIN_BATCH_FENCES | CHAIN_BATCH_RESIDENT_RINGS)) != 0)
+        return fail(CHAIN_EINVAL, "unknown batch flags");
     if (d->spin_limit < 0) return fail(CHAIN_EINVAL, "spin_limit must be >= 0");
     if (d->max_chains < 0 || d->max_clusters < 0)
         return fail(CHAIN_EINVAL, "max_chains and max_clusters must be >= 0");
-    return make_shape(d->sites_per_lane, d->kdepth, sh);
+    int rc = make_shape(d->sites_per_lane, d->kdepth, sh);
+    sh->resident_rings = (d->flags & CHAIN_BATCH_RESIDENT_RINGS) != 0;
+    return rc;
 }
 
 Layout batch_layout(int64_t chains, int64_t clusters, int64_t max_passes) {
@@ -199,13 +203,19 @@ void bind(chain_rk4_batch *b, chain_rk4 *const *hs, int count) {
     b->total_clusters = 0;
     for (int i = 0; i < count; ++i) {
         const int64_t n = hs[i]->d.n;
-        if (n <= kBatchResidentSites) {
+        if (b->sh.resident_rings && n <= kBatchResidentSites) {
             b->resident[i] = 1;
             continue;
         }
         split_clusters(n, b->sh.tile_max, &b->clusters[i], &b->uq[i], &b->ur[i]);
         b->total_clusters += b->clusters[i];
     }
+}
+
+bool has_resident_items(const chain_rk4_batch *b) {
+    for (char r : b->resident)
+        if (r) return true;
+    return false;
 }
 
 }  // namespace
@@ -395,7 +405,7 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
 
     int blocks = b->d.grid_blocks;
     if (blocks == 0) {
-        blocks = persistent_capacity(b->model, b->prec, b->sh.sites);
+        blocks = persistent_capacity(b->model, b->prec, b->sh.sites, has_resident_items(b));
         if (blocks <= 0) return fail(CHAIN_EHIP, "occupancy query failed");
     }
     if (blocks > total_items) blocks = static_cast<int>(total_items);
@@ -455,7 +465,9 @@ int chain_rk4_batch_get_plan(const chain_rk4_batch *b, chain_rk4_batch_plan *out
     P.sites_per_lane = b->sh.sites;
     P.kdepth = b->sh.depth;
     P.waves_per_cluster = kBatchWaves;
-    P.grid_blocks = b->d.grid_blocks ? b->d.grid_blocks : persistent_capacity(b->model, b->prec, b->sh.sites);
+    P.grid_blocks = b->d.grid_blocks ? b->d.grid_blocks
+                                     : persistent_capacity(b->model, b->prec, b->sh.sites,
+                                                           has_resident_items(b));
     P.halo = b->sh.halo;
     P.tile_max = b->sh.tile_max;
     P.total_clusters = b->total_clusters;

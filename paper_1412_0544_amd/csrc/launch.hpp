@@ -150,7 +150,7 @@ struct BatchArgs {
 };
 
 // Blocks of the persistent kernel the device holds at once (0 on error).
-int persistent_capacity(int model, int prec, int sites_per_lane);
+int persistent_capacity(int model, int prec, int sites_per_lane, bool resident_items);
 hipError_t launch_persistent(int model, int prec, int sites_per_lane, int blocks,
                              const BatchArgs &a, hipStream_t s);
 

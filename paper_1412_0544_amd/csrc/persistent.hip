@@ -58,14 +58,16 @@ __device__ __forceinline__ void drain_memory() {
 // COH: cluster data moves through device-coherent loads and stores, and the
 // hand-off only waits for them to complete. Otherwise: ordinary accesses with
 // an agent-scope release (cache write-back) and acquire (invalidate).
-template <int M, class R, bool KAHAN, int S, bool COH>
+// RES: the launch has resident-ring items. Without them the kernel carries no
+// resident path, which leaves the cluster pass more registers per wavefront.
+template <int M, class R, bool KAHAN, int S, bool COH, bool RES>
 __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) {
     constexpr int W = kBatchWaves, WPB = kBatchWaves;
     constexpr int RMAX = kBatchResidentSites;
     constexpr int SPT = RMAX / kBatchThreads;
     constexpr int E = 64 * S * W;
     __shared__ SlotsOf<M, R, WPB> slots;
-    __shared__ __align__(16) R ring[2 * RMAX];
+    __shared__ __align__(16) R ring[RES ? 2 * RMAX : 1];
     __shared__ long long claimed;
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -79,11 +81,14 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
         __syncthreads();
         if (item >= a.total_items) break;
 
-        if (item < a.n_resident) {
-            const BatchChain &ch = a.chains[a.n_tiled + item];
-            run_resident<M, R, KAHAN, kBatchThreads, SPT>(ch.front, ch.front, static_cast<int>(ch.n),
-                                                          ch.nsteps, ch.dt, ring);
-            continue;
+        if constexpr (RES) {
+            if (item < a.n_resident) {
+                const BatchChain &ch = a.chains[a.n_tiled + item];
+                run_resident<M, R, KAHAN, kBatchThreads, SPT>(ch.front, ch.front,
+                                                              static_cast<int>(ch.n), ch.nsteps,
+                                                              ch.dt, ring);
+                continue;
+            }
         }
 
         const int64_t j = item - a.n_resident;
@@ -118,14 +123,15 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
     }
 }
 
-template <int M, class R, bool KAHAN, int S, bool COH>
+template <int M, class R, bool KAHAN, int S, bool COH, bool RES>
 int capacity_one() {
     static int cached[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<M, R, KAHAN, S, COH>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                         persistent_kernel<M, R, KAHAN, S, COH, RES>,
                                                          kBatchThreads, 0) != hipSuccess)
             return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -136,22 +142,25 @@ int capacity_one() {
 }
 
 template <int M, class R, bool KAHAN>
-int capacity_s(int s) {
+int capacity_s(int s, bool res) {
     switch (s) {
-    case 4: return capacity_one<M, R, KAHAN, 4, true>();
-    case 8: return capacity_one<M, R, KAHAN, 8, true>();
-    case 16: return capacity_one<M, R, KAHAN, 16, true>();
+    case 4: return res ? capacity_one<M, R, KAHAN, 4, true, true>()
+                       : capacity_one<M, R, KAHAN, 4, true, false>();
+    case 8: return res ? capacity_one<M, R, KAHAN, 8, true, true>()
+                       : capacity_one<M, R, KAHAN, 8, true, false>();
+    case 16: return res ? capacity_one<M, R, KAHAN, 16, true, true>()
+                        : capacity_one<M, R, KAHAN, 16, true, false>();
     default: return 0;
     }
 }
 
-template <int M, class R, bool KAHAN, bool COH>
+template <int M, class R, bool KAHAN, bool COH, bool RES>
 hipError_t launch_c(int s, int blocks, const BatchArgs &a, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>(blocks)), block(kBatchThreads);
     switch (s) {
-    case 4: persistent_kernel<M, R, KAHAN, 4, COH><<<grid, block, 0, st>>>(a); break;
-    case 8: persistent_kernel<M, R, KAHAN, 8, COH><<<grid, block, 0, st>>>(a); break;
-    case 16: persistent_kernel<M, R, KAHAN, 16, COH><<<grid, block, 0, st>>>(a); break;
+    case 4: persistent_kernel<M, R, KAHAN, 4, COH, RES><<<grid, block, 0, st>>>(a); break;
+    case 8: persistent_kernel<M, R, KAHAN, 8, COH, RES><<<grid, block, 0, st>>>(a); break;
+    case 16: persistent_kernel<M, R, KAHAN, 16, COH, RES><<<grid, block, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -159,16 +168,22 @@ hipError_t launch_c(int s, int blocks, const BatchArgs &a, hipStream_t st) {
 
 template <int M, class R, bool KAHAN>
 hipError_t launch_s(int s, int blocks, const BatchArgs &a, hipStream_t st) {
-    return a.fences ? launch_c<M, R, KAHAN, false>(s, blocks, a, st)
-                    : launch_c<M, R, KAHAN, true>(s, blocks, a, st);
+    const bool res = a.n_resident > 0;
+    if (a.fences)
+        return res ? launch_c<M, R, KAHAN, false, true>(s, blocks, a, st)
+                   : launch_c<M, R, KAHAN, false, false>(s, blocks, a, st);
+    return res ? launch_c<M, R, KAHAN, true, true>(s, blocks, a, st)
+               : launch_c<M, R, KAHAN, true, false>(s, blocks, a, st);
 }
 
 }  // namespace
 
-int persistent_capacity(int model, int prec, int s) {
+int persistent_capacity(int model, int prec, int s, bool res) {
     if (model == kQuartic)
-        return prec == 0 ? capacity_s<kQuartic, double, false>(s) : capacity_s<kQuartic, float, true>(s);
-    return prec == 0 ? capacity_s<kHarmonic, double, false>(s) : capacity_s<kHarmonic, float, true>(s);
+        return prec == 0 ? capacity_s<kQuartic, double, false>(s, res)
+                         : capacity_s<kQuartic, float, true>(s, res);
+    return prec == 0 ? capacity_s<kHarmonic, double, false>(s, res)
+                     : capacity_s<kHarmonic, float, true>(s, res);
 }
 
 hipError_t launch_persistent(int model, int prec, int s, int blocks, const BatchArgs &a,

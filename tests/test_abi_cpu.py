@@ -126,14 +126,14 @@ def test_batch_calls_reject_bad_arguments_without_a_gpu():
 
 def test_batch_cluster_count_helper():
     lib = L.lib()
-    assert lib.chain_rk4_batch_clusters(1000, 0, 0) == 0        # kept on chip
+    assert lib.chain_rk4_batch_clusters(300, 0, 0) == 1         # a short ring: one cluster
 
     def expect(n, sites, depth):
         keep = 64 * sites * 4 - 4 * depth                          # cluster minus both halos
         return -(-n // (keep - 4))
 
     # default shape: 4 sites per lane, depth 32
-    for n in (1025, 5000, 65536, 1 << 24):
+    for n in (1000, 1025, 5000, 65536, 1 << 24):
         assert lib.chain_rk4_batch_clusters(n, 0, 0) == expect(n, 4, 32)
         assert lib.chain_rk4_batch_clusters(n, 8, 12) == expect(n, 8, 12)
     assert lib.chain_rk4_batch_clusters(100, 5, 0) == 0          # invalid shape

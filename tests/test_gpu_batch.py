@@ -48,7 +48,7 @@ def solo(n, seed, steps, prec="fp64", model="quartic", dt=0.01):
 
 
 @pytest.mark.parametrize("shape", [(0, 0, 0), (8, 12, 0), (4, 16, 0), (16, 8, 0), (4, 2, 0),
-                                   (8, 12, 1), (4, 16, 1)])
+                                   (8, 12, 1), (4, 16, 1), (0, 0, 2), (8, 32, 2), (4, 16, 3)])
 def test_batch_matches_solo_bitwise(shape):
     sites, depth, flags = shape
     steps = [37, 0, 1, 100, 5, 2, 64, 13, 3, 24]
@@ -84,7 +84,8 @@ def test_grid_size_and_repeats_do_not_change_bits():
     """Race check: one workgroup, a few, and the full device, repeated."""
     lengths = [300, 5003, 20011, 65536, 100000]
     ref = None
-    for grid, flags in ((1, 0), (3, 0), (0, 0), (0, 0), (0, 1), (17, 0), (0, 0), (5, 1)):
+    for grid, flags in ((1, 0), (3, 0), (0, 0), (0, 0), (0, 1), (17, 0), (0, 0), (5, 1), (0, 2),
+                        (2, 2)):
         chains = make_chains(lengths, range(50, 55))
         b = Batch(chains, max_steps=60, grid_blocks=grid, flags=flags)
         b.step([60, 41, 60, 33, 60])
