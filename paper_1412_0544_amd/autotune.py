@@ -22,18 +22,20 @@ from .chain import Chain, state_dtype
 CACHE_ENV = "CHAIN_RK4_TUNE_CACHE"
 _lock = threading.Lock()
 
-SITES = (4, 8, 16)
+SITES = (2, 4, 8, 16)
 WAVES = (1, 2, 4, 8)
 DEPTHS = (1, 2, 4, 6, 8, 12, 16, 24, 32)
 
 
 def default_candidates(prec: str = "fp64"):
-    """Shapes worth timing: cluster sizes that keep the halo small."""
+    """Shapes worth timing: every cluster size at the deeper depths that keep
+    at least half of the cluster (the halo of the quartic and harmonic chains
+    is 2 sites per step and side)."""
     out = []
-    for s in (8, 16):
+    for s in SITES:
         for w in WAVES:
-            for k in (8, 12, 16, 24, 32):
-                if 64 * s * w > 16 * k:
+            for k in (16, 24, 32):
+                if 64 * s * w >= 8 * k:
                     out.append((s, w, k))
     return out
 
