@@ -61,6 +61,15 @@ class Chain:
 
     ``q0`` and ``p0`` (numpy arrays or tensors) are copied into device tensors
     of the precision's dtype; ``state()`` returns those tensors.
+
+    model: "quartic", "harmonic", "quartic_nnn" or "harmonic_nnn";
+    prec: "fp64" or "fp32_kahan"; method: "fused" or "naive" (one kernel per
+    stage). sites_per_lane, waves_per_cluster and kdepth fix the cluster
+    shape (0 = the library's plan for this length). graph: replay each
+    distinct step count from a captured graph (saves launch time on short
+    chains). resident: True keeps a ring of at most 4096 sites in one
+    workgroup for all steps of a call. tableau: (a, b) of any explicit
+    Runge-Kutta method instead of classical RK4 (see ``tableaus``).
     """
 
     def __init__(self, q0, p0, dt: float, model="quartic", prec="fp64", method="fused",
