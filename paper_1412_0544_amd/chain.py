@@ -13,7 +13,8 @@ from . import _lib as L
 
 MODELS = {"quartic": L.CHAIN_QUARTIC, "harmonic": L.CHAIN_HARMONIC,
           "quartic_nnn": L.CHAIN_QUARTIC_NNN, "harmonic_nnn": L.CHAIN_HARMONIC_NNN}
-PRECS = {"fp64": L.CHAIN_FP64, "fp32_kahan": L.CHAIN_FP32_KAHAN}
+PRECS = {"fp64": L.CHAIN_FP64, "fp32_kahan": L.CHAIN_FP32_KAHAN,
+         "fp32_kahan64": L.CHAIN_FP32_KAHAN64}
 METHODS = {"fused": L.CHAIN_FUSED, "naive": L.CHAIN_NAIVE}
 
 
@@ -63,7 +64,8 @@ class Chain:
     of the precision's dtype; ``state()`` returns those tensors.
 
     model: "quartic", "harmonic", "quartic_nnn" or "harmonic_nnn";
-    prec: "fp64" or "fp32_kahan"; method: "fused" or "naive" (one kernel per
+    prec: "fp64", "fp32_kahan" or "fp32_kahan64" (FP32 state, FP64 carries:
+    classical RK4 on a single tiled chain only); method: "fused" or "naive" (one kernel per
     stage). sites_per_lane, waves_per_cluster and kdepth fix the cluster
     shape (0 = the library's plan for this length). graph: replay each
     distinct step count from a captured graph (saves launch time on short
@@ -89,7 +91,8 @@ class Chain:
         flags = ((L.CHAIN_FLAG_GRAPH if graph else 0) |
                  {None: 0, True: L.CHAIN_FLAG_RESIDENT, False: L.CHAIN_FLAG_NO_RESIDENT}[resident])
         scheme = L.CHAIN_SCHEME_RK4 if tableau is None else L.CHAIN_SCHEME_TABLEAU
-        self.desc = L.Desc(self.q.numel(), _code(MODELS, model), _code(PRECS, prec), float(dt),
+        self.prec = _code(PRECS, prec)
+        self.desc = L.Desc(self.q.numel(), _code(MODELS, model), self.prec, float(dt),
                            _code(METHODS, method), int(sites_per_lane), int(kdepth),
                            int(waves_per_cluster), flags, scheme)
         lib = L.lib()
@@ -135,22 +138,25 @@ class Chain:
         return {k: getattr(P, k) for k, _ in L.Plan._fields_}
 
     def carries(self):
-        """Device pointers (ints) of the FP32 carries, or (None, None) for FP64."""
+        """Device pointers (ints) of the carries, or (None, None) for FP64."""
         cq, cp = L.VP(), L.VP()
         L.check(L.lib().chain_rk4_get_carries(self._h, ctypes.byref(cq), ctypes.byref(cp)),
                 "chain_rk4_get_carries")
         return cq.value, cp.value
 
     def carry_tensors(self):
-        """Views of the FP32 carries as tensors (FP32 precision only)."""
+        """Views of the carries as tensors (float32, or float64 for
+        "fp32_kahan64"); (None, None) for FP64."""
         cq, cp = self.carries()
         if cq is None:
             return None, None
         base = self._ws.data_ptr()
         n = self.q.numel()
+        dt = torch.float64 if self.prec == L.CHAIN_FP32_KAHAN64 else torch.float32
+        w = 8 if dt == torch.float64 else 4
         flat = self._ws.view(torch.uint8)
-        tq = flat[cq - base: cq - base + 4 * n].view(torch.float32)
-        tp = flat[cp - base: cp - base + 4 * n].view(torch.float32)
+        tq = flat[cq - base: cq - base + w * n].view(dt)
+        tp = flat[cp - base: cp - base + w * n].view(dt)
         return tq, tp
 
     def state(self):

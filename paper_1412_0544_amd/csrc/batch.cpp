@@ -117,6 +117,8 @@ int check_handles(chain_rk4 *const *hs, int count, int model, int prec) {
             return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
         if (hs[i]->d.model != CHAIN_QUARTIC && hs[i]->d.model != CHAIN_HARMONIC)
             return fail(CHAIN_EINVAL, "handle %d: batches take the quartic and harmonic models only", i);
+        if (hs[i]->d.prec == CHAIN_FP32_KAHAN64)
+            return fail(CHAIN_EINVAL, "handle %d: batches take CHAIN_FP64 or CHAIN_FP32_KAHAN", i);
     }
     std::vector<chain_rk4 *> sorted(hs, hs + count);
     std::sort(sorted.begin(), sorted.end());
@@ -425,8 +427,8 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
             const size_t bytes = static_cast<size_t>(h->d.n) * elem_bytes(h->d.prec);
             HIP_TRY(hipMemcpyAsync(h->front.q, h->back.q, bytes, hipMemcpyDeviceToDevice, b->stream));
             HIP_TRY(hipMemcpyAsync(h->front.p, h->back.p, bytes, hipMemcpyDeviceToDevice, b->stream));
-            if (h->d.prec == CHAIN_FP32_KAHAN) {
-                const size_t cb = static_cast<size_t>(h->d.n) * sizeof(float);
+            if (has_carries(h->d.prec)) {
+                const size_t cb = static_cast<size_t>(h->d.n) * carry_bytes(h->d.prec);
                 HIP_TRY(hipMemcpyAsync(h->front.cq, h->back.cq, cb, hipMemcpyDeviceToDevice, b->stream));
                 HIP_TRY(hipMemcpyAsync(h->front.cp, h->back.cp, cb, hipMemcpyDeviceToDevice, b->stream));
             }

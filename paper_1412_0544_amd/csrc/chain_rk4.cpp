@@ -41,6 +41,8 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 size_t elem_bytes(int prec) { return prec == CHAIN_FP64 ? sizeof(double) : sizeof(float); }
+bool has_carries(int prec) { return prec == CHAIN_FP32_KAHAN || prec == CHAIN_FP32_KAHAN64; }
+size_t carry_bytes(int prec) { return prec == CHAIN_FP32_KAHAN64 ? sizeof(double) : sizeof(float); }
 
 bool is_gfx950(int dev) {
     static int cached[64];  // 0 unknown, 1 yes, 2 no
@@ -113,7 +115,7 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC && d->model != CHAIN_ROESSLER &&
         d->model != CHAIN_QUARTIC_NNN && d->model != CHAIN_HARMONIC_NNN)
         return fail(CHAIN_EINVAL, "unknown model %d", d->model);
-    if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN)
+    if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN && d->prec != CHAIN_FP32_KAHAN64)
         return fail(CHAIN_EINVAL, "unknown precision %d", d->prec);
     if (d->model == CHAIN_ROESSLER && d->prec != CHAIN_FP64)
         return fail(CHAIN_EINVAL, "the Roessler chain runs in FP64 only");
@@ -134,6 +136,8 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->scheme == CHAIN_SCHEME_TABLEAU) {
         if (d->model == CHAIN_ROESSLER)
             return fail(CHAIN_EINVAL, "a tableau method is not available for the Roessler chain");
+        if (d->prec == CHAIN_FP32_KAHAN64)
+            return fail(CHAIN_EINVAL, "tableau methods take CHAIN_FP64 or CHAIN_FP32_KAHAN");
     }
     if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT | CHAIN_FLAG_RESIDENT))
         return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
@@ -146,6 +150,8 @@ int check_desc(const chain_rk4_desc *d) {
             d->scheme != CHAIN_SCHEME_RK4 || d->method != CHAIN_FUSED)
             return fail(CHAIN_EINVAL, "resident rings run the classical RK4 of the quartic and "
                                       "harmonic chains on the fused path only");
+        if (d->prec == CHAIN_FP32_KAHAN64)
+            return fail(CHAIN_EINVAL, "resident rings take CHAIN_FP64 or CHAIN_FP32_KAHAN");
     }
     return CHAIN_OK;
 }
@@ -153,7 +159,7 @@ int check_desc(const chain_rk4_desc *d) {
 // Workspace regions, in order. Unused regions have size 0.
 struct Layout {
     size_t back_q, back_p, back_z;    // fused: back buffer of the ping-pong
-    size_t cq, cp, back_cq, back_cp;  // FP32: carries (front and back)
+    size_t cq, cp, back_cq, back_cp;  // FP32 state: carries (front and back)
     size_t naive[10];                 // naive: k1..k3 and two stage arguments
     size_t naive_z[5];                // naive, Roessler: the same for z
     size_t naive_tab[2 * (kMaxStages - 1) + 4];  // naive tableau: slopes, two arguments
@@ -165,14 +171,14 @@ Layout layout(const chain_rk4_desc *d) {
     Layout L{};
     const size_t n = static_cast<size_t>(d->n);
     const size_t arr = round_up(n * elem_bytes(d->prec));
-    const size_t carr = round_up(n * sizeof(float));
+    const size_t carr = round_up(n * carry_bytes(d->prec));
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += bytes;
         return o;
     };
-    const bool kahan = d->prec == CHAIN_FP32_KAHAN;
+    const bool kahan = has_carries(d->prec);
     const bool three = d->model == CHAIN_ROESSLER;
     if (d->method == CHAIN_FUSED) {
         L.back_q = take(arr);
@@ -351,8 +357,8 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
         HIP_TRY(hipMemcpyAsync(h->front.p, cur.p, b, hipMemcpyDeviceToDevice, s));
         if (d.model == CHAIN_ROESSLER)
             HIP_TRY(hipMemcpyAsync(h->front.z, cur.z, b, hipMemcpyDeviceToDevice, s));
-        if (d.prec == CHAIN_FP32_KAHAN) {
-            const size_t cb = static_cast<size_t>(d.n) * sizeof(float);
+        if (has_carries(d.prec)) {
+            const size_t cb = static_cast<size_t>(d.n) * carry_bytes(d.prec);
             HIP_TRY(hipMemcpyAsync(h->front.cq, cur.cq, cb, hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(h->front.cp, cur.cp, cb, hipMemcpyDeviceToDevice, s));
         }
@@ -433,12 +439,12 @@ int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *
         h->back.p = ws + L.back_p;
         if (three) h->back.z = reinterpret_cast<double *>(ws + L.back_z);
     }
-    if (d->prec == CHAIN_FP32_KAHAN) {
-        h->front.cq = reinterpret_cast<float *>(ws + L.cq);
-        h->front.cp = reinterpret_cast<float *>(ws + L.cp);
+    if (has_carries(d->prec)) {
+        h->front.cq = ws + L.cq;
+        h->front.cp = ws + L.cp;
         if (d->method == CHAIN_FUSED) {
-            h->back.cq = reinterpret_cast<float *>(ws + L.back_cq);
-            h->back.cp = reinterpret_cast<float *>(ws + L.back_cp);
+            h->back.cq = ws + L.back_cq;
+            h->back.cp = ws + L.back_cp;
         }
     }
     if (d->method == CHAIN_NAIVE && d->scheme == CHAIN_SCHEME_TABLEAU) {
@@ -463,8 +469,8 @@ int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *
     }
     h->partials = reinterpret_cast<double *>(ws + L.partials);
     h->result = reinterpret_cast<double *>(ws + L.result);
-    if (d->prec == CHAIN_FP32_KAHAN) {
-        const size_t cb = round_up(static_cast<size_t>(d->n) * sizeof(float));
+    if (has_carries(d->prec)) {
+        const size_t cb = round_up(static_cast<size_t>(d->n) * carry_bytes(d->prec));
         hipError_t e = launch_fill_zero(h->front.cq, cb, h->stream);
         if (e == hipSuccess) e = launch_fill_zero(h->front.cp, cb, h->stream);
         if (e != hipSuccess) {

@@ -193,20 +193,22 @@ __device__ __forceinline__ void store_coherent(R *p, R v) {
 }
 
 // Registers of one lane's S sites.
-template <class R, bool KAHAN, int S>
+template <class R, bool KAHAN, int S, class C = float>
 struct LaneState {
     R q[S], p[S];
-    float cq[KAHAN ? S : 1], cp[KAHAN ? S : 1];
+    C cq[KAHAN ? S : 1], cp[KAHAN ? S : 1];   // carries of the compensated update
 };
 
 // Load this lane's S sites, starting at unwrapped site s0 of a ring of n
 // sites. `contiguous` (uniform over the cluster) says the cluster's sites
 // need no wrap, so vector loads apply.
-template <class R, bool KAHAN, int S, bool COH = false>
-__device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const StateRef &in, int64_t n,
-                                          int64_t s0, bool contiguous) {
+template <class R, bool KAHAN, int S, bool COH = false, class C = float>
+__device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S, C> &st, const StateRef &in,
+                                          int64_t n, int64_t s0, bool contiguous) {
     const R *qin = static_cast<const R *>(in.q);
     const R *pin = static_cast<const R *>(in.p);
+    const C *cqin = static_cast<const C *>(in.cq);
+    const C *cpin = static_cast<const C *>(in.cp);
     if constexpr (COH) {
         if (contiguous) {
             const R *qb = qin + s0, *pb = pin + s0;
@@ -215,8 +217,8 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
                 st.q[j] = load_coherent(qb + j);
                 st.p[j] = load_coherent(pb + j);
                 if constexpr (KAHAN) {
-                    st.cq[j] = load_coherent(in.cq + s0 + j);
-                    st.cp[j] = load_coherent(in.cp + s0 + j);
+                    st.cq[j] = load_coherent(cqin + s0 + j);
+                    st.cp[j] = load_coherent(cpin + s0 + j);
                 }
             }
         } else {
@@ -226,8 +228,8 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
                 st.q[j] = load_coherent(qin + i);
                 st.p[j] = load_coherent(pin + i);
                 if constexpr (KAHAN) {
-                    st.cq[j] = load_coherent(in.cq + i);
-                    st.cp[j] = load_coherent(in.cp + i);
+                    st.cq[j] = load_coherent(cqin + i);
+                    st.cp[j] = load_coherent(cpin + i);
                 }
             }
         }
@@ -235,8 +237,8 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
         load_contig<R, S>(st.q, qin + s0);
         load_contig<R, S>(st.p, pin + s0);
         if constexpr (KAHAN) {
-            load_contig<float, S>(st.cq, in.cq + s0);
-            load_contig<float, S>(st.cp, in.cp + s0);
+            load_contig<C, S>(st.cq, cqin + s0);
+            load_contig<C, S>(st.cp, cpin + s0);
         }
     } else {
 #pragma unroll
@@ -245,8 +247,8 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
             st.q[j] = qin[i];
             st.p[j] = pin[i];
             if constexpr (KAHAN) {
-                st.cq[j] = in.cq[i];
-                st.cp[j] = in.cp[i];
+                st.cq[j] = cqin[i];
+                st.cp[j] = cpin[i];
             }
         }
     }
@@ -255,12 +257,14 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S> &st, const Stat
 // Store the kept sites of this lane: cluster-local positions
 // [keep_lo, keep_hi) that are also below n (lo is the lane's first local
 // position, s0 its unwrapped site; kept sites never wrap).
-template <class R, bool KAHAN, int S, bool COH = false>
-__device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, const StateRef &out,
+template <class R, bool KAHAN, int S, bool COH = false, class C = float>
+__device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, const StateRef &out,
                                            int64_t n, int64_t s0, int lo, int64_t keep_lo,
                                            int64_t keep_hi) {
     R *qout = static_cast<R *>(out.q);
     R *pout = static_cast<R *>(out.p);
+    C *cqout = static_cast<C *>(out.cq);
+    C *cpout = static_cast<C *>(out.cp);
     if constexpr (COH) {
         R *qb = qout + s0, *pb = pout + s0;
         const bool all = lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n;
@@ -270,8 +274,8 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
                 store_coherent(qb + j, st.q[j]);
                 store_coherent(pb + j, st.p[j]);
                 if constexpr (KAHAN) {
-                    store_coherent(out.cq + s0 + j, st.cq[j]);
-                    store_coherent(out.cp + s0 + j, st.cp[j]);
+                    store_coherent(cqout + s0 + j, st.cq[j]);
+                    store_coherent(cpout + s0 + j, st.cp[j]);
                 }
             }
         }
@@ -279,8 +283,8 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
         store_contig<R, S>(qout + s0, st.q);
         store_contig<R, S>(pout + s0, st.p);
         if constexpr (KAHAN) {
-            store_contig<float, S>(out.cq + s0, st.cq);
-            store_contig<float, S>(out.cp + s0, st.cp);
+            store_contig<C, S>(cqout + s0, st.cq);
+            store_contig<C, S>(cpout + s0, st.cp);
         }
     } else {
 #pragma unroll
@@ -291,8 +295,8 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
                 qout[g] = st.q[j];
                 pout[g] = st.p[j];
                 if constexpr (KAHAN) {
-                    out.cq[g] = st.cq[j];
-                    out.cp[g] = st.cp[j];
+                    cqout[g] = st.cq[j];
+                    cpout[g] = st.cp[j];
                 }
             }
         }
@@ -307,7 +311,7 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S> &st, con
 // every second stage. The caller guarantees halo >= 2*range*ksteps and
 // halo + keep <= 64*S*W, so the stored sites are exact. All wavefronts of
 // the cluster must call this together.
-template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false>
+template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false, class C = float>
 __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
                                             int64_t e0, int64_t halo, int64_t keep, int ksteps,
                                             double dt, SlotsOf<M, R, WPB> *slots, int lane,
@@ -315,8 +319,8 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     constexpr int E = 64 * S * W;
     const int lo = (wic * 64 + lane) * S;
     const int64_t s0 = e0 + lo;
-    LaneState<R, KAHAN, S> st;
-    load_lane<R, KAHAN, S, COH>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
+    LaneState<R, KAHAN, S, C> st;
+    load_lane<R, KAHAN, S, COH, C>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
     const StepConsts<R> c(dt);
     R Q[S], P[S], aq[S], ap[S];
     for (int k = 0; k < ksteps; ++k) {
@@ -329,7 +333,7 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
         else
             final_update<S>(st.q, st.p, aq, ap, c);
     }
-    store_lane<R, KAHAN, S, COH>(st, out, n, s0, lo, halo, halo + keep);
+    store_lane<R, KAHAN, S, COH, C>(st, out, n, s0, lo, halo, halo + keep);
 }
 
 // Whole-ring resident run by a block of T threads: thread t owns sites
@@ -354,8 +358,8 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
             q[j] = qin[i];
             p[j] = pin[i];
             if constexpr (KAHAN) {
-                cq[j] = in.cq[i];
-                cp[j] = in.cp[i];
+                cq[j] = static_cast<const float *>(in.cq)[i];
+                cp[j] = static_cast<const float *>(in.cp)[i];
             }
             buf0[i] = q[j];
             Q[j] = q[j];
@@ -388,8 +392,8 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
                     } else {
                         stage_one<M, 4, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
                         if constexpr (KAHAN) {
-                            kahan_add(q[j], cq[j], c.h6 * aq[j]);
-                            kahan_add(p[j], cp[j], c.h6 * ap[j]);
+                            kahan_step(q[j], cq[j], aq[j], c.h6, c.h6lo);
+                            kahan_step(p[j], cp[j], ap[j], c.h6, c.h6lo);
                         } else {
                             q[j] = fma_r(c.h6, aq[j], q[j]);
                             p[j] = fma_r(c.h6, ap[j], p[j]);
@@ -414,8 +418,8 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
             qout[i] = q[j];
             pout[i] = p[j];
             if constexpr (KAHAN) {
-                out.cq[i] = cq[j];
-                out.cp[i] = cp[j];
+                static_cast<float *>(out.cq)[i] = cq[j];
+                static_cast<float *>(out.cp)[i] = cp[j];
             }
         }
     }

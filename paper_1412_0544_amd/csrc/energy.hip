@@ -14,13 +14,13 @@
 namespace chainrk4 {
 namespace {
 
-template <class R, bool KAHAN>
+template <class R, bool KAHAN, class C>
 __device__ __forceinline__ void coords(const StateRef &y, int64_t i, double &q, double &p) {
     const R *yq = static_cast<const R *>(y.q);
     const R *yp = static_cast<const R *>(y.p);
     if constexpr (KAHAN) {
-        q = static_cast<double>(yq[i]) - static_cast<double>(y.cq[i]);
-        p = static_cast<double>(yp[i]) - static_cast<double>(y.cp[i]);
+        q = static_cast<double>(yq[i]) - static_cast<double>(static_cast<const C *>(y.cq)[i]);
+        p = static_cast<double>(yp[i]) - static_cast<double>(static_cast<const C *>(y.cp)[i]);
     } else {
         q = static_cast<double>(yq[i]);
         p = static_cast<double>(yp[i]);
@@ -40,7 +40,7 @@ __device__ __forceinline__ double block_sum(double v) {
     return s[0];
 }
 
-template <int M, class R, bool KAHAN>
+template <int M, class R, bool KAHAN, class C>
 __global__ __launch_bounds__(kEnergyThreads) void energy_partial(StateRef y, int64_t n,
                                                                  double *partials) {
     double acc = 0.0;
@@ -49,11 +49,11 @@ __global__ __launch_bounds__(kEnergyThreads) void energy_partial(StateRef y, int
          i += stride) {
         const int64_t ip = (i == n - 1) ? 0 : i + 1;
         double q, p, qn, pn;
-        coords<R, KAHAN>(y, i, q, p);
-        coords<R, KAHAN>(y, ip, qn, pn);
+        coords<R, KAHAN, C>(y, i, q, p);
+        coords<R, KAHAN, C>(y, ip, qn, pn);
         if constexpr (coupling_range<M>() == 2) {
             double qnn, pnn;
-            coords<R, KAHAN>(y, wrap_index(i + 2, n), qnn, pnn);
+            coords<R, KAHAN, C>(y, wrap_index(i + 2, n), qnn, pnn);
             acc += ModelOps<M, double>::energy2(q, p, qn - q, qnn - q);
         } else {
             acc += ModelOps<M, double>::energy(q, p, qn - q);
@@ -77,10 +77,10 @@ __global__ void fill_zero_kernel(uint32_t *p, size_t words) {
         p[i] = 0u;
 }
 
-template <int M, class R, bool KAHAN>
+template <int M, class R, bool KAHAN, class C = float>
 hipError_t energy_dispatch(StateRef y, int64_t n, double *partials, double *result, hipStream_t s) {
     const int nb = energy_blocks(n);
-    energy_partial<M, R, KAHAN><<<nb, kEnergyThreads, 0, s>>>(y, n, partials);
+    energy_partial<M, R, KAHAN, C><<<nb, kEnergyThreads, 0, s>>>(y, n, partials);
     energy_finish<<<1, kEnergyThreads, 0, s>>>(partials, nb, result);
     return hipGetLastError();
 }
@@ -97,8 +97,12 @@ int energy_blocks(int64_t n) {
 template <int M>
 hipError_t energy_dispatch_prec(int prec, StateRef y, int64_t n, double *partials, double *result,
                                 hipStream_t s) {
-    return prec == 0 ? energy_dispatch<M, double, false>(y, n, partials, result, s)
-                     : energy_dispatch<M, float, true>(y, n, partials, result, s);
+    switch (prec) {
+    case 0: return energy_dispatch<M, double, false>(y, n, partials, result, s);
+    case 1: return energy_dispatch<M, float, true>(y, n, partials, result, s);
+    case 2: return energy_dispatch<M, float, true, double>(y, n, partials, result, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_energy(int model, int prec, StateRef y, int64_t n, double *partials,

@@ -28,7 +28,7 @@ constexpr int fused_block_threads(int W) { return W == 1 ? kFusedThreads : 64 * 
 
 // One block per cluster (four one-wavefront clusters when W = 1); the grid
 // covers every cluster of the pass.
-template <int M, class R, bool KAHAN, int S, int W>
+template <int M, class R, bool KAHAN, int S, int W, class C>
 __global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass a) {
     constexpr int WPB = fused_block_threads(W) / 64;  // wavefronts per block
     constexpr int CPB = WPB / W;                       // clusters per block
@@ -40,8 +40,9 @@ __global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass
     // W > 1: a block is exactly one cluster and the grid has no extra blocks,
     // so every wavefront reaches every barrier. W = 1: no barriers.
     if (cluster >= a.waves) return;
-    run_cluster<M, R, KAHAN, S, W, WPB>(a.in, a.out, a.n, cluster * a.tile - a.halo, a.halo, a.tile,
-                                        a.ksteps, a.dt, &slots, lane, wib, wic);
+    run_cluster<M, R, KAHAN, S, W, WPB, false, C>(a.in, a.out, a.n, cluster * a.tile - a.halo,
+                                                  a.halo, a.tile, a.ksteps, a.dt, &slots, lane,
+                                                  wib, wic);
 }
 
 template <int M, class R, bool KAHAN, int T, int SPT>
@@ -51,34 +52,34 @@ __global__ __launch_bounds__(T) void resident_kernel(ResidentRun a) {
                                       reinterpret_cast<R *>(smem));
 }
 
-template <int M, class R, bool KAHAN, int S, int W>
+template <int M, class R, bool KAHAN, int S, int W, class C>
 hipError_t fused_launch_one(const FusedPass &a, hipStream_t st) {
     constexpr int T = fused_block_threads(W);
     constexpr int clusters_per_block = T / 64 / W;
     const int64_t blocks64 = (a.waves + clusters_per_block - 1) / clusters_per_block;
     if (blocks64 <= 0 || blocks64 > 0x7fffffff) return hipErrorInvalidValue;
-    fused_kernel<M, R, KAHAN, S, W><<<dim3(static_cast<unsigned>(blocks64)), dim3(T), 0, st>>>(a);
+    fused_kernel<M, R, KAHAN, S, W, C><<<dim3(static_cast<unsigned>(blocks64)), dim3(T), 0, st>>>(a);
     return hipGetLastError();
 }
 
-template <int M, class R, bool KAHAN, int S>
+template <int M, class R, bool KAHAN, int S, class C>
 hipError_t fused_dispatch_w(int w, const FusedPass &a, hipStream_t st) {
     switch (w) {
-    case 1: return fused_launch_one<M, R, KAHAN, S, 1>(a, st);
-    case 2: return fused_launch_one<M, R, KAHAN, S, 2>(a, st);
-    case 4: return fused_launch_one<M, R, KAHAN, S, 4>(a, st);
-    case 8: return fused_launch_one<M, R, KAHAN, S, 8>(a, st);
+    case 1: return fused_launch_one<M, R, KAHAN, S, 1, C>(a, st);
+    case 2: return fused_launch_one<M, R, KAHAN, S, 2, C>(a, st);
+    case 4: return fused_launch_one<M, R, KAHAN, S, 4, C>(a, st);
+    case 8: return fused_launch_one<M, R, KAHAN, S, 8, C>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int M, class R, bool KAHAN>
+template <int M, class R, bool KAHAN, class C = float>
 hipError_t fused_dispatch_s(int s, int w, const FusedPass &a, hipStream_t st) {
     switch (s) {
-    case 2: return fused_dispatch_w<M, R, KAHAN, 2>(w, a, st);
-    case 4: return fused_dispatch_w<M, R, KAHAN, 4>(w, a, st);
-    case 8: return fused_dispatch_w<M, R, KAHAN, 8>(w, a, st);
-    case 16: return fused_dispatch_w<M, R, KAHAN, 16>(w, a, st);
+    case 2: return fused_dispatch_w<M, R, KAHAN, 2, C>(w, a, st);
+    case 4: return fused_dispatch_w<M, R, KAHAN, 4, C>(w, a, st);
+    case 8: return fused_dispatch_w<M, R, KAHAN, 8, C>(w, a, st);
+    case 16: return fused_dispatch_w<M, R, KAHAN, 16, C>(w, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -105,8 +106,12 @@ hipError_t resident_dispatch(const ResidentRun &a, hipStream_t st) {
 
 template <int M>
 hipError_t fused_dispatch_prec(int prec, int s, int w, const FusedPass &a, hipStream_t st) {
-    return prec == 0 ? fused_dispatch_s<M, double, false>(s, w, a, st)
-                     : fused_dispatch_s<M, float, true>(s, w, a, st);
+    switch (prec) {
+    case 0: return fused_dispatch_s<M, double, false>(s, w, a, st);
+    case 1: return fused_dispatch_s<M, float, true>(s, w, a, st);
+    case 2: return fused_dispatch_s<M, float, true, double>(s, w, a, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_fused(int model, int prec, int s, int w, const FusedPass &a, hipStream_t st) {

@@ -17,6 +17,8 @@ namespace chainrk4 {
 int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int hip_fail(hipError_t e, const char *what);
 size_t elem_bytes(int prec);
+bool has_carries(int prec);    // the FP32 precisions: per-site carries in the workspace
+size_t carry_bytes(int prec);  // bytes of one carry
 bool is_gfx950(int dev);
 
 #define HIP_TRY(expr)                                                  \

@@ -12,7 +12,8 @@ namespace chainrk4 {
 // update: q, p are float* and cq, cp are the float carries.
 struct StateRef {
     void *q, *p;
-    float *cq, *cp;
+    void *cq, *cp;   // compensated update: per-site carries (float, or double for
+                     // FP32 state with FP64 carries)
     double *z;   // third coordinate of the Roessler chain (q = x, p = y)
 };
 

@@ -12,7 +12,7 @@ namespace {
 
 constexpr int kNaiveThreads = 256;
 
-template <int M, class R, bool KAHAN, int STAGE>
+template <int M, class R, bool KAHAN, int STAGE, class C>
 __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBufs b, int64_t n,
                                                              double dt) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kNaiveThreads + threadIdx.x;
@@ -66,13 +66,19 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
         R *wp = static_cast<R *>(y.p);
         if constexpr (KAHAN) {
             R q1 = qj, p1 = pj;
-            float cq = y.cq[i], cp = y.cp[i];
-            kahan_add(q1, cq, c.h6 * accq);
-            kahan_add(p1, cp, c.h6 * accp);
+            C *ycq = static_cast<C *>(y.cq), *ycp = static_cast<C *>(y.cp);
+            C cq = ycq[i], cp = ycp[i];
+            if constexpr (sizeof(C) == 8) {
+                kahan_step(q1, cq, accq, c.h6d);
+                kahan_step(p1, cp, accp, c.h6d);
+            } else {
+                kahan_step(q1, cq, accq, c.h6, c.h6lo);
+                kahan_step(p1, cp, accp, c.h6, c.h6lo);
+            }
             wq[i] = q1;
             wp[i] = p1;
-            y.cq[i] = cq;
-            y.cp[i] = cp;
+            ycq[i] = cq;
+            ycp[i] = cp;
         } else {
             wq[i] = fma_r(c.h6, accq, qj);
             wp[i] = fma_r(c.h6, accp, pj);
@@ -80,15 +86,15 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
     }
 }
 
-template <int M, class R, bool KAHAN>
+template <int M, class R, bool KAHAN, class C = float>
 hipError_t naive_dispatch(StateRef y, const NaiveBufs &b, int64_t n, double dt, hipStream_t s) {
     const int64_t blocks = (n + kNaiveThreads - 1) / kNaiveThreads;
     if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>(blocks)), block(kNaiveThreads);
-    naive_stage<M, R, KAHAN, 1><<<grid, block, 0, s>>>(y, b, n, dt);
-    naive_stage<M, R, KAHAN, 2><<<grid, block, 0, s>>>(y, b, n, dt);
-    naive_stage<M, R, KAHAN, 3><<<grid, block, 0, s>>>(y, b, n, dt);
-    naive_stage<M, R, KAHAN, 4><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 1, C><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 2, C><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 3, C><<<grid, block, 0, s>>>(y, b, n, dt);
+    naive_stage<M, R, KAHAN, 4, C><<<grid, block, 0, s>>>(y, b, n, dt);
     return hipGetLastError();
 }
 
@@ -97,8 +103,12 @@ hipError_t naive_dispatch(StateRef y, const NaiveBufs &b, int64_t n, double dt, 
 template <int M>
 hipError_t naive_dispatch_prec(int prec, StateRef y, const NaiveBufs &b, int64_t n, double dt,
                                hipStream_t s) {
-    return prec == 0 ? naive_dispatch<M, double, false>(y, b, n, dt, s)
-                     : naive_dispatch<M, float, true>(y, b, n, dt, s);
+    switch (prec) {
+    case 0: return naive_dispatch<M, double, false>(y, b, n, dt, s);
+    case 1: return naive_dispatch<M, float, true>(y, b, n, dt, s);
+    case 2: return naive_dispatch<M, float, true, double>(y, b, n, dt, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_naive_step(int model, int prec, StateRef y, const NaiveBufs &b, int64_t n,

@@ -95,17 +95,37 @@ __device__ __forceinline__ R site_force2(R b1l, R b1r, R b2l, R b2r, R q) {
 template <class R>
 struct StepConsts {
     R h, hh, h6;
+    R h6lo;      // dt/6 - h6: with h6 it gives dt/6 to about twice R's precision
+    double h6d;  // dt/6 in FP64 (the compensated update with FP64 carries)
     __device__ __forceinline__ explicit StepConsts(double dt)
         : h(static_cast<R>(dt)),
           hh(static_cast<R>(0.5) * static_cast<R>(dt)),
-          h6(static_cast<R>(dt) / static_cast<R>(6)) {}
+          h6(static_cast<R>(dt / 6.0)),
+          h6lo(static_cast<R>(dt / 6.0 - static_cast<double>(static_cast<R>(dt / 6.0)))),
+          h6d(dt / 6.0) {}
 };
 
-// Kahan-compensated y += delta with carry c (the true value is y - c).
-__device__ __forceinline__ void kahan_add(float &y, float &c, float delta) {
-    float v = delta - c;
-    float t = y + v;
+// Kahan-compensated y += (hi + lo) * acc with carry c (the true value is
+// y - c). The step factor comes in two FP32 parts (hi + lo = h exactly to
+// about 48 bits), so the increment carries no systematic FP32 rounding of h:
+// a factor rounded once to FP32 scales every step's increment by the same
+// (1 + eps), a first-order error that the carry cannot undo. Two fused
+// multiply-adds form v = (hi + lo) acc - c with one final rounding, the same
+// instruction count as a product and a difference.
+__device__ __forceinline__ void kahan_step(float &y, float &c, float acc, float hi, float lo) {
+    const float v = __builtin_fmaf(hi, acc, __builtin_fmaf(lo, acc, -c));
+    const float t = y + v;
     c = (t - y) - v;
+    y = t;
+}
+
+// The same with an FP64 carry: the increment h * acc and the carry stay in
+// FP64, only the running value y is FP32 (its rounding error goes to the
+// carry; t - y of two FP32 values is exact in FP64).
+__device__ __forceinline__ void kahan_step(float &y, double &c, float acc, double h) {
+    const double v = h * static_cast<double>(acc) - c;
+    const float t = static_cast<float>(static_cast<double>(y) + v);
+    c = (static_cast<double>(t) - static_cast<double>(y)) - v;
     y = t;
 }
 
@@ -240,15 +260,21 @@ __device__ __forceinline__ void final_update(double (&q)[S], double (&p)[S], con
     }
 }
 
-// Final combination for FP32 with the Kahan-compensated sum.
-template <int S>
-__device__ __forceinline__ void final_update_kahan(float (&q)[S], float (&p)[S], float (&cq)[S],
-                                                   float (&cp)[S], const float (&aq)[S],
+// Final combination for FP32 with the Kahan-compensated sum: the increment
+// (h/6) acc with h/6 from the FP64 step, in the carry's precision.
+template <int S, class C>
+__device__ __forceinline__ void final_update_kahan(float (&q)[S], float (&p)[S], C (&cq)[S],
+                                                   C (&cp)[S], const float (&aq)[S],
                                                    const float (&ap)[S], const StepConsts<float> &c) {
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        kahan_add(q[j], cq[j], c.h6 * aq[j]);
-        kahan_add(p[j], cp[j], c.h6 * ap[j]);
+        if constexpr (sizeof(C) == 8) {
+            kahan_step(q[j], cq[j], aq[j], c.h6d);
+            kahan_step(p[j], cp[j], ap[j], c.h6d);
+        } else {
+            kahan_step(q[j], cq[j], aq[j], c.h6, c.h6lo);
+            kahan_step(p[j], cp[j], ap[j], c.h6, c.h6lo);
+        }
     }
 }
 

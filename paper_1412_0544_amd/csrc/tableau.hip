@@ -102,6 +102,7 @@ __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass
     LaneState<R, KAHAN, S> st;
     load_lane<R, KAHAN, S>(st, a.in, a.n, s0, e0 >= 0 && e0 + E <= a.n);
     const R dt = static_cast<R>(a.dt);
+    const R dtlo = static_cast<R>(a.dt - static_cast<double>(dt));  // dt - R(dt)
     const int s = t.stages;
     // kq[m] holds P_m (the q part of k_m) for m >= 1; the q part of k_0 is p
     R kq[SMAX][S], kp[SMAX][S], Q[S], fq[S], fp[S];
@@ -140,8 +141,8 @@ __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             if constexpr (KAHAN) {
-                kahan_add(st.q[i], st.cq[i], dt * fq[i]);
-                kahan_add(st.p[i], st.cp[i], dt * fp[i]);
+                kahan_step(st.q[i], st.cq[i], fq[i], dt, dtlo);
+                kahan_step(st.p[i], st.cp[i], fp[i], dt, dtlo);
             } else {
                 st.q[i] = fma_r(dt, fq[i], st.q[i]);
                 st.p[i] = fma_r(dt, fp[i], st.p[i]);
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(kNaiveTabThreads) void naive_tab_stage(StateRef y, 
     if (i >= n) return;
     using Ops = ModelOps<M, R>;
     const R dt = static_cast<R>(dt_);
+    const R dtlo = static_cast<R>(dt_ - static_cast<double>(dt));  // dt - R(dt)
     R *yq = static_cast<R *>(y.q);
     R *yp = static_cast<R *>(y.p);
     const R Qj = argq[i];
@@ -243,13 +245,14 @@ __global__ __launch_bounds__(kNaiveTabThreads) void naive_tab_stage(StateRef y, 
         }
         if constexpr (KAHAN) {
             R q1 = qi, p1 = pi;
-            float cq = y.cq[i], cp = y.cp[i];
-            kahan_add(q1, cq, dt * fq);
-            kahan_add(p1, cp, dt * fp);
+            float *ycq = static_cast<float *>(y.cq), *ycp = static_cast<float *>(y.cp);
+            float cq = ycq[i], cp = ycp[i];
+            kahan_step(q1, cq, fq, dt, dtlo);
+            kahan_step(p1, cp, fp, dt, dtlo);
             yq[i] = q1;
             yp[i] = p1;
-            y.cq[i] = cq;
-            y.cp[i] = cp;
+            ycq[i] = cq;
+            ycp[i] = cp;
         } else {
             yq[i] = fma_r(dt, fq, qi);
             yp[i] = fma_r(dt, fp, pi);

@@ -66,7 +66,7 @@ def test_long_chaotic_run_statistics_match_oracle(seed):
     assert abs(a.mean() - b.mean()) < 3 * se + 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan", "fp32_kahan64"])
 def test_checkpoint_and_resume_bitwise(prec):
     n = 50_000
     dtype = np.float64 if prec == "fp64" else np.float32

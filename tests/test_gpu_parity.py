@@ -242,10 +242,11 @@ def test_full_size_pi_mode_closed_form():
 FP32_TOL_100 = 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_kahan64"])
 @pytest.mark.parametrize("n", [1, 3, 1000, 20011])
-def test_fp32_kahan_error_bound(n):
+def test_fp32_kahan_error_bound(n, prec):
     q0, p0 = workloads.chain_ics(n, 10, dtype=np.float32)
-    ch = Chain(q0, p0, 0.01, prec="fp32_kahan", sites_per_lane=16, kdepth=4, resident=False)
+    ch = Chain(q0, p0, 0.01, prec=prec, sites_per_lane=16, kdepth=4, resident=False)
     ch.step(100)
     cq, cp = ch.carry_tensors()
     q = ch.q.double() - cq.double()
@@ -277,6 +278,45 @@ def test_fp32_paths_identical_bits():
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
+
+
+def test_fp32_fp64_carry_paths_identical_bits():
+    """FP32 state with FP64 carries: every tiled shape and the per-stage
+    method give the same bits, carries included."""
+    n = 4000
+    q0, p0 = workloads.chain_ics(n, 12, dtype=np.float32)
+    outs = []
+    for kw in (dict(sites_per_lane=16, kdepth=4), dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1),
+               dict(sites_per_lane=4, kdepth=12, waves_per_cluster=8),
+               dict(sites_per_lane=2, kdepth=5, waves_per_cluster=2),
+               dict(method="naive"), dict()):
+        ch = Chain(q0, p0, 0.01, prec="fp32_kahan64", **kw)
+        ch.step(30)
+        cq, cp = ch.carry_tensors()
+        assert cq.dtype == torch.float64
+        outs.append([t.cpu().numpy().copy() for t in (ch.q, ch.p, cq, cp)])
+        ch.close()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("model", ["harmonic", "quartic_nnn"])
+def test_fp64_carry_other_models(model):
+    n, steps = 3001, 60
+    q0, p0 = workloads.chain_ics(n, 13, dtype=np.float32)
+    ch = Chain(q0, p0, 0.01, model=model, prec="fp32_kahan64")
+    ch.step(steps)
+    cq, cp = ch.carry_tensors()
+    q = (ch.q.double() - cq).cpu().numpy()
+    p = (ch.p.double() - cp).cpu().numpy()
+    e = ch.energy()
+    ch.close()
+    mid = {"harmonic": oracle.HARMONIC, "quartic_nnn": oracle.QUARTIC_NNN}[model]
+    qo, po = oracle.rk4(mid, q0.astype(np.float64), p0.astype(np.float64), 0.01, steps)
+    assert maxerr(q, qo) <= FP32_TOL_100 and maxerr(p, po) <= FP32_TOL_100
+    eo = oracle.energy(mid, qo, po)
+    assert abs(e - eo) <= 1e-5 * abs(eo)
 
 
 def test_chain_longer_than_two_to_the_31():
