@@ -367,6 +367,18 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
                      "rel_drift_max_abs": float(np.max(np.abs(drift))),
                      "rel_drift_samples": drift[:: max(1, len(drift) // 20)]}
         ch.close()
+    # the drift again at a step exact in FP32 (2^-7): the FP32 stages then
+    # advance by the same step as the final combination
+    dt2 = 2.0 ** -7
+    out["exact_dt"] = {"dt": dt2, "steps": steps}
+    for name, prec, q, p in (("fp64", "fp64", q32.double(), p32.double()),
+                             ("fp32_kahan", "fp32_kahan", q32, p32),
+                             ("fp32_kahan64", "fp32_kahan64", q32, p32)):
+        ch = Chain(q, p, dt2, prec=prec, device=dev)
+        e0 = ch.energy()
+        ch.step(steps)
+        out["exact_dt"][name + "_rel_drift"] = (ch.energy() - e0) / e0
+        ch.close()
     # 100-step error against the oracle (FP32-rounded ICs), sampled sites
     q0 = q32.double().cpu().numpy()
     p0 = p32.double().cpu().numpy()
