@@ -45,7 +45,8 @@ FLOPS_PER_SU = {"quartic": 58, "harmonic": 38, "roessler": 75, "quartic_nnn": 78
                 "harmonic_nnn": 50}
 # Bytes per site-update of one pass: read q, p and write q, p once.
 BYTES_PER_SITE_PASS = {"fp64": 32, "fp32_kahan": 32,      # FP32: q, p, cq, cp
-                       "fp32_kahan64": 48}                # FP32 q, p; FP64 cq, cp
+                       "fp32_kahan64": 48,                # FP32 q, p; FP64 cq, cp
+                       "fp32": 16}                        # FP32 q, p, no carries
 BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 
 
@@ -342,7 +343,8 @@ def ev_seconds(fn, stream):
 
 
 def variant_precision(n, dt, dev, steps=10_000, every=100):
-    """FP32 state with compensated update (FP32 or FP64 carries) vs the FP64 GPU path on the same
+    """FP32 state with compensated update (FP32 or FP64 carries), and plain
+    FP32 as the control, vs the FP64 GPU path on the same
     chain: relative energy drift sampled every `every` steps, and the 100-step
     state error against the FP64 oracle (sampled sites, from the FP32-rounded
     initial state)."""
@@ -355,7 +357,8 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
     out = {"n": n, "steps": steps, "dt": dt}
     for name, prec, q, p in (("fp64", "fp64", q32.double(), p32.double()),
                              ("fp32_kahan", "fp32_kahan", q32, p32),
-                             ("fp32_kahan64", "fp32_kahan64", q32, p32)):
+                             ("fp32_kahan64", "fp32_kahan64", q32, p32),
+                             ("fp32", "fp32", q32, p32)):
         ch = Chain(q, p, dt, prec=prec, device=dev)
         e0 = ch.energy()
         drift = []
@@ -373,7 +376,8 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
     out["exact_dt"] = {"dt": dt2, "steps": steps}
     for name, prec, q, p in (("fp64", "fp64", q32.double(), p32.double()),
                              ("fp32_kahan", "fp32_kahan", q32, p32),
-                             ("fp32_kahan64", "fp32_kahan64", q32, p32)):
+                             ("fp32_kahan64", "fp32_kahan64", q32, p32),
+                             ("fp32", "fp32", q32, p32)):
         ch = Chain(q, p, dt2, prec=prec, device=dev)
         e0 = ch.energy()
         ch.step(steps)
@@ -386,7 +390,8 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
     qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, dt, 100, sites)
     for name, prec, q, p in (("fp64", "fp64", q32.double(), p32.double()),
                              ("fp32_kahan", "fp32_kahan", q32, p32),
-                             ("fp32_kahan64", "fp32_kahan64", q32, p32)):
+                             ("fp32_kahan64", "fp32_kahan64", q32, p32),
+                             ("fp32", "fp32", q32, p32)):
         ch = Chain(q, p, dt, prec=prec, device=dev)
         ch.step(100)
         cq, cp = ch.carry_tensors()

@@ -62,11 +62,14 @@ enum chain_prec {
     CHAIN_FP32_KAHAN = 1,  /* q, p and stages in FP32; the final update of each
                               step is Kahan-compensated with a per-site FP32
                               carry; energies are reduced in FP64 */
-    CHAIN_FP32_KAHAN64 = 2 /* as CHAIN_FP32_KAHAN with FP64 carries: the
+    CHAIN_FP32_KAHAN64 = 2,/* as CHAIN_FP32_KAHAN with FP64 carries: the
                               increment (h/6)*sum and the carry are FP64, q and
                               p stay FP32. Quartic and harmonic chains (NN and
                               NNN), classical RK4 on single handles; no
                               resident rings, tableaus or batches */
+    CHAIN_FP32 = 3         /* plain FP32, no compensation: the control against
+                              which the compensated forms are measured; the
+                              same restrictions as CHAIN_FP32_KAHAN64 */
 };
 
 enum chain_method {
@@ -175,7 +178,7 @@ size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d);
 /*
  * Create a handle over caller-owned device buffers.
  *   q, p       device arrays of d->n values (double for CHAIN_FP64, float for
- *              the two FP32 precisions), 16-byte aligned; they hold the initial state
+ *              the FP32 precisions), 16-byte aligned; they hold the initial state
  *              and, after each step call completes, the advanced state.
  *   workspace  device buffer of ws_bytes >= chain_rk4_workspace_bytes(d),
  *              256-byte aligned (NULL allowed only if that size is 0).
@@ -206,8 +209,8 @@ int chain_rk4_step(chain_rk4 *h, int64_t nsteps);
  * Total energy of the current state, in FP64, written to *e_out (host).
  * Quartic: sum_i p_i^2/2 + q_i^2/2 + q_i^4/4 + (q_{i+1}-q_i)^4/4;
  * harmonic: sum_i p_i^2/2 + q_i^2/2 + (q_{i+1}-q_i)^2/2; the NNN models add
- * (q_{i+2}-q_i)^4/4 or (q_{i+2}-q_i)^2/2 per site. For the FP32 precisions
- * each coordinate enters as (hi - carry) in FP64. The sum order is fixed for
+ * (q_{i+2}-q_i)^4/4 or (q_{i+2}-q_i)^2/2 per site. For the compensated FP32
+ * precisions each coordinate enters as (hi - carry) in FP64. The sum order is fixed for
  * a given n, so repeated calls agree bitwise. Synchronises the stream.
  * Returns CHAIN_ENONFINITE (with *e_out set) if the energy is NaN or Inf,
  * CHAIN_EINVAL for a CHAIN_ROESSLER handle (a dissipative system with no
@@ -223,8 +226,8 @@ int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out);
 
 /*
  * Device pointers of the per-site carries (n floats each, or n doubles for
- * CHAIN_FP32_KAHAN64, inside the workspace) that complete the state of an
- * FP32 handle: the
+ * CHAIN_FP32_KAHAN64, inside the workspace) that complete the state of a
+ * compensated FP32 handle: the
  * compensated coordinate is q - cq, the momentum p - cp. Copying q, p and
  * both carries saves the full state; writing them restores it. For CHAIN_FP64
  * both pointers are set to NULL.

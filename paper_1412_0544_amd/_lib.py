@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libchainrk4.so")
 
 CHAIN_QUARTIC, CHAIN_HARMONIC, CHAIN_ROESSLER = 0, 1, 2
 CHAIN_QUARTIC_NNN, CHAIN_HARMONIC_NNN = 3, 4
-CHAIN_FP64, CHAIN_FP32_KAHAN, CHAIN_FP32_KAHAN64 = 0, 1, 2
+CHAIN_FP64, CHAIN_FP32_KAHAN, CHAIN_FP32_KAHAN64, CHAIN_FP32 = 0, 1, 2, 3
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT, CHAIN_FLAG_RESIDENT = 1, 2, 4
 CHAIN_BATCH_FENCES, CHAIN_BATCH_RESIDENT_RINGS = 1, 2

@@ -14,7 +14,7 @@ from . import _lib as L
 MODELS = {"quartic": L.CHAIN_QUARTIC, "harmonic": L.CHAIN_HARMONIC,
           "quartic_nnn": L.CHAIN_QUARTIC_NNN, "harmonic_nnn": L.CHAIN_HARMONIC_NNN}
 PRECS = {"fp64": L.CHAIN_FP64, "fp32_kahan": L.CHAIN_FP32_KAHAN,
-         "fp32_kahan64": L.CHAIN_FP32_KAHAN64}
+         "fp32_kahan64": L.CHAIN_FP32_KAHAN64, "fp32": L.CHAIN_FP32}
 METHODS = {"fused": L.CHAIN_FUSED, "naive": L.CHAIN_NAIVE}
 
 
@@ -64,8 +64,9 @@ class Chain:
     of the precision's dtype; ``state()`` returns those tensors.
 
     model: "quartic", "harmonic", "quartic_nnn" or "harmonic_nnn";
-    prec: "fp64", "fp32_kahan" or "fp32_kahan64" (FP32 state, FP64 carries:
-    classical RK4 on a single tiled chain only); method: "fused" or "naive" (one kernel per
+    prec: "fp64", "fp32_kahan", "fp32_kahan64" (FP32 state, FP64 carries) or
+    "fp32" (no compensation, a control); the last two run classical RK4 on
+    a single tiled chain only. method: "fused" or "naive" (one kernel per
     stage). sites_per_lane, waves_per_cluster and kdepth fix the cluster
     shape (0 = the library's plan for this length). graph: replay each
     distinct step count from a captured graph (saves launch time on short

@@ -117,7 +117,7 @@ int check_handles(chain_rk4 *const *hs, int count, int model, int prec) {
             return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
         if (hs[i]->d.model != CHAIN_QUARTIC && hs[i]->d.model != CHAIN_HARMONIC)
             return fail(CHAIN_EINVAL, "handle %d: batches take the quartic and harmonic models only", i);
-        if (hs[i]->d.prec == CHAIN_FP32_KAHAN64)
+        if (hs[i]->d.prec == CHAIN_FP32_KAHAN64 || hs[i]->d.prec == CHAIN_FP32)
             return fail(CHAIN_EINVAL, "handle %d: batches take CHAIN_FP64 or CHAIN_FP32_KAHAN", i);
     }
     std::vector<chain_rk4 *> sorted(hs, hs + count);

@@ -115,7 +115,8 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC && d->model != CHAIN_ROESSLER &&
         d->model != CHAIN_QUARTIC_NNN && d->model != CHAIN_HARMONIC_NNN)
         return fail(CHAIN_EINVAL, "unknown model %d", d->model);
-    if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN && d->prec != CHAIN_FP32_KAHAN64)
+    if (d->prec != CHAIN_FP64 && d->prec != CHAIN_FP32_KAHAN && d->prec != CHAIN_FP32_KAHAN64 &&
+        d->prec != CHAIN_FP32)
         return fail(CHAIN_EINVAL, "unknown precision %d", d->prec);
     if (d->model == CHAIN_ROESSLER && d->prec != CHAIN_FP64)
         return fail(CHAIN_EINVAL, "the Roessler chain runs in FP64 only");
@@ -136,7 +137,7 @@ int check_desc(const chain_rk4_desc *d) {
     if (d->scheme == CHAIN_SCHEME_TABLEAU) {
         if (d->model == CHAIN_ROESSLER)
             return fail(CHAIN_EINVAL, "a tableau method is not available for the Roessler chain");
-        if (d->prec == CHAIN_FP32_KAHAN64)
+        if (d->prec == CHAIN_FP32_KAHAN64 || d->prec == CHAIN_FP32)
             return fail(CHAIN_EINVAL, "tableau methods take CHAIN_FP64 or CHAIN_FP32_KAHAN");
     }
     if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT | CHAIN_FLAG_RESIDENT))
@@ -150,7 +151,7 @@ int check_desc(const chain_rk4_desc *d) {
             d->scheme != CHAIN_SCHEME_RK4 || d->method != CHAIN_FUSED)
             return fail(CHAIN_EINVAL, "resident rings run the classical RK4 of the quartic and "
                                       "harmonic chains on the fused path only");
-        if (d->prec == CHAIN_FP32_KAHAN64)
+        if (d->prec == CHAIN_FP32_KAHAN64 || d->prec == CHAIN_FP32)
             return fail(CHAIN_EINVAL, "resident rings take CHAIN_FP64 or CHAIN_FP32_KAHAN");
     }
     return CHAIN_OK;

@@ -101,6 +101,7 @@ hipError_t energy_dispatch_prec(int prec, StateRef y, int64_t n, double *partial
     case 0: return energy_dispatch<M, double, false>(y, n, partials, result, s);
     case 1: return energy_dispatch<M, float, true>(y, n, partials, result, s);
     case 2: return energy_dispatch<M, float, true, double>(y, n, partials, result, s);
+    case 3: return energy_dispatch<M, float, false>(y, n, partials, result, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -110,6 +110,7 @@ hipError_t fused_dispatch_prec(int prec, int s, int w, const FusedPass &a, hipSt
     case 0: return fused_dispatch_s<M, double, false>(s, w, a, st);
     case 1: return fused_dispatch_s<M, float, true>(s, w, a, st);
     case 2: return fused_dispatch_s<M, float, true, double>(s, w, a, st);
+    case 3: return fused_dispatch_s<M, float, false>(s, w, a, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -107,6 +107,7 @@ hipError_t naive_dispatch_prec(int prec, StateRef y, const NaiveBufs &b, int64_t
     case 0: return naive_dispatch<M, double, false>(y, b, n, dt, s);
     case 1: return naive_dispatch<M, float, true>(y, b, n, dt, s);
     case 2: return naive_dispatch<M, float, true, double>(y, b, n, dt, s);
+    case 3: return naive_dispatch<M, float, false>(y, b, n, dt, s);
     default: return hipErrorInvalidValue;
     }
 }

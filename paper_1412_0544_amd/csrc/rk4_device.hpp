@@ -249,10 +249,11 @@ __device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&P)[S], R (&q)[S],
     }
 }
 
-// Final combination (Eq. 5) for FP64: y = y + (h/6) acc.
-template <int S>
-__device__ __forceinline__ void final_update(double (&q)[S], double (&p)[S], const double (&aq)[S],
-                                             const double (&ap)[S], const StepConsts<double> &c) {
+// Final combination (Eq. 5) without compensation: y = y + (h/6) acc (FP64,
+// or plain FP32).
+template <int S, class R>
+__device__ __forceinline__ void final_update(R (&q)[S], R (&p)[S], const R (&aq)[S],
+                                             const R (&ap)[S], const StepConsts<R> &c) {
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         q[j] = fma_r(c.h6, aq[j], q[j]);

@@ -43,7 +43,7 @@ def test_workspace_bytes():
     assert f(desc(n=4096, flags=4)) > 0                            # resident ring
     # per-stage tableau method: 7 + 7 slope arrays and two stage arguments
     assert f(desc(n=1 << 20, method=1, scheme=1)) >= 18 * 8 * (1 << 20)
-    for bad in (desc(n=0), desc(model=7), desc(prec=3), desc(prec=-1), desc(dt=float("nan")),
+    for bad in (desc(n=0), desc(model=7), desc(prec=4), desc(prec=-1), desc(dt=float("nan")),
                 desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
                 desc(kdepth=33), desc(kdepth=-1), desc(sites_per_lane=2, model=2), desc(sites_per_lane=1), desc(model=5), desc(model=2, prec=1), desc(flags=64), desc(waves_per_cluster=3),
                 desc(waves_per_cluster=16), desc(scheme=7), desc(scheme=1, model=2),
@@ -65,6 +65,21 @@ def test_fp64_carry_precision_validation_and_workspace():
     for m in (0, 1, 3, 4):
         assert f(desc(prec=2, model=m)) > 0
     for bad in (desc(prec=2, flags=4), desc(prec=2, scheme=1), desc(prec=2, model=2)):
+        assert f(bad) == 0
+
+
+def test_plain_fp32_control_precision_validation_and_workspace():
+    """CHAIN_FP32 (no compensation) keeps no carries: the workspace of the
+    fused path is the FP32 back buffer, 8 bytes per site, below the
+    compensated form's 24; the same restrictions as the FP64-carry form."""
+    lib = L.lib()
+    f = lambda d: lib.chain_rk4_workspace_bytes(ctypes.byref(d))
+    n = 1 << 20
+    assert f(desc(n=n, prec=1)) - f(desc(n=n, prec=3)) == 4 * 4 * n
+    assert f(desc(n=n, prec=0)) - f(desc(n=n, prec=3)) == 2 * 4 * n
+    for m in (0, 1, 3, 4):
+        assert f(desc(prec=3, model=m)) > 0 and f(desc(prec=3, model=m, method=1)) > 0
+    for bad in (desc(prec=3, flags=4), desc(prec=3, scheme=1), desc(prec=3, model=2)):
         assert f(bad) == 0
 
 

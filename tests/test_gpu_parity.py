@@ -301,6 +301,37 @@ def test_fp32_fp64_carry_paths_identical_bits():
             assert np.array_equal(a, b)
 
 
+def test_plain_fp32_control():
+    """Plain FP32 (no compensation): every tiled shape and the per-stage
+    method give the same bits; its 100-step error stays within 1e-4 of the
+    FP64 oracle and is at least 4x the compensated form's (N = 2^16)."""
+    n = 1 << 16
+    q0, p0 = workloads.chain_ics(n, 14, dtype=np.float32)
+    outs = []
+    for kw in (dict(sites_per_lane=16, kdepth=4), dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1),
+               dict(sites_per_lane=2, kdepth=5, waves_per_cluster=2), dict(method="naive"), dict()):
+        ch = Chain(q0, p0, 0.01, prec="fp32", **kw)
+        ch.step(100)
+        assert ch.carry_tensors() == (None, None)
+        outs.append([t.cpu().numpy().copy() for t in (ch.q, ch.p)])
+        ch.close()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+    sites = np.unique(np.linspace(0, n - 1, 64).astype(np.int64))
+    qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0.astype(np.float64), p0.astype(np.float64), 0.01,
+                              100, sites, threads=8)
+    plain = max(maxerr(outs[0][0][sites], qs), maxerr(outs[0][1][sites], ps))
+    ch = Chain(q0, p0, 0.01, prec="fp32_kahan")
+    ch.step(100)
+    cq, cp = ch.carry_tensors()
+    q = (ch.q.double() - cq.double()).cpu().numpy()[sites]
+    p = (ch.p.double() - cp.double()).cpu().numpy()[sites]
+    ch.close()
+    comp = max(maxerr(q, qs), maxerr(p, ps))
+    assert plain <= 1e-4 and comp * 4 <= plain, (plain, comp)
+
+
 @pytest.mark.parametrize("model", ["harmonic", "quartic_nnn"])
 def test_fp64_carry_other_models(model):
     n, steps = 3001, 60
