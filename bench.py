@@ -55,9 +55,9 @@ BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 # the kernel sources with this sha256 and this cluster shape (sites per lane,
 # wavefronts per cluster, halo) on N = 2^24.
 MEASURED_TRAFFIC = {
-    "sha256": "359b0ed04907d491d88b3de0f651e9984393cb213c8977228795d040fec0c7e9",
+    "sha256": "774fc3936d47d53b94322b150c2a3357ef1932ac8a1865c30de8224e7ca284ad",
     "shape": (8, 4, 64), "n": 1 << 24,
-    "bytes_per_launch": 555252619, "fetch_factor": 0.5000, "write_factor": 1.0000,
+    "bytes_per_launch": 555307777, "fetch_factor": 0.5000, "write_factor": 1.0000,
 }
 
 
@@ -191,6 +191,10 @@ def main(argv=None):
     ap.add_argument("--roessler", action="store_true",
                     help="only the Roessler chain with the paper's protocol (N = 2^20, T = 50 "
                          "steps, best of 10)")
+    ap.add_argument("--roessler-n", type=int, default=1 << 20,
+                    help="chain length of --roessler (the paper's is 2^20)")
+    ap.add_argument("--roessler-steps", type=int, default=50,
+                    help="steps per timed call of --roessler (the paper's T is 50)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -218,11 +222,13 @@ def main(argv=None):
                           "plan_sweep": plan_sweep(dev)}), flush=True)
         return 0
     if args.roessler:
+        rn, rs = args.roessler_n, args.roessler_steps
         print(json.dumps({"metric": "RK4 steps/s of the Roessler chain (Perf = T / t_wall)",
                           "unit": "steps/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
-                          "config": {"workload": "Roessler chain N=2^20, dt=0.01, T=50 steps, "
+                          "config": {"workload": f"Roessler chain N={rn}, dt=0.01, T={rs} steps, "
                                                  "best of 10"},
-                          "roessler": variant_roessler(dev, sweep=args.sweep)}), flush=True)
+                          "roessler": variant_roessler(dev, n=rn, steps=rs, sweep=args.sweep)}),
+              flush=True)
         return 0
     n, dt, js = args.n, 0.01, args.job_steps
     log(f"[bench] generating ICs n={n}")
@@ -524,7 +530,7 @@ def size_sweep(dev, dt=0.01, steps=50, trials=10, exps=range(10, 27, 2)):
 
 
 def roessler_shapes():
-    return [(s, w, k) for s in (4, 8) for w in (1, 2, 4, 8) for k in (4, 8, 16)
+    return [(s, w, k) for s in (4, 8) for w in (1, 2, 4, 8) for k in (8, 16, 25, 32)
             if 64 * s * w > 16 * k]
 
 
