@@ -191,6 +191,13 @@ def main(argv=None):
     ap.add_argument("--roessler", action="store_true",
                     help="only the Roessler chain with the paper's protocol (N = 2^20, T = 50 "
                          "steps, best of 10)")
+    ap.add_argument("--serve", action="store_true",
+                    help="only the served-job workload: --serve-jobs jobs at each load in "
+                         "--serve-rho")
+    ap.add_argument("--serve-rho", default="0.5,0.8",
+                    help="offered loads of --serve, comma separated")
+    ap.add_argument("--serve-rate", type=float, default=5.4e11,
+                    help="device capacity (site-updates/s) the loads of --serve refer to")
     ap.add_argument("--roessler-n", type=int, default=1 << 20,
                     help="chain length of --roessler (the paper's is 2^20)")
     ap.add_argument("--roessler-steps", type=int, default=50,
@@ -220,6 +227,20 @@ def main(argv=None):
                           "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
                           "config": {"workload": "quartic chain, dt=0.01, 64 steps, best of 3"},
                           "plan_sweep": plan_sweep(dev)}), flush=True)
+        return 0
+    if args.serve:
+        loads = {}
+        for rho in (float(x) for x in args.serve_rho.split(",")):
+            log(f"[bench] serving {args.serve_jobs} jobs at load {rho}")
+            loads[str(rho)] = variant_serving(0.01, dev, jobs=args.serve_jobs, rho=rho,
+                                              rate_su=args.serve_rate)
+        print(json.dumps({"metric": "served-job latency p50/p99 and throughput", "unit": "s",
+                          "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": f"{args.serve_jobs} jobs, N log-uniform "
+                                                 "[1e3, 4e6], steps U[1e3, 1e5], Poisson "
+                                                 f"arrivals at rho x {args.serve_rate:.3g} "
+                                                 "site-updates/s"},
+                          "serving": loads}), flush=True)
         return 0
     if args.roessler:
         rn, rs = args.roessler_n, args.roessler_steps
