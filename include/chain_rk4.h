@@ -170,8 +170,9 @@ typedef struct chain_rk4_plan {
 
 /*
  * Device workspace bytes a chain described by `d` needs (the back buffer of
- * the ping-pong update, the FP32 carries, the naive method's stage arrays and
- * the energy partials). Returns 0 if `d` is invalid.
+ * the ping-pong update, the carries of the compensated FP32 precisions, the
+ * naive method's stage arrays and the energy partials). Returns 0 if `d` is
+ * invalid.
  */
 size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d);
 
@@ -183,8 +184,8 @@ size_t chain_rk4_workspace_bytes(const chain_rk4_desc *d);
  *   workspace  device buffer of ws_bytes >= chain_rk4_workspace_bytes(d),
  *              256-byte aligned (NULL allowed only if that size is 0).
  *   stream     stream for every later call on this handle.
- * The handle borrows q, p and workspace until chain_rk4_destroy. The FP32
- * carries are zeroed on `stream`. Returns CHAIN_EINVAL for NULL or misaligned
+ * The handle borrows q, p and workspace until chain_rk4_destroy. The carries
+ * of a compensated FP32 precision are zeroed on `stream`. Returns CHAIN_EINVAL for NULL or misaligned
  * pointers or an invalid descriptor, CHAIN_ENOMEM if ws_bytes is too small,
  * CHAIN_EDEVICE if the current device is not gfx950.
  */
@@ -227,10 +228,10 @@ int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out);
 /*
  * Device pointers of the per-site carries (n floats each, or n doubles for
  * CHAIN_FP32_KAHAN64, inside the workspace) that complete the state of a
- * compensated FP32 handle: the
- * compensated coordinate is q - cq, the momentum p - cp. Copying q, p and
- * both carries saves the full state; writing them restores it. For CHAIN_FP64
- * both pointers are set to NULL.
+ * compensated FP32 handle: the compensated coordinate is q - cq, the momentum
+ * p - cp. Copying q, p and both carries saves the full state; writing them
+ * restores it. For CHAIN_FP64 and CHAIN_FP32 (no carries) both pointers are
+ * set to NULL.
  */
 int chain_rk4_get_carries(const chain_rk4 *h, void **cq, void **cp);
 
