@@ -94,8 +94,8 @@ using SlotsOf = typename std::conditional<coupling_range<M>() == 2, EdgeSlots2<R
 // lane 0 forms its left bond term itself (the same operation on the same
 // values as the left wavefront's lane 63).
 template <int M, int S, int STAGE, int W, int WPB, class R>
-__device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S], R (&aq)[S],
-                                           R (&ap)[S], const StepConsts<R> &c,
+__device__ __forceinline__ void lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S], R (&s)[S],
+                                           R (&a)[S], const StepConsts<R> &c,
                                            EdgeSlots<R, WPB> *slots, int lane, int wib, int wic,
                                            int parity) {
     const R first = (STAGE == 1) ? q[0] : Q[0];
@@ -112,7 +112,7 @@ __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&
     if constexpr (W > 1) {
         if (lane == 0 && wic > 0) bl0 = ModelOps<M, R>::bond(first - slots->last[parity][wib - 1]);
     }
-    stage_sites<M, S, STAGE>(Q, P, q, p, aq, ap, bl0, brS, c);
+    stage_sites<M, S, STAGE>(Q, X, q, p, s, a, bl0, brS, c);
 }
 
 // The same with next-nearest-neighbour coupling: the right neighbour lane's
@@ -122,8 +122,8 @@ __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&
 // cluster lane 0 forms them itself from the left wavefront's last two
 // coordinates (the same operations on the same values).
 template <int M, int S, int STAGE, int W, int WPB, class R>
-__device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
-                                               R (&aq)[S], R (&ap)[S], const StepConsts<R> &c,
+__device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
+                                               R (&s)[S], R (&a)[S], const StepConsts<R> &c,
                                                EdgeSlots2<R, WPB> *slots, int lane, int wib,
                                                int wic, int parity) {
     using Ops = ModelOps<M, R>;
@@ -160,19 +160,19 @@ __device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&P)[S], R (&q)[S], 
             b2lm1 = Ops::bond(f1 - L0);
         }
     }
-    stage_sites_nnn<M, S, STAGE>(Q, P, q, p, aq, ap, b1l0, b2lm2, b2lm1, b1rS, b2rS2, b2rS1, c);
+    stage_sites_nnn<M, S, STAGE>(Q, X, q, p, s, a, b1l0, b2lm2, b2lm1, b1rS, b2rS2, b2rS1, c);
 }
 
 // Dispatch on the coupling range of the model.
 template <int M, int S, int STAGE, int W, int WPB, class R>
-__device__ __forceinline__ void any_lane_stage(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
-                                               R (&aq)[S], R (&ap)[S], const StepConsts<R> &c,
+__device__ __forceinline__ void any_lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
+                                               R (&s)[S], R (&a)[S], const StepConsts<R> &c,
                                                SlotsOf<M, R, WPB> *slots, int lane, int wib,
                                                int wic, int parity) {
     if constexpr (coupling_range<M>() == 2)
-        lane_stage_nnn<M, S, STAGE, W, WPB>(Q, P, q, p, aq, ap, c, slots, lane, wib, wic, parity);
+        lane_stage_nnn<M, S, STAGE, W, WPB>(Q, X, q, p, s, a, c, slots, lane, wib, wic, parity);
     else
-        lane_stage<M, S, STAGE, W, WPB>(Q, P, q, p, aq, ap, c, slots, lane, wib, wic, parity);
+        lane_stage<M, S, STAGE, W, WPB>(Q, X, q, p, s, a, c, slots, lane, wib, wic, parity);
 }
 
 // Device-coherent element access (memory scope: agent). Stores are written
@@ -322,16 +322,16 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     LaneState<R, KAHAN, S, C> st;
     load_lane<R, KAHAN, S, COH, C>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
     const StepConsts<R> c(dt);
-    R Q[S], P[S], aq[S], ap[S];
+    R Q[S], X[S], s[S], a[S];  // stage argument and the values site_update carries
     for (int k = 0; k < ksteps; ++k) {
-        any_lane_stage<M, S, 1, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
-        any_lane_stage<M, S, 2, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
-        any_lane_stage<M, S, 3, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 0);
-        any_lane_stage<M, S, 4, W, WPB>(Q, P, st.q, st.p, aq, ap, c, slots, lane, wib, wic, 1);
+        any_lane_stage<M, S, 1, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
+        any_lane_stage<M, S, 2, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
+        any_lane_stage<M, S, 3, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
+        any_lane_stage<M, S, 4, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
         if constexpr (KAHAN)
-            final_update_kahan<S>(st.q, st.p, st.cq, st.cp, aq, ap, c);
+            final_update_kahan<S>(st.q, st.p, st.cq, st.cp, s, a, c);
         else
-            final_update<S>(st.q, st.p, aq, ap, c);
+            final_update<S>(st.q, st.p, s, a, c);
     }
     store_lane<R, KAHAN, S, COH, C>(st, out, n, s0, lo, halo, halo + keep);
 }
@@ -339,7 +339,8 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
 // Whole-ring resident run by a block of T threads: thread t owns sites
 // t + T*j (j < SPT, n <= T*SPT). The stage argument of every site is
 // published in LDS (`lds` holds 2*n values, two buffers used in turn, one
-// barrier per stage); the state, P and the accumulators stay in registers.
+// barrier per stage); the state and the values carried between stages stay
+// in registers.
 // `out` may equal `in`: every load happens before the first store.
 template <int M, class R, bool KAHAN, int T, int SPT>
 __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef &out, int n,
@@ -349,7 +350,7 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
     const int t = threadIdx.x;
     const R *qin = static_cast<const R *>(in.q);
     const R *pin = static_cast<const R *>(in.p);
-    R q[SPT], p[SPT], Q[SPT], P[SPT], aq[SPT], ap[SPT];  // Q: own stage argument
+    R q[SPT], p[SPT], Q[SPT], X[SPT], s[SPT], a[SPT];  // Q: own stage argument
     float cq[KAHAN ? SPT : 1], cp[KAHAN ? SPT : 1];
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
@@ -382,27 +383,21 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
                     const int im = (i == 0) ? n - 1 : i - 1;
                     const int ip = (i == n - 1) ? 0 : i + 1;
                     const R Qm = cur[im], Qj = Q[j], Qp = cur[ip];
-                    R Qn = Qj, Pn = P[j];
+                    R Qn = Qj;
                     if (stage == 1) {
-                        stage_one<M, 1, R>(Qm, Qj, Qp, p[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                        stage_one<M, 1, R>(Qm, Qj, Qp, q[j], p[j], X[j], s[j], a[j], Qn, c);
                     } else if (stage == 2) {
-                        stage_one<M, 2, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                        stage_one<M, 2, R>(Qm, Qj, Qp, q[j], p[j], X[j], s[j], a[j], Qn, c);
                     } else if (stage == 3) {
-                        stage_one<M, 3, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
+                        stage_one<M, 3, R>(Qm, Qj, Qp, q[j], p[j], X[j], s[j], a[j], Qn, c);
                     } else {
-                        stage_one<M, 4, R>(Qm, Qj, Qp, P[j], q[j], p[j], aq[j], ap[j], Qn, Pn, c);
-                        if constexpr (KAHAN) {
-                            kahan_step(q[j], cq[j], aq[j], c.h6, c.h6lo);
-                            kahan_step(p[j], cp[j], ap[j], c.h6, c.h6lo);
-                        } else {
-                            q[j] = fma_r(c.h6, aq[j], q[j]);
-                            p[j] = fma_r(c.h6, ap[j], p[j]);
-                        }
+                        stage_one<M, 4, R>(Qm, Qj, Qp, q[j], p[j], X[j], s[j], a[j], Qn, c);
+                        site_final<R, KAHAN, float>(q[j], p[j], cq[KAHAN ? j : 0],
+                                                    cp[KAHAN ? j : 0], s[j], a[j], c);
                         Qn = q[j];
                     }
                     nxt[i] = Qn;
                     Q[j] = Qn;
-                    if (stage != 4) P[j] = Pn;
                 }
             }
             __syncthreads();

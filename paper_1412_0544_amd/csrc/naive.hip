@@ -1,9 +1,10 @@
 // naive.hip -- the standard implementation of an RK4 step (Sec. 2.2): one
-// kernel per stage, each a full sweep over the chain whose results (the
-// slope k_j and the next stage argument, Eq. 3-4) go through memory. Stage 4
-// reads k1..k3 back and applies the final combination (Eq. 5) in place. It is
-// the baseline the fused kernel is measured against, and it uses the same
-// per-site operation order, so both give identical bits.
+// kernel per stage, each a full sweep over the chain whose per-site results
+// go through memory before the next stage reads them. It is the baseline the
+// fused kernel is measured against, and it uses the same per-site operation
+// order (site_update, site_final), so both give identical bits. What goes
+// through memory: the stage argument (Q2 and Q4 in one array, Q3 in another),
+// F1, F2 and the running sum F1 + F2 + F3.
 #include "launch.hpp"
 #include "rk4_device.hpp"
 
@@ -21,68 +22,66 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
     const int64_t ip = (i == n - 1) ? 0 : i + 1;
     const R *yq = static_cast<const R *>(y.q);
     const R *yp = static_cast<const R *>(y.p);
-    // stage argument: y itself, then the ping-pong stage buffers
-    const R *aq = STAGE == 1 ? yq : STAGE == 3 ? static_cast<const R *>(b.ybq) : static_cast<const R *>(b.yaq);
-    const R *ap = STAGE == 1 ? yp : STAGE == 3 ? static_cast<const R *>(b.ybp) : static_cast<const R *>(b.yap);
+    R *Qa = static_cast<R *>(b.yaq);   // Q2, then Q4
+    R *Qb = static_cast<R *>(b.ybq);   // Q3
+    R *F1 = static_cast<R *>(b.k1p);
+    R *F2 = static_cast<R *>(b.k2p);
+    R *sum = static_cast<R *>(b.k2q);  // F1 + F2 (+ F3)
+    // stage argument: q, Q2, Q3, Q4
+    const R *arg = STAGE == 1 ? yq : STAGE == 3 ? Qb : Qa;
     const StepConsts<R> c(dt);
 
-    const R Qj = aq[i];
-    const R Pj = ap[i];
+    const R Qj = arg[i];
     R F;
     if constexpr (coupling_range<M>() == 2) {
-        const R b1l = ModelOps<M, R>::bond(Qj - aq[im]);
-        const R b1r = ModelOps<M, R>::bond(aq[ip] - Qj);
-        const R b2l = ModelOps<M, R>::bond(Qj - aq[wrap_index(i - 2, n)]);
-        const R b2r = ModelOps<M, R>::bond(aq[wrap_index(i + 2, n)] - Qj);
+        const R b1l = ModelOps<M, R>::bond(Qj - arg[im]);
+        const R b1r = ModelOps<M, R>::bond(arg[ip] - Qj);
+        const R b2l = ModelOps<M, R>::bond(Qj - arg[wrap_index(i - 2, n)]);
+        const R b2r = ModelOps<M, R>::bond(arg[wrap_index(i + 2, n)] - Qj);
         F = site_force2<M, R>(b1l, b1r, b2l, b2r, Qj);
     } else {
-        const R bl = ModelOps<M, R>::bond(Qj - aq[im]);
-        const R br = ModelOps<M, R>::bond(aq[ip] - Qj);
+        const R bl = ModelOps<M, R>::bond(Qj - arg[im]);
+        const R br = ModelOps<M, R>::bond(arg[ip] - Qj);
         F = site_force<M, R>(bl, br, Qj);
     }
     const R qj = yq[i];
     const R pj = yp[i];
-
-    if constexpr (STAGE < 4) {
-        R *kq = static_cast<R *>(STAGE == 1 ? b.k1q : STAGE == 2 ? b.k2q : b.k3q);
-        R *kp = static_cast<R *>(STAGE == 1 ? b.k1p : STAGE == 2 ? b.k2p : b.k3p);
-        R *nq = static_cast<R *>(STAGE == 2 ? b.ybq : b.yaq);
-        R *np = static_cast<R *>(STAGE == 2 ? b.ybp : b.yap);
-        const R a = STAGE == 3 ? c.h : c.hh;
-        kq[i] = Pj;
-        kp[i] = F;
-        nq[i] = fma_r(a, Pj, qj);
-        np[i] = fma_r(a, F, pj);
+    R Qo = Qj, X = 0, sj = 0, a = 0;
+    if constexpr (STAGE == 1) {
+        site_update<1>(F, Qj, Qo, X, qj, pj, sj, a, c);
+        Qa[i] = Qo;
+        F1[i] = a;
+    } else if constexpr (STAGE == 2) {
+        sj = F1[i];
+        site_update<2>(F, Qj, Qo, X, qj, pj, sj, a, c);
+        Qb[i] = Qo;
+        F2[i] = X;
+        sum[i] = sj;
+    } else if constexpr (STAGE == 3) {
+        X = F2[i];
+        sj = sum[i];
+        site_update<3>(F, Qj, Qo, X, qj, pj, sj, a, c);
+        Qa[i] = Qo;
+        sum[i] = sj;
     } else {
-        R accq = static_cast<const R *>(b.k1q)[i];
-        R accp = static_cast<const R *>(b.k1p)[i];
-        accq = fma_r(static_cast<R>(2), static_cast<const R *>(b.k2q)[i], accq);
-        accp = fma_r(static_cast<R>(2), static_cast<const R *>(b.k2p)[i], accp);
-        accq = fma_r(static_cast<R>(2), static_cast<const R *>(b.k3q)[i], accq);
-        accp = fma_r(static_cast<R>(2), static_cast<const R *>(b.k3p)[i], accp);
-        accq = accq + Pj;
-        accp = accp + F;
+        sj = sum[i];
+        a = F1[i];
+        site_update<4>(F, Qj, Qo, X, qj, pj, sj, a, c);
+        R q1 = qj, p1 = pj;
         R *wq = static_cast<R *>(y.q);
         R *wp = static_cast<R *>(y.p);
         if constexpr (KAHAN) {
-            R q1 = qj, p1 = pj;
             C *ycq = static_cast<C *>(y.cq), *ycp = static_cast<C *>(y.cp);
             C cq = ycq[i], cp = ycp[i];
-            if constexpr (sizeof(C) == 8) {
-                kahan_step(q1, cq, accq, c.h6d);
-                kahan_step(p1, cp, accp, c.h6d);
-            } else {
-                kahan_step(q1, cq, accq, c.h6, c.h6lo);
-                kahan_step(p1, cp, accp, c.h6, c.h6lo);
-            }
-            wq[i] = q1;
-            wp[i] = p1;
+            site_final<R, true, C>(q1, p1, cq, cp, sj, a, c);
             ycq[i] = cq;
             ycp[i] = cp;
         } else {
-            wq[i] = fma_r(c.h6, accq, qj);
-            wp[i] = fma_r(c.h6, accp, pj);
+            R unused = 0;
+            site_final<R, false, R>(q1, p1, unused, unused, sj, a, c);
         }
+        wq[i] = q1;
+        wp[i] = p1;
     }
 }
 

@@ -91,18 +91,31 @@ __device__ __forceinline__ R site_force2(R b1l, R b1r, R b2l, R b2r, R q) {
     return ((b1r - b1l) + (b2r - b2l)) - ModelOps<M, R>::onsite(q);
 }
 
-// Step constants in the working precision.
+// Step constants in the working precision. The products of two step factors
+// (hh2, hhh, h26) are formed in FP64 and rounded once.
 template <class R>
 struct StepConsts {
     R h, hh, h6;
-    R h6lo;      // dt/6 - h6: with h6 it gives dt/6 to about twice R's precision
-    double h6d;  // dt/6 in FP64 (the compensated update with FP64 carries)
+    R hh2;       // (h/2)^2
+    R hhh;       // h * h/2
+    R h26;       // h^2/6
+    R hlo;       // dt - h: with h it gives dt to about twice R's precision
+    R h6lo;      // dt/6 - h6, the same for dt/6
+    R h26lo;     // dt^2/6 - h26, the same for dt^2/6
+    double hd, h6d, h26d;  // dt, dt/6, dt^2/6 in FP64 (FP64 carries)
     __device__ __forceinline__ explicit StepConsts(double dt)
         : h(static_cast<R>(dt)),
           hh(static_cast<R>(0.5) * static_cast<R>(dt)),
           h6(static_cast<R>(dt / 6.0)),
+          hh2(static_cast<R>((0.5 * dt) * (0.5 * dt))),
+          hhh(static_cast<R>(dt * (0.5 * dt))),
+          h26(static_cast<R>(dt * dt / 6.0)),
+          hlo(static_cast<R>(dt - static_cast<double>(static_cast<R>(dt)))),
           h6lo(static_cast<R>(dt / 6.0 - static_cast<double>(static_cast<R>(dt / 6.0)))),
-          h6d(dt / 6.0) {}
+          h26lo(static_cast<R>(dt * dt / 6.0 - static_cast<double>(static_cast<R>(dt * dt / 6.0)))),
+          hd(dt),
+          h6d(dt / 6.0),
+          h26d(dt * dt / 6.0) {}
 };
 
 // Kahan-compensated y += (hi + lo) * acc with carry c (the true value is
@@ -112,21 +125,28 @@ struct StepConsts {
 // (1 + eps), a first-order error that the carry cannot undo. Two fused
 // multiply-adds form v = (hi + lo) acc - c with one final rounding, the same
 // instruction count as a product and a difference.
-__device__ __forceinline__ void kahan_step(float &y, float &c, float acc, float hi, float lo) {
-    const float v = __builtin_fmaf(hi, acc, __builtin_fmaf(lo, acc, -c));
+// Add v = increment - c to y and keep the new rounding error in c.
+__device__ __forceinline__ void kahan_finish(float &y, float &c, float v) {
     const float t = y + v;
     c = (t - y) - v;
     y = t;
 }
 
-// The same with an FP64 carry: the increment h * acc and the carry stay in
-// FP64, only the running value y is FP32 (its rounding error goes to the
-// carry; t - y of two FP32 values is exact in FP64).
-__device__ __forceinline__ void kahan_step(float &y, double &c, float acc, double h) {
-    const double v = h * static_cast<double>(acc) - c;
+// The same with an FP64 carry: the increment and the carry stay in FP64, only
+// the running value y is FP32 (its rounding error goes to the carry; t - y of
+// two FP32 values is exact in FP64).
+__device__ __forceinline__ void kahan_finish(float &y, double &c, double v) {
     const float t = static_cast<float>(static_cast<double>(y) + v);
     c = (static_cast<double>(t) - static_cast<double>(y)) - v;
     y = t;
+}
+
+__device__ __forceinline__ void kahan_step(float &y, float &c, float acc, float hi, float lo) {
+    kahan_finish(y, c, __builtin_fmaf(hi, acc, __builtin_fmaf(lo, acc, -c)));
+}
+
+__device__ __forceinline__ void kahan_step(float &y, double &c, float acc, double h) {
+    kahan_finish(y, c, h * static_cast<double>(acc) - c);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,51 +184,82 @@ template <class R>
 __device__ __forceinline__ R from_left(R x) { return dpp<kDppWaveShr1>(x); }
 
 // ---------------------------------------------------------------------------
-// The per-site part of stage STAGE once the force F at the stage argument
-// (Q, P) is known: accumulate k_STAGE and form the next stage argument.
-// Stage 1 reads its argument from q, p; Qo, Po receive the next argument.
+// The per-site part of stage STAGE once the force F_STAGE at the stage
+// argument Q_STAGE is known.
+//
+// For dq/dt = p, dp/dt = F(q) the q slopes of RK4 (Eq. 3-5) are the p stage
+// values P_j = p + a_j h F_{j-1}, so every q quantity follows from p and the
+// forces (exact algebra; only the rounding differs from the stage-by-stage
+// form):
+//   Q2 = q + (h/2) p,   Q3 = Q2 + (h/2)^2 F1,   Q4 = q + h p + h (h/2) F2,
+//   q' = q + h p + (h^2/6)(F1 + F2 + F3),
+//   p' = p + (h/6)(F1 + 2 F2 + 2 F3 + F4),  F1 + 2F2 + 2F3 + F4 = 2(F1 + F2 + F3) + F4 - F1.
+// The P_j are never formed: 11 operations per site and step besides the four
+// forces, against 14 for the stage-by-stage form. Per site, between stages:
+//   Qo  the stage argument, overwritten with the next one (Qj: its old value)
+//   X   F2 (stage 2 to 3)
+//   s   F1 + F2 + F3 (stages 1 to 3)
+//   a   F1 (stages 1 to 4); after stage 4, F1 + 2F2 + 2F3 + F4
 // ---------------------------------------------------------------------------
 template <int STAGE, class R>
-__device__ __forceinline__ void site_update(R F, R Pj, R &Qo, R &Po, R qj, R pj, R &aq, R &ap,
+__device__ __forceinline__ void site_update(R F, R Qj, R &Qo, R &X, R qj, R pj, R &s, R &a,
                                             const StepConsts<R> &c) {
     if (STAGE == 1) {
-        // k1 = (p, F): its q part is p itself, folded into stage 2
-        ap = F;
-        Qo = fma_r(c.hh, Pj, qj);
-        Po = fma_r(c.hh, F, pj);
+        a = F;
+        s = F;
+        Qo = fma_r(c.hh, pj, qj);
     } else if (STAGE == 2) {
-        aq = fma_r(static_cast<R>(2), Pj, pj);
-        ap = fma_r(static_cast<R>(2), F, ap);
-        Qo = fma_r(c.hh, Pj, qj);
-        Po = fma_r(c.hh, F, pj);
+        Qo = fma_r(c.hh2, s, Qj);
+        X = F;
+        s = s + F;
     } else if (STAGE == 3) {
-        aq = fma_r(static_cast<R>(2), Pj, aq);
-        ap = fma_r(static_cast<R>(2), F, ap);
-        Qo = fma_r(c.h, Pj, qj);
-        Po = fma_r(c.h, F, pj);
+        Qo = fma_r(c.hhh, X, fma_r(c.h, pj, qj));
+        s = s + F;
     } else {
-        aq = aq + Pj;
-        ap = ap + F;
+        a = fma_r(static_cast<R>(2), s, F) - a;
+    }
+}
+
+// The end of the step for one site: q' = q + h p + (h^2/6) s, p' = p + (h/6) a
+// (s, a as left by stage 4). FP64 and plain FP32 round each operation. The
+// compensated FP32 forms keep the rounding of each update in the carry (FP32,
+// or FP64 with the increment formed in FP64), and take every step factor of
+// the increment in two FP32 parts (hi + lo): a factor rounded once to FP32
+// scales the same term of every step alike, an error the carry cannot undo.
+// For h that is a first-order error; for h^2/6 it is an energy drift of order
+// eps h^2 per step, which a split removes too (one more fused multiply-add).
+template <class R, bool KAHAN, class C>
+__device__ __forceinline__ void site_final(R &q, R &p, C &cq, C &cp, R s, R a,
+                                           const StepConsts<R> &c) {
+    if constexpr (!KAHAN) {
+        q = fma_r(c.h26, s, fma_r(c.h, p, q));
+        p = fma_r(c.h6, a, p);
+    } else if constexpr (sizeof(C) == 8) {
+        kahan_finish(q, cq, fma_r(c.h26d, static_cast<double>(s),
+                                  fma_r(c.hd, static_cast<double>(p), -cq)));
+        kahan_step(p, cp, a, c.h6d);
+    } else {
+        kahan_finish(q, cq, fma_r(c.h, p, fma_r(c.hlo, p, fma_r(c.h26, s, fma_r(c.h26lo, s, -cq)))));
+        kahan_step(p, cp, a, c.h6, c.h6lo);
     }
 }
 
 // ---------------------------------------------------------------------------
 // One RK4 stage over the S consecutive sites a lane holds.
-//   Q, P    stage argument (in), overwritten with the next stage argument
-//   q, p    state at the start of the step; after stage 4, the new state
-//   aq, ap  accumulators k1 + 2 k2 + 2 k3 (+ k4)
+//   Q       stage argument (in), overwritten with the next stage argument
+//   q, p    state at the start of the step
+//   X, s, a per-site values carried between stages (site_update)
 //   bl0     bond term left of site 0; brS bond term right of site S-1
-// Stage 1 reads its argument from q, p (Q, P are outputs only).
+// Stage 1 reads its argument from q (Q is an output only).
 // ---------------------------------------------------------------------------
 template <int M, int S, int STAGE, class R>
-__device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
-                                            R (&aq)[S], R (&ap)[S], R bl0, R brS,
+__device__ __forceinline__ void stage_sites(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
+                                            R (&s)[S], R (&a)[S], R bl0, R brS,
                                             const StepConsts<R> &c) {
     R bl = bl0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const R Qj = (STAGE == 1) ? q[j] : Q[j];
-        const R Pj = (STAGE == 1) ? p[j] : P[j];
         R br;
         if (j + 1 < S) {
             const R Qn = (STAGE == 1) ? q[j + 1] : Q[j + 1];
@@ -218,7 +269,7 @@ __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (
         }
         const R F = site_force<M, R>(bl, br, Qj);
         bl = br;
-        site_update<STAGE>(F, Pj, Q[j], P[j], q[j], p[j], aq[j], ap[j], c);
+        site_update<STAGE>(F, Qj, Q[j], X[j], q[j], p[j], s[j], a[j], c);
     }
 }
 
@@ -227,15 +278,14 @@ __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&P)[S], R (&q)[S], R (
 //   b1l0 = phi(Q_0 - Q_{-1}),  b2lm2 = phi(Q_0 - Q_{-2}),  b2lm1 = phi(Q_1 - Q_{-1}),
 //   b1rS = phi(Q_S - Q_{S-1}), b2rS2 = phi(Q_S - Q_{S-2}), b2rS1 = phi(Q_{S+1} - Q_{S-1}).
 template <int M, int S, int STAGE, class R>
-__device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&P)[S], R (&q)[S], R (&p)[S],
-                                                R (&aq)[S], R (&ap)[S], R b1l0, R b2lm2, R b2lm1,
+__device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
+                                                R (&s)[S], R (&a)[S], R b1l0, R b2lm2, R b2lm1,
                                                 R b1rS, R b2rS2, R b2rS1, const StepConsts<R> &c) {
     static_assert(S >= 2, "a lane holds at least two sites");
     R b1l = b1l0, b2l_lo = b2lm2, b2l_hi = b2lm1;  // phi of bonds (j-1, j), (j-2, j), (j-1, j+1)
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const R Qj = (STAGE == 1) ? q[j] : Q[j];
-        const R Pj = (STAGE == 1) ? p[j] : P[j];
         R b1r, b2r;
         if (j + 1 < S) b1r = ModelOps<M, R>::bond(((STAGE == 1) ? q[j + 1] : Q[j + 1]) - Qj);
         else b1r = b1rS;
@@ -245,48 +295,39 @@ __device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&P)[S], R (&q)[S],
         b1l = b1r;
         b2l_lo = b2l_hi;
         b2l_hi = b2r;
-        site_update<STAGE>(F, Pj, Q[j], P[j], q[j], p[j], aq[j], ap[j], c);
+        site_update<STAGE>(F, Qj, Q[j], X[j], q[j], p[j], s[j], a[j], c);
     }
 }
 
-// Final combination (Eq. 5) without compensation: y = y + (h/6) acc (FP64,
-// or plain FP32).
+// The end of the step (Eq. 5) for the S sites of a lane: without
+// compensation, and with the carries of the compensated FP32 forms.
 template <int S, class R>
-__device__ __forceinline__ void final_update(R (&q)[S], R (&p)[S], const R (&aq)[S],
-                                             const R (&ap)[S], const StepConsts<R> &c) {
+__device__ __forceinline__ void final_update(R (&q)[S], R (&p)[S], const R (&s)[S],
+                                             const R (&a)[S], const StepConsts<R> &c) {
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        q[j] = fma_r(c.h6, aq[j], q[j]);
-        p[j] = fma_r(c.h6, ap[j], p[j]);
+        R unused = 0;
+        site_final<R, false, R>(q[j], p[j], unused, unused, s[j], a[j], c);
     }
 }
 
-// Final combination for FP32 with the Kahan-compensated sum: the increment
-// (h/6) acc with h/6 from the FP64 step, in the carry's precision.
 template <int S, class C>
 __device__ __forceinline__ void final_update_kahan(float (&q)[S], float (&p)[S], C (&cq)[S],
-                                                   C (&cp)[S], const float (&aq)[S],
-                                                   const float (&ap)[S], const StepConsts<float> &c) {
+                                                   C (&cp)[S], const float (&s)[S],
+                                                   const float (&a)[S],
+                                                   const StepConsts<float> &c) {
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-        if constexpr (sizeof(C) == 8) {
-            kahan_step(q[j], cq[j], aq[j], c.h6d);
-            kahan_step(p[j], cp[j], ap[j], c.h6d);
-        } else {
-            kahan_step(q[j], cq[j], aq[j], c.h6, c.h6lo);
-            kahan_step(p[j], cp[j], ap[j], c.h6, c.h6lo);
-        }
-    }
+    for (int j = 0; j < S; ++j) site_final<float, true, C>(q[j], p[j], cq[j], cp[j], s[j], a[j], c);
 }
 
-// Same arithmetic for one site held alone (naive and resident kernels).
+// Same arithmetic for one site held alone (resident kernel).
 template <int M, int STAGE, class R>
-__device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R Pj, R qj, R pj, R &aq, R &ap,
-                                          R &Qn, R &Pn, const StepConsts<R> &c) {
+__device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R qj, R pj, R &X, R &s, R &a, R &Qn,
+                                          const StepConsts<R> &c) {
     const R bl = ModelOps<M, R>::bond(Qj - Qm);
     const R br = ModelOps<M, R>::bond(Qp - Qj);
     const R F = site_force<M, R>(bl, br, Qj);
-    site_update<STAGE>(F, Pj, Qn, Pn, qj, pj, aq, ap, c);
+    site_update<STAGE>(F, Qj, Qn, X, qj, pj, s, a, c);
 }
 
 // ---------------------------------------------------------------------------
