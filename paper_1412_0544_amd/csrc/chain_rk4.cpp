@@ -163,7 +163,7 @@ struct Layout {
     size_t cq, cp, back_cq, back_cp;  // FP32 state: carries (front and back)
     size_t naive[10];                 // naive: k1..k3 and two stage arguments
     size_t naive_z[5];                // naive, Roessler: the same for z
-    size_t naive_tab[2 * (kMaxStages - 1) + 4];  // naive tableau: slopes, two arguments
+    size_t naive_tab[(kMaxStages - 1) + 2];  // naive tableau: forces, two arguments
     size_t partials, result;          // energy
     size_t total;
 };
@@ -451,12 +451,9 @@ int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *
     if (d->method == CHAIN_NAIVE && d->scheme == CHAIN_SCHEME_TABLEAU) {
         NaiveTabBufs &b = h->naive_tab;
         int k = 0;
-        for (int m = 0; m < kMaxStages - 1; ++m) b.kq[m] = ws + L.naive_tab[k++];
         for (int m = 0; m < kMaxStages - 1; ++m) b.kp[m] = ws + L.naive_tab[k++];
         b.qa = ws + L.naive_tab[k++];
-        b.pa = ws + L.naive_tab[k++];
         b.qb = ws + L.naive_tab[k++];
-        b.pb = ws + L.naive_tab[k++];
     } else if (d->method == CHAIN_NAIVE) {
         void **slots[10] = {&h->naive.k1q, &h->naive.k1p, &h->naive.k2q, &h->naive.k2p,
                             &h->naive.k3q, &h->naive.k3p, &h->naive.yaq, &h->naive.yap,
@@ -568,6 +565,30 @@ int check_tableau(const chain_rk4_tableau *t, TabArgs *out) {
     return CHAIN_OK;
 }
 
+// The coefficients the kernels use (TabArgs), for step h, in FP64 and in a
+// fixed order: with P_m = p + h sum_l a_ml F_l the stage arguments are
+// Q_j = q + h sum_m a_jm P_m = q + h c_j p + h^2 sum_l (A^2)_jl F_l, and the
+// update q' = q + h sum_m b_m P_m = q + h (sum b) p + h^2 sum_l (b^T A)_l F_l.
+void derive_tableau(TabArgs &t, double h) {
+    const int s = t.stages;
+    t.hsb = 0.0;
+    for (int j = 0; j < kMaxStages; ++j) {
+        double c = 0.0, w = 0.0;
+        for (int m = 0; m < j; ++m) c += t.a[j][m];
+        for (int m = j + 1; m < s; ++m) w += t.b[m] * t.a[m][j];
+        t.hc[j] = j < s ? h * c : 0.0;
+        t.hb[j] = j < s ? h * t.b[j] : 0.0;
+        t.w[j] = j < s ? h * h * w : 0.0;
+        if (j < s) t.hsb += t.b[j];
+        for (int l = 0; l < kMaxStages; ++l) {
+            double g = 0.0;
+            for (int m = l + 1; m < j; ++m) g += t.a[j][m] * t.a[m][l];
+            t.g[j][l] = (j < s && l < s) ? h * h * g : 0.0;
+        }
+    }
+    t.hsb *= h;
+}
+
 }  // namespace
 
 int64_t chain_rk4_tableau_reach(int32_t model, const chain_rk4_tableau *t) {
@@ -597,6 +618,7 @@ int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t) {
         return fail(CHAIN_EINVAL, "the cluster is too small for this tableau's reach");
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
+    derive_tableau(a, h->d.dt);
     h->tableau = a;
     h->plan = P;
     h->has_tableau = true;

@@ -68,6 +68,15 @@ struct TabArgs {
     int32_t stages, pad;
     double a[kMaxStages][kMaxStages];
     double b[kMaxStages];
+    // What the kernels use, derived in FP64 for the handle's step h (for
+    // dq/dt = p the q stage arguments and the q update follow from p and the
+    // forces): Q_j = q + hc_j p + sum_l g_jl F_l, p' = p + sum_m hb_m F_m,
+    // q' = q + hsb p + sum_l w_l F_l.
+    double hc[kMaxStages];             // h c_j, c_j = sum_m a_jm
+    double g[kMaxStages][kMaxStages];  // h^2 (A^2)_jl (zero for l >= j - 1)
+    double hb[kMaxStages];             // h b_m
+    double w[kMaxStages];              // h^2 (b^T A)_l (zero for the last stage)
+    double hsb;                        // h sum_m b_m
 };
 // Cluster shapes the tableau kernel is built for: sites per lane 4 or 8 with
 // up to 4 stages, 4 with up to 8; wavefronts per cluster 1 or 4.
@@ -75,13 +84,12 @@ hipError_t launch_tableau(int model, int prec, int sites_per_lane, int waves_per
                           const FusedPass &a, const TabArgs &t, hipStream_t s);
 
 // The per-stage implementation of a tableau method (Sec. 2.2 with general
-// coefficients): kernel j evaluates the slope k_j at its stage argument and
+// coefficients): kernel j evaluates the force F_j at its stage argument and
 // forms the next argument (or, for the last stage, the new state in place).
-// Slopes k_m of stages m < s-1 go through memory; the q part of k_0 is p.
+// The forces of stages m < s-1 go through memory.
 struct NaiveTabBufs {
-    void *kq[kMaxStages - 1];  // P_m, m = 1..s-2 (entry 0 unused)
     void *kp[kMaxStages - 1];  // F(Q_m), m = 0..s-2
-    void *qa, *pa, *qb, *pb;   // stage arguments (ping-pong)
+    void *qa, *qb;             // stage arguments (ping-pong)
 };
 hipError_t launch_naive_tableau_step(int model, int prec, StateRef y, const NaiveTabBufs &b,
                                      int64_t n, double dt, const TabArgs &t, hipStream_t s);

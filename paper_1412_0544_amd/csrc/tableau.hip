@@ -3,12 +3,16 @@
 // Sec. 2 notes the cluster technique carries over to every explicit scheme).
 //
 // The cluster, the loads, the stores and the lane exchange are those of the
-// classical-RK4 kernel; only the stage arithmetic differs. Every stage keeps
-// its slope k_j = (P_j, F(Q_j)) in registers, so the stage argument
-//   (Q_j, P_j) = (q, p) + dt * sum_{m<j} a[j][m] k_m
-// and the final combination (q, p) + dt * sum_m b[m] k_m can use any
-// coefficients. The tableau arrives as a kernel argument; SMAX (4 or 8) bounds
-// the stage count at compile time so the slopes stay in registers.
+// classical-RK4 kernel; only the stage arithmetic differs. For dq/dt = p,
+// dp/dt = F(q) the q slopes are the p stage values P_m = p + h sum_l a_ml F_l,
+// so (exact algebra on Eq. 3-5 with general coefficients)
+//   Q_j = q + h c_j p + h^2 sum_l (A^2)_jl F_l,        c_j = sum_m a_jm,
+//   q'  = q + h (sum_m b_m) p + h^2 sum_l (b^T A)_l F_l,
+//   p'  = p + h sum_m b_m F_m,
+// and only the forces F_l of the stages are kept (in registers). (A^2)_jl is
+// zero for l >= j - 1 and (b^T A)_l for the last stage, so those terms are not
+// formed. The host derives the coefficients, scaled by the step, in FP64 (TabArgs);
+// SMAX (4 or 8) bounds the stage count at compile time.
 #include "cluster.hpp"
 
 namespace chainrk4 {
@@ -85,6 +89,27 @@ __device__ __forceinline__ void lane_force(const R (&Q)[S], R (&F)[S], SlotsOf<M
 
 constexpr int tab_block_threads(int W) { return W == 1 ? kFusedThreads : 64 * W; }
 
+// A coefficient as two parts in the working precision: hi = R(x), lo = R(x - hi).
+// For FP64 the second part is not used.
+template <class R>
+struct Coef {
+    R hi, lo;
+    __device__ __forceinline__ explicit Coef(double x)
+        : hi(static_cast<R>(x)), lo(static_cast<R>(x - static_cast<double>(static_cast<R>(x)))) {}
+};
+
+// acc += x * F. FP64 rounds once; the compensated FP32 form takes x in two
+// parts, since a coefficient rounded once to FP32 would scale the same term
+// of every step alike (an error the carry of the update cannot undo).
+template <class R, bool KAHAN>
+__device__ __forceinline__ R coef_fma(const Coef<R> &x, R F, R acc, bool first) {
+    if constexpr (KAHAN) {
+        return first ? fma_r(x.hi, F, x.lo * F) : fma_r(x.hi, F, fma_r(x.lo, F, acc));
+    } else {
+        return first ? x.hi * F : fma_r(x.hi, F, acc);
+    }
+}
+
 template <int M, class R, bool KAHAN, int S, int W, int SMAX>
 __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass a, TabArgs t) {
     constexpr int WPB = tab_block_threads(W) / 64;
@@ -101,51 +126,46 @@ __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass
     const int64_t s0 = e0 + lo;
     LaneState<R, KAHAN, S> st;
     load_lane<R, KAHAN, S>(st, a.in, a.n, s0, e0 >= 0 && e0 + E <= a.n);
-    const R dt = static_cast<R>(a.dt);
-    const R dtlo = static_cast<R>(a.dt - static_cast<double>(dt));  // dt - R(dt)
     const int s = t.stages;
-    // kq[m] holds P_m (the q part of k_m) for m >= 1; the q part of k_0 is p
-    R kq[SMAX][S], kp[SMAX][S], Q[S], fq[S], fp[S];
+    R F[SMAX][S], Q[S], fq[S], fp[S];
     int parity = 0;
     for (int k = 0; k < a.ksteps; ++k) {
 #pragma unroll
         for (int j = 0; j < SMAX; ++j) {
             if (j >= s) break;  // uniform: the stage count is a kernel argument
             if (j == 0) {
-                lane_force<M, S, W, WPB>(st.q, kp[0], &slots, lane, wib, wic, parity);
+                lane_force<M, S, W, WPB>(st.q, F[0], &slots, lane, wib, wic, parity);
             } else {
+                const R hc = static_cast<R>(t.hc[j]);
 #pragma unroll
                 for (int i = 0; i < S; ++i) {
-                    R sq = static_cast<R>(0), sp = static_cast<R>(0);
+                    R x = fma_r(hc, st.p[i], st.q[i]);
 #pragma unroll
-                    for (int m = 0; m < j; ++m) {
-                        const R c = static_cast<R>(t.a[j][m]);
-                        sq = fma_r(c, m == 0 ? st.p[i] : kq[m][i], sq);
-                        sp = fma_r(c, kp[m][i], sp);
-                    }
-                    Q[i] = fma_r(dt, sq, st.q[i]);
-                    kq[j][i] = fma_r(dt, sp, st.p[i]);
+                    for (int l = 0; l + 1 < j; ++l) x = fma_r(static_cast<R>(t.g[j][l]), F[l][i], x);
+                    Q[i] = x;
                 }
-                lane_force<M, S, W, WPB>(Q, kp[j], &slots, lane, wib, wic, parity);
+                lane_force<M, S, W, WPB>(Q, F[j], &slots, lane, wib, wic, parity);
             }
             parity ^= 1;
             // the final combination, accumulated stage by stage in stage order
-            const R bj = static_cast<R>(t.b[j]);
+            // (w of the last stage is zero, which adds nothing: no branch)
+            const Coef<R> hb(t.hb[j]), w(t.w[j]);
 #pragma unroll
             for (int i = 0; i < S; ++i) {
-                const R kqj = j == 0 ? st.p[i] : kq[j][i];
-                fq[i] = j == 0 ? bj * kqj : fma_r(bj, kqj, fq[i]);
-                fp[i] = j == 0 ? bj * kp[0][i] : fma_r(bj, kp[j][i], fp[i]);
+                fp[i] = coef_fma<R, KAHAN>(hb, F[j][i], fp[i], j == 0);
+                fq[i] = coef_fma<R, KAHAN>(w, F[j][i], fq[i], j == 0);
             }
         }
+        const Coef<R> hsb(t.hsb);
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             if constexpr (KAHAN) {
-                kahan_step(st.q[i], st.cq[i], fq[i], dt, dtlo);
-                kahan_step(st.p[i], st.cp[i], fp[i], dt, dtlo);
+                kahan_finish(st.q[i], st.cq[i],
+                             fma_r(hsb.hi, st.p[i], fma_r(hsb.lo, st.p[i], fq[i] - st.cq[i])));
+                kahan_finish(st.p[i], st.cp[i], fp[i] - st.cp[i]);
             } else {
-                st.q[i] = fma_r(dt, fq[i], st.q[i]);
-                st.p[i] = fma_r(dt, fp[i], st.p[i]);
+                st.q[i] = fma_r(hsb.hi, st.p[i], st.q[i]) + fq[i];
+                st.p[i] = st.p[i] + fp[i];
             }
         }
     }
@@ -189,73 +209,62 @@ hipError_t tab_dispatch_prec(int prec, int s, int w, const FusedPass &a, const T
 
 constexpr int kNaiveTabThreads = 256;
 
-// Stage j of the per-stage implementation at site i: the slope k_j at the
-// stage argument (Qj from `arg`, with its neighbours; Pj), then the next stage
-// argument, or the final combination in place. Same per-site operation order
-// as tableau_kernel, so both give identical bits.
+// Stage j of the per-stage implementation at site i: the force F_j at the
+// stage argument (from `arg`, with its neighbours), kept in memory for the
+// later stages, then the next stage argument, or the final combination in
+// place. Same per-site operation order as tableau_kernel, so both give
+// identical bits.
 template <int M, class R, bool KAHAN>
 __global__ __launch_bounds__(kNaiveTabThreads) void naive_tab_stage(StateRef y, NaiveTabBufs b,
-                                                                    const R *argq, const R *argp,
-                                                                    R *nextq, R *nextp, int j,
-                                                                    int64_t n, double dt_,
-                                                                    TabArgs t) {
+                                                                    const R *arg, R *next, int j,
+                                                                    int64_t n, TabArgs t) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kNaiveTabThreads + threadIdx.x;
     if (i >= n) return;
     using Ops = ModelOps<M, R>;
-    const R dt = static_cast<R>(dt_);
-    const R dtlo = static_cast<R>(dt_ - static_cast<double>(dt));  // dt - R(dt)
     R *yq = static_cast<R *>(y.q);
     R *yp = static_cast<R *>(y.p);
-    const R Qj = argq[i];
-    const R Pj = argp[i];
-    R F;
+    const R Qj = arg[i];
+    R Fj;
     if constexpr (coupling_range<M>() == 2) {
-        F = site_force2<M, R>(Ops::bond(Qj - argq[wrap_index(i - 1, n)]),
-                              Ops::bond(argq[wrap_index(i + 1, n)] - Qj),
-                              Ops::bond(Qj - argq[wrap_index(i - 2, n)]),
-                              Ops::bond(argq[wrap_index(i + 2, n)] - Qj), Qj);
+        Fj = site_force2<M, R>(Ops::bond(Qj - arg[wrap_index(i - 1, n)]),
+                               Ops::bond(arg[wrap_index(i + 1, n)] - Qj),
+                               Ops::bond(Qj - arg[wrap_index(i - 2, n)]),
+                               Ops::bond(arg[wrap_index(i + 2, n)] - Qj), Qj);
     } else {
-        F = site_force<M, R>(Ops::bond(Qj - argq[wrap_index(i - 1, n)]),
-                             Ops::bond(argq[wrap_index(i + 1, n)] - Qj), Qj);
+        Fj = site_force<M, R>(Ops::bond(Qj - arg[wrap_index(i - 1, n)]),
+                              Ops::bond(arg[wrap_index(i + 1, n)] - Qj), Qj);
     }
     const R qi = yq[i], pi = yp[i];
-    // slope m at this site: (P_m, F_m); stage j's comes from registers
-    auto kqm = [&](int m) -> R {
-        return m == j ? Pj : (m == 0 ? pi : static_cast<const R *>(b.kq[m])[i]);
-    };
-    auto kpm = [&](int m) -> R { return m == j ? F : static_cast<const R *>(b.kp[m])[i]; };
-    if (j + 1 < t.stages) {
-        if (j > 0) static_cast<R *>(b.kq[j])[i] = Pj;
-        static_cast<R *>(b.kp[j])[i] = F;
-        R sq = static_cast<R>(0), sp = static_cast<R>(0);
-        for (int m = 0; m <= j; ++m) {
-            const R c = static_cast<R>(t.a[j + 1][m]);
-            sq = fma_r(c, kqm(m), sq);
-            sp = fma_r(c, kpm(m), sp);
-        }
-        nextq[i] = fma_r(dt, sq, qi);
-        nextp[i] = fma_r(dt, sp, pi);
+    // force of stage m at this site; stage j's comes from registers
+    auto Fm = [&](int m) -> R { return m == j ? Fj : static_cast<const R *>(b.kp[m])[i]; };
+    const int s = t.stages;
+    if (j + 1 < s) {
+        static_cast<R *>(b.kp[j])[i] = Fj;
+        R x = fma_r(static_cast<R>(t.hc[j + 1]), pi, qi);
+        for (int l = 0; l < j; ++l) x = fma_r(static_cast<R>(t.g[j + 1][l]), Fm(l), x);
+        next[i] = x;
     } else {
-        R fq = static_cast<R>(t.b[0]) * kqm(0);
-        R fp = static_cast<R>(t.b[0]) * kpm(0);
-        for (int m = 1; m < t.stages; ++m) {
-            const R c = static_cast<R>(t.b[m]);
-            fq = fma_r(c, kqm(m), fq);
-            fp = fma_r(c, kpm(m), fp);
+        R fq = static_cast<R>(0), fp = static_cast<R>(0);
+        for (int m = 0; m < s; ++m) {
+            const Coef<R> hb(t.hb[m]), w(t.w[m]);
+            const R f = Fm(m);
+            fp = coef_fma<R, KAHAN>(hb, f, fp, m == 0);
+            fq = coef_fma<R, KAHAN>(w, f, fq, m == 0);
         }
+        const Coef<R> hsb(t.hsb);
         if constexpr (KAHAN) {
             R q1 = qi, p1 = pi;
             float *ycq = static_cast<float *>(y.cq), *ycp = static_cast<float *>(y.cp);
             float cq = ycq[i], cp = ycp[i];
-            kahan_step(q1, cq, fq, dt, dtlo);
-            kahan_step(p1, cp, fp, dt, dtlo);
+            kahan_finish(q1, cq, fma_r(hsb.hi, pi, fma_r(hsb.lo, pi, fq - cq)));
+            kahan_finish(p1, cp, fp - cp);
             yq[i] = q1;
             yp[i] = p1;
             ycq[i] = cq;
             ycp[i] = cp;
         } else {
-            yq[i] = fma_r(dt, fq, qi);
-            yp[i] = fma_r(dt, fp, pi);
+            yq[i] = fma_r(hsb.hi, pi, qi) + fq;
+            yp[i] = pi + fp;
         }
     }
 }
@@ -266,20 +275,18 @@ hipError_t naive_tab_dispatch(StateRef y, const NaiveTabBufs &b, int64_t n, doub
     const int64_t blocks = (n + kNaiveTabThreads - 1) / kNaiveTabThreads;
     if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>(blocks)), block(kNaiveTabThreads);
-    const R *aq = static_cast<const R *>(y.q), *ap = static_cast<const R *>(y.p);
+    const R *arg = static_cast<const R *>(y.q);
     if (t.stages == 1) {
         // the only stage would read neighbours of q while writing q: read a copy
         hipError_t e = hipMemcpyAsync(b.qa, y.q, n * sizeof(R), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
-        aq = static_cast<const R *>(b.qa);
+        arg = static_cast<const R *>(b.qa);
     }
     for (int j = 0; j < t.stages; ++j) {
-        R *nq = static_cast<R *>(j % 2 == 0 ? b.qa : b.qb);
-        R *np = static_cast<R *>(j % 2 == 0 ? b.pa : b.pb);
-        if (t.stages == 1) nq = np = nullptr;
-        naive_tab_stage<M, R, KAHAN><<<grid, block, 0, st>>>(y, b, aq, ap, nq, np, j, n, dt, t);
-        aq = nq;
-        ap = np;
+        R *next = static_cast<R *>(j % 2 == 0 ? b.qa : b.qb);
+        if (t.stages == 1) next = nullptr;
+        naive_tab_stage<M, R, KAHAN><<<grid, block, 0, st>>>(y, b, arg, next, j, n, t);
+        arg = next;
     }
     return hipGetLastError();
 }

@@ -41,8 +41,8 @@ def test_workspace_bytes():
     assert f(desc(n=1 << 20, prec=1)) >= 6 * 4 * (1 << 20)
     assert f(desc(n=1 << 20, method=1)) >= 10 * 8 * (1 << 20)
     assert f(desc(n=4096, flags=4)) > 0                            # resident ring
-    # per-stage tableau method: 7 + 7 slope arrays and two stage arguments
-    assert f(desc(n=1 << 20, method=1, scheme=1)) >= 18 * 8 * (1 << 20)
+    # per-stage tableau method: 7 force arrays and two stage arguments
+    assert f(desc(n=1 << 20, method=1, scheme=1)) >= 9 * 8 * (1 << 20)
     for bad in (desc(n=0), desc(model=7), desc(prec=4), desc(prec=-1), desc(dt=float("nan")),
                 desc(dt=float("inf")), desc(method=5), desc(sites_per_lane=5),
                 desc(kdepth=33), desc(kdepth=-1), desc(sites_per_lane=2, model=2), desc(sites_per_lane=1), desc(model=5), desc(model=2, prec=1), desc(flags=64), desc(waves_per_cluster=3),
