@@ -268,7 +268,7 @@ def main(argv=None):
         print(json.dumps({"metric": "site-updates/sec, second-neighbour bonds",
                           "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
                           "dtype": "f64", "config": {"workload": "quartic NNN chain N=2^24, dt=0.01"},
-                          "quartic_nnn": variant_nnn(qd, pd, dt, n, dev)}), flush=True)
+                          "quartic_nnn": variant_nnn(qd, pd, dt, n, dev, sweep=args.sweep)}), flush=True)
         return 0
     if args.tableaus:
         print(json.dumps({"metric": "site-updates/sec by explicit RK method",
@@ -652,12 +652,29 @@ def variant_short_rings(dt, dev, steps=1000, jobs=5):
     return out
 
 
-def variant_nnn(qd, pd, dt, n, dev, steps=480):
+def variant_nnn(qd, pd, dt, n, dev, steps=480, sweep=False):
     """The quartic chain with second-neighbour bonds on the bench chain: the
     library plan (halo 4 per step) and the per-stage baseline, device time of
-    `steps` steps (best of 3)."""
+    `steps` steps (best of 3); with `sweep`, every cluster shape at depths 8,
+    12 and 16 (device time of 96 steps)."""
     from paper_1412_0544_amd import Chain
     out = {}
+    if sweep:
+        table = {}
+        for s_ in (2, 4, 8):
+            for w in (1, 2, 4, 8):
+                for k in (8, 12, 16):
+                    if 64 * s_ * w <= 16 * k:
+                        continue
+                    ch = Chain(qd, pd, dt, model="quartic_nnn", sites_per_lane=s_,
+                               waves_per_cluster=w, kdepth=k, device=dev)
+                    ch.step(k)
+                    best = min(ev_seconds(lambda: ch.step(96), ch.stream) for _ in range(3))
+                    ch.close()
+                    table[f"s{s_}_w{w}_k{k}"] = n * 96 / best
+        out["shapes_su_per_s"] = table
+        out["best_shape"] = max(table, key=table.get)
+        log(f"[bench] NNN shapes: best {out['best_shape']} {table[out['best_shape']]:.3e} SU/s")
     for method in ("fused", "naive"):
         ch = Chain(qd, pd, dt, model="quartic_nnn", method=method, device=dev)
         ch.step(32)
