@@ -127,7 +127,7 @@ def tune(n: int, model: str = "quartic", prec: str = "fp64", dt: float = 0.01,
     return best, table
 
 
-BATCH_CANDIDATES = ((4, 16), (4, 32), (8, 16), (8, 32))
+BATCH_CANDIDATES = ((4, 16), (4, 24), (4, 32), (8, 16), (8, 24), (8, 32))
 
 
 def _snapshot(chains):

@@ -42,6 +42,24 @@ __device__ __forceinline__ long long uniform64(long long x) {
     return static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
+// The same for a pointer, a double and a chain's state pointers. The chain
+// table is read with ordinary loads (the kernel writes global memory, so the
+// compiler cannot prove them uniform); moving what every lane holds alike to
+// scalar registers keeps it out of the vector registers of the cluster pass.
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+    return reinterpret_cast<T *>(uniform64(reinterpret_cast<long long>(p)));
+}
+
+__device__ __forceinline__ double uniform_f64(double x) {
+    return __builtin_bit_cast(double, uniform64(__builtin_bit_cast(long long, x)));
+}
+
+__device__ __forceinline__ StateRef uniform_ref(const StateRef &r) {
+    return StateRef{uniform_ptr(r.q), uniform_ptr(r.p), uniform_ptr(r.cq), uniform_ptr(r.cp),
+                    uniform_ptr(r.z)};
+}
+
 __device__ __forceinline__ int pass_steps(const BatchChain &ch, int e, int depth) {
     if (e < ch.nhead) return e == 0 ? ch.head0 : ch.head1;
     if (ch.tail > 0 && e == ch.passes - 1) return ch.tail;
@@ -105,13 +123,14 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
             __syncthreads();
             if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        const int64_t start = 4 * (static_cast<int64_t>(g) * ch.uq + (g < ch.ur ? g : ch.ur));
-        const int64_t keep = (g == G - 1) ? ch.n - start : 4 * (ch.uq + (g < ch.ur ? 1 : 0));
-        const StateRef &in = (pass & 1) ? ch.back : ch.front;
-        const StateRef &out = (pass & 1) ? ch.front : ch.back;
-        run_cluster<M, R, KAHAN, S, W, WPB, COH>(in, out, ch.n, start - a.halo, a.halo, keep,
-                                                 pass_steps(ch, pass, a.depth), ch.dt, &slots, lane,
-                                                 wib, wib);
+        const int64_t n = uniform64(ch.n), uq = uniform64(ch.uq), ur = uniform64(ch.ur);
+        const int64_t start = 4 * (static_cast<int64_t>(g) * uq + (g < ur ? g : ur));
+        const int64_t keep = (g == G - 1) ? n - start : 4 * (uq + (g < ur ? 1 : 0));
+        const StateRef in = uniform_ref((pass & 1) ? ch.back : ch.front);
+        const StateRef out = uniform_ref((pass & 1) ? ch.front : ch.back);
+        const int ksteps = __builtin_amdgcn_readfirstlane(pass_steps(ch, pass, a.depth));
+        run_cluster<M, R, KAHAN, S, W, WPB, COH>(in, out, n, start - a.halo, a.halo, keep, ksteps,
+                                                 uniform_f64(ch.dt), &slots, lane, wib, wib);
         static_assert(E >= 64, "cluster");
         if constexpr (COH)
             drain_memory();
