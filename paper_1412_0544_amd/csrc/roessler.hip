@@ -10,28 +10,42 @@ namespace {
 
 constexpr int roessler_block_threads(int W) { return W == 1 ? kFusedThreads : 64 * W; }
 
-// One stage of the Roessler chain for the S sites of this lane; the x edge
-// values are exchanged like the coordinates of the Hamiltonian chains.
-template <int S, int STAGE, int W, int WPB>
+// Edge x values of every lane of a block, double-buffered by stage parity.
+template <int NL>
+struct LaneEdges {
+    double first[2][NL], last[2][NL];
+};
+
+// One stage of the Roessler chain for the S sites of this lane. Only x
+// crosses lanes. A one-wavefront cluster moves the edge values by DPP. A
+// cluster of several wavefronts has every lane publish its first and last x
+// in LDS and read its neighbours' after one barrier: no lane-dependent
+// branches, which holds the kernel to 92 VGPRs (5 wavefronts per SIMD)
+// instead of 117 with DPP plus two LDS slots per wavefront. The bond term
+// x_{i} - x_{i-1} across two lanes is the same operation on the same values
+// in both lanes, so the result does not depend on the route.
+template <int S, int STAGE, int W, int NL>
 __device__ __forceinline__ void roessler_lane_stage(double (&X)[S], double (&Y)[S], double (&Z)[S],
                                                     double (&x)[S], double (&y)[S], double (&z)[S],
                                                     double (&ax)[S], double (&ay)[S],
                                                     double (&az)[S], const StepConsts<double> &c,
-                                                    EdgeSlots<double, WPB> *slots, int lane, int wib,
-                                                    int wic, int parity) {
+                                                    LaneEdges<NL> *edges, int gl, int parity) {
     const double first = (STAGE == 1) ? x[0] : X[0];
     const double last = (STAGE == 1) ? x[S - 1] : X[S - 1];
-    double right = from_right(first);
+    double brS, bl0;
     if constexpr (W > 1) {
-        if (lane == 0) slots->first[parity][wib] = first;
-        if (lane == 63) slots->last[parity][wib] = last;
+        edges->first[parity][gl] = first;
+        edges->last[parity][gl] = last;
         __syncthreads();
-        if (lane == 63 && wic + 1 < W) right = slots->first[parity][wib + 1];
-    }
-    const double brS = right - last;
-    double bl0 = from_left(brS);
-    if constexpr (W > 1) {
-        if (lane == 0 && wic > 0) bl0 = first - slots->last[parity][wib - 1];
+        // the cluster's outermost lanes read a clamped or foreign value: their
+        // sites lie in the recomputed halo
+        const double right = edges->first[parity][gl + 1 < NL ? gl + 1 : gl];
+        const double left = edges->last[parity][gl > 0 ? gl - 1 : gl];
+        brS = right - last;
+        bl0 = first - left;
+    } else {
+        brS = from_right(first) - last;
+        bl0 = from_left(brS);
     }
     roessler_stage_sites<S, STAGE>(X, Y, Z, x, y, z, ax, ay, az, bl0, brS, c);
 }
@@ -65,7 +79,8 @@ __global__ __launch_bounds__(roessler_block_threads(W)) void roessler_fused_kern
     const int wib = threadIdx.x >> 6;
     const int wic = wib % W;
     const int64_t cluster = static_cast<int64_t>(blockIdx.x) * CPB + wib / W;
-    __shared__ EdgeSlots<double, WPB> slots;
+    constexpr int NL = W > 1 ? WPB * 64 : 1;
+    __shared__ LaneEdges<NL> edges;
     if (cluster >= a.waves) return;  // W = 1 only (a W > 1 grid has no extra blocks)
     const int64_t e0 = cluster * a.tile - a.halo;
     const int lo = (wic * 64 + lane) * S;
@@ -75,10 +90,10 @@ __global__ __launch_bounds__(roessler_block_threads(W)) void roessler_fused_kern
     const StepConsts<double> c(a.dt);
     double X[S], Y[S], Z[S], ax[S], ay[S], az[S];
     for (int k = 0; k < a.ksteps; ++k) {
-        roessler_lane_stage<S, 1, W, WPB>(X, Y, Z, x, y, z, ax, ay, az, c, &slots, lane, wib, wic, 0);
-        roessler_lane_stage<S, 2, W, WPB>(X, Y, Z, x, y, z, ax, ay, az, c, &slots, lane, wib, wic, 1);
-        roessler_lane_stage<S, 3, W, WPB>(X, Y, Z, x, y, z, ax, ay, az, c, &slots, lane, wib, wic, 0);
-        roessler_lane_stage<S, 4, W, WPB>(X, Y, Z, x, y, z, ax, ay, az, c, &slots, lane, wib, wic, 1);
+        roessler_lane_stage<S, 1, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 0);
+        roessler_lane_stage<S, 2, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 1);
+        roessler_lane_stage<S, 3, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 0);
+        roessler_lane_stage<S, 4, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 1);
     }
     double *xo = static_cast<double *>(a.out.q);
     double *yo = static_cast<double *>(a.out.p);
