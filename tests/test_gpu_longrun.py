@@ -111,7 +111,7 @@ def test_fp32_kahan_energy_drift_bound():
 def test_fp32_energy_drift_matches_fp64_at_a_step_exact_in_fp32():
     """At dt = 2^-7 the FP32 stages advance by exactly the step of the final
     combination, so over 10^4 steps the systematic RK4 energy drift of both
-    FP32 variants is the FP64 one (measured within 11% at N = 2^24). At a
+    FP32 variants is the FP64 one (measured within 6% at N = 2^24). At a
     step FP32 cannot hold (0.01), the stage step is off by a relative 2e-8,
     an error of order eps*h^2 per step in the energy that opposes the RK4
     drift; this test does not use such a step."""
