@@ -164,11 +164,15 @@ int check_desc(const chain_rk4_desc *d) {
     return CHAIN_OK;
 }
 
+// Arrays of N values the per-stage method of the Hamiltonian chains keeps.
+constexpr int kNaiveArraysHamiltonian = 5;
+
 // Workspace regions, in order. Unused regions have size 0.
 struct Layout {
     size_t back_q, back_p, back_z;    // fused: back buffer of the ping-pong
     size_t cq, cp, back_cq, back_cp;  // FP32 state: carries (front and back)
-    size_t naive[10];                 // naive: k1..k3 and two stage arguments
+    size_t naive[10];                 // naive: k1..k3 and two stage arguments (Roessler;
+                                      // the Hamiltonian chains take the first 5)
     size_t naive_z[5];                // naive, Roessler: the same for z
     size_t naive_tab[(kMaxStages - 1) + 2];  // naive tableau: forces, two arguments
     size_t partials, result;          // energy
@@ -204,7 +208,7 @@ Layout layout(const chain_rk4_desc *d) {
     if (d->method == CHAIN_NAIVE && d->scheme == CHAIN_SCHEME_TABLEAU) {
         for (size_t &o : L.naive_tab) o = take(arr);
     } else if (d->method == CHAIN_NAIVE) {
-        for (int i = 0; i < 10; ++i) L.naive[i] = take(arr);
+        for (int i = 0; i < (three ? 10 : kNaiveArraysHamiltonian); ++i) L.naive[i] = take(arr);
         if (three)
             for (int i = 0; i < 5; ++i) L.naive_z[i] = take(arr);
     }
@@ -463,16 +467,20 @@ int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *
         for (int m = 0; m < kMaxStages - 1; ++m) b.kp[m] = ws + L.naive_tab[k++];
         b.qa = ws + L.naive_tab[k++];
         b.qb = ws + L.naive_tab[k++];
+    } else if (d->method == CHAIN_NAIVE && !three) {
+        // the per-stage kernels of the Hamiltonian chains: Q2/Q4, Q3, F1, F2
+        // and the running force sum
+        void **slots[kNaiveArraysHamiltonian] = {&h->naive.yaq, &h->naive.ybq, &h->naive.k1p,
+                                                 &h->naive.k2p, &h->naive.k2q};
+        for (int i = 0; i < kNaiveArraysHamiltonian; ++i) *slots[i] = ws + L.naive[i];
     } else if (d->method == CHAIN_NAIVE) {
         void **slots[10] = {&h->naive.k1q, &h->naive.k1p, &h->naive.k2q, &h->naive.k2p,
                             &h->naive.k3q, &h->naive.k3p, &h->naive.yaq, &h->naive.yap,
                             &h->naive.ybq, &h->naive.ybp};
         for (int i = 0; i < 10; ++i) *slots[i] = ws + L.naive[i];
-        if (three) {
-            double **zs[5] = {&h->naive.k1z, &h->naive.k2z, &h->naive.k3z, &h->naive.yaz,
-                              &h->naive.ybz};
-            for (int i = 0; i < 5; ++i) *zs[i] = reinterpret_cast<double *>(ws + L.naive_z[i]);
-        }
+        double **zs[5] = {&h->naive.k1z, &h->naive.k2z, &h->naive.k3z, &h->naive.yaz,
+                          &h->naive.ybz};
+        for (int i = 0; i < 5; ++i) *zs[i] = reinterpret_cast<double *>(ws + L.naive_z[i]);
     }
     h->partials = reinterpret_cast<double *>(ws + L.partials);
     h->result = reinterpret_cast<double *>(ws + L.result);

@@ -40,7 +40,10 @@ struct ResidentRun {
     int64_t nsteps;
 };
 
-// Naive method: one kernel per RK stage over memory.
+// Naive method: one kernel per RK stage over memory. The Roessler chain uses
+// every array (slopes k1..k3 and the ping-pong stage arguments of x, y, z);
+// the Hamiltonian chains use yaq (Q2, then Q4), ybq (Q3), k1p (F1), k2p (F2)
+// and k2q (the running sum of the forces).
 struct NaiveBufs {
     void *k1q, *k1p, *k2q, *k2p, *k3q, *k3p;  // stage slopes
     void *yaq, *yap, *ybq, *ybp;              // stage arguments (ping-pong)

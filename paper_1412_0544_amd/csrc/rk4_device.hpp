@@ -118,14 +118,9 @@ struct StepConsts {
           h26d(dt * dt / 6.0) {}
 };
 
-// Kahan-compensated y += (hi + lo) * acc with carry c (the true value is
-// y - c). The step factor comes in two FP32 parts (hi + lo = h exactly to
-// about 48 bits), so the increment carries no systematic FP32 rounding of h:
-// a factor rounded once to FP32 scales every step's increment by the same
-// (1 + eps), a first-order error that the carry cannot undo. Two fused
-// multiply-adds form v = (hi + lo) acc - c with one final rounding, the same
-// instruction count as a product and a difference.
-// Add v = increment - c to y and keep the new rounding error in c.
+// Kahan-compensated update of y with carry c (the true value is y - c): the
+// caller forms v = increment - c; kahan_finish adds it to y and keeps the new
+// rounding error in c.
 __device__ __forceinline__ void kahan_finish(float &y, float &c, float v) {
     const float t = y + v;
     c = (t - y) - v;
@@ -141,10 +136,17 @@ __device__ __forceinline__ void kahan_finish(float &y, double &c, double v) {
     y = t;
 }
 
+// y += (hi + lo) acc, compensated. The step factor comes in two FP32 parts
+// (hi + lo = h to about 48 bits), so the increment carries no systematic FP32
+// rounding of h: a factor rounded once to FP32 scales every step's increment
+// by the same (1 + eps), a first-order error that the carry cannot undo. Two
+// fused multiply-adds form v = (hi + lo) acc - c with one final rounding, the
+// same instruction count as a product and a difference.
 __device__ __forceinline__ void kahan_step(float &y, float &c, float acc, float hi, float lo) {
     kahan_finish(y, c, __builtin_fmaf(hi, acc, __builtin_fmaf(lo, acc, -c)));
 }
 
+// The same with an FP64 carry: the increment h acc is formed in FP64.
 __device__ __forceinline__ void kahan_step(float &y, double &c, float acc, double h) {
     kahan_finish(y, c, h * static_cast<double>(acc) - c);
 }
