@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -45,14 +46,17 @@ bool has_carries(int prec) { return prec == CHAIN_FP32_KAHAN || prec == CHAIN_FP
 size_t carry_bytes(int prec) { return prec == CHAIN_FP32_KAHAN64 ? sizeof(double) : sizeof(float); }
 
 bool is_gfx950(int dev) {
-    static int cached[64];  // 0 unknown, 1 yes, 2 no
+    // 0 unknown, 1 yes, 2 no; handles on different threads may ask at once
+    static std::atomic<int> cached[64];
     if (dev < 0 || dev >= 64) return false;
-    if (cached[dev] == 0) {
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
-        cached[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+        v = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+        cached[dev].store(v, std::memory_order_relaxed);
     }
-    return cached[dev] == 1;
+    return v == 1;
 }
 
 }  // namespace chainrk4

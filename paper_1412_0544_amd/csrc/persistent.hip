@@ -13,6 +13,8 @@
 // sees the flags, so the neighbour data is visible across XCDs. Every wait is
 // bounded: past the limit the error word is set and the item goes on, so
 // every block always exits.
+#include <atomic>
+
 #include "cluster.hpp"
 
 namespace chainrk4 {
@@ -144,10 +146,11 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
 
 template <int M, class R, bool KAHAN, int S, bool COH, bool RES>
 int capacity_one() {
-    static int cached[64];
+    static std::atomic<int> cached[64];  // batches on different threads may ask at once
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    if (cached[dev] == 0) {
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
                                                          persistent_kernel<M, R, KAHAN, S, COH, RES>,
@@ -155,9 +158,10 @@ int capacity_one() {
             return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
-        cached[dev] = per_cu * cus;
+        v = per_cu * cus;
+        cached[dev].store(v, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return v;
 }
 
 template <int M, class R, bool KAHAN>
