@@ -85,11 +85,14 @@ constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 17, 2, 1, 16},
                                    {int64_t(1) << 19, 4, 1, 32},
                                    {int64_t(1) << 21, 8, 1, 32},
                                    {INT64_MAX, 8, 4, 32}};
+// FP32 state (all three FP32 precisions agree): multi-wavefront clusters from
+// 2^18 sites on, where the all-lane LDS exchange leaves room for more sites
+// per lane.
 constexpr ShapeRow kShapeFp32[] = {{int64_t(1) << 17, 2, 1, 16},
-                                   {int64_t(1) << 19, 4, 1, 32},
-                                   {int64_t(1) << 21, 8, 1, 32},
-                                   {int64_t(1) << 23, 4, 8, 32},
-                                   {INT64_MAX, 8, 8, 32}};
+                                   {int64_t(1) << 19, 2, 4, 32},
+                                   {int64_t(1) << 21, 4, 4, 32},
+                                   {int64_t(1) << 23, 8, 4, 32},
+                                   {INT64_MAX, 16, 4, 32}};
 
 ShapeRow shape_for(int prec, int64_t n) {
     const ShapeRow *rows = prec == CHAIN_FP64 ? kShapeFp64 : kShapeFp32;

@@ -68,98 +68,176 @@ __device__ __forceinline__ void store_contig(R *__restrict__ dst, const R (&src)
     }
 }
 
-// Edge coordinates a wavefront publishes for its neighbours in the cluster,
-// double-buffered by stage parity so one barrier per stage suffices.
-template <class R, int WPB>
+// Coordinates cross lanes by one of three routes:
+//  * one-wavefront cluster: DPP only (the wavefront's edge lanes take values
+//    that only reach the halo);
+//  * several wavefronts, 8-byte state: DPP inside each wavefront, and the
+//    wavefront edge lanes exchange through two LDS slots per wavefront;
+//  * several wavefronts, 4-byte state: every lane publishes its edge
+//    coordinates in LDS and reads its neighbours' after the stage's barrier
+//    (no lane-dependent branches and no DPP moves, which frees registers:
+//    the FP32 kernels with 16 sites per lane go from 3 to 4 wavefronts per
+//    SIMD; for FP64 state the wider LDS traffic measured slower).
+// Every bond term that joins two lanes is formed by the same operation on
+// the same two coordinates whichever lane forms it, so the route does not
+// change a bit of the result.
+template <int W, class R>
+constexpr bool all_lane_exchange() {
+    return W > 1 && sizeof(R) == 4;
+}
+
+// LDS slots, double-buffered by stage parity so one barrier per stage
+// suffices. A block of a multi-wavefront cluster holds exactly one cluster.
+// ALL: one slot per lane; otherwise one per wavefront.
+template <class R, int WPB, bool ALL>
 struct EdgeSlots {
-    R first[2][WPB];
-    R last[2][WPB];
+    R first[2][ALL ? 64 * WPB : WPB];
+    R last[2][ALL ? 64 * WPB : WPB];
 };
 
 // The same for next-nearest-neighbour coupling: two coordinates per edge.
-template <class R, int WPB>
+template <class R, int WPB, bool ALL>
 struct EdgeSlots2 {
-    R first[2][2][WPB];   // [parity][0: Q_0, 1: Q_1][wavefront]
-    R last[2][2][WPB];    // [parity][0: Q_{S-1}, 1: Q_{S-2}][wavefront]
+    R first[2][ALL ? 64 * WPB : WPB][2];  // [parity][slot][0: Q_0, 1: Q_1]
+    R last[2][ALL ? 64 * WPB : WPB][2];   // [parity][slot][0: Q_{S-1}, 1: Q_{S-2}]
 };
 
-template <int M, class R, int WPB>
-using SlotsOf = typename std::conditional<coupling_range<M>() == 2, EdgeSlots2<R, WPB>,
-                                          EdgeSlots<R, WPB>>::type;
+template <int M, class R, int W, int WPB>
+using SlotsOf =
+    typename std::conditional<coupling_range<M>() == 2,
+                              EdgeSlots2<R, WPB, all_lane_exchange<W, R>()>,
+                              EdgeSlots<R, WPB, all_lane_exchange<W, R>()>>::type;
 
-// One stage for the S sites of this lane. The right neighbour's first
-// coordinate comes in, this lane forms its last bond term, and that term goes
-// to the right neighbour lane as its left bond term. At a wavefront edge
-// inside the cluster the neighbour coordinate comes from LDS instead, and
-// lane 0 forms its left bond term itself (the same operation on the same
-// values as the left wavefront's lane 63).
+// Lane of the block and its two neighbour lanes in the cluster. The
+// outermost lanes of the cluster read their own slot instead (their sites lie
+// in the recomputed halo, so any finite value does).
+struct LaneNbrs {
+    int self, left, right;
+};
+template <int W, int WPB>
+__device__ __forceinline__ LaneNbrs lane_nbrs(int lane, int wib) {
+    static_assert(W > 1 && W == WPB, "a block of a multi-wavefront cluster is one cluster");
+    constexpr int NL = 64 * W;
+    const int t = wib * 64 + lane;
+    return {t, t > 0 ? t - 1 : t, t + 1 < NL ? t + 1 : t};
+}
+
+// Bond terms that reach past this lane's first and last site, NN coupling:
+// bl = bond(first - left neighbour's last), br = bond(right neighbour's
+// first - last).
+template <int M, int W, int WPB, class R>
+__device__ __forceinline__ void edge_bonds(R first, R last, SlotsOf<M, R, W, WPB> *slots, int lane,
+                                           int wib, int wic, int parity, R &bl, R &br) {
+    using Ops = ModelOps<M, R>;
+    if constexpr (all_lane_exchange<W, R>()) {
+        const LaneNbrs nb = lane_nbrs<W, WPB>(lane, wib);
+        slots->first[parity][nb.self] = first;
+        slots->last[parity][nb.self] = last;
+        __syncthreads();
+        br = Ops::bond(slots->first[parity][nb.right] - last);
+        bl = Ops::bond(first - slots->last[parity][nb.left]);
+    } else {
+        R right = from_right(first);
+        if constexpr (W > 1) {
+            if (lane == 0) slots->first[parity][wib] = first;
+            if (lane == 63) slots->last[parity][wib] = last;
+            __syncthreads();
+            if (lane == 63 && wic + 1 < W) right = slots->first[parity][wib + 1];
+        }
+        br = Ops::bond(right - last);
+        bl = from_left(br);
+        if constexpr (W > 1) {
+            if (lane == 0 && wic > 0) bl = Ops::bond(first - slots->last[parity][wib - 1]);
+        }
+    }
+}
+
+// The same with next-nearest-neighbour coupling: three bond terms reach past
+// each end (b1: first neighbour; b2a, b2b: the two second-neighbour bonds
+// that cross the edge, the outer one first). f0, f1: the lane's first two
+// coordinates; l0, l1: its last two, outermost first.
+template <int M, int W, int WPB, class R>
+__device__ __forceinline__ void edge_bonds2(R f0, R f1, R l0, R l1,
+                                            SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
+                                            int wic, int parity, R &b1l, R &b2la, R &b2lb,
+                                            R &b1r, R &b2ra, R &b2rb) {
+    using Ops = ModelOps<M, R>;
+    if constexpr (all_lane_exchange<W, R>()) {
+        const LaneNbrs nb = lane_nbrs<W, WPB>(lane, wib);
+        slots->first[parity][nb.self][0] = f0;
+        slots->first[parity][nb.self][1] = f1;
+        slots->last[parity][nb.self][0] = l0;
+        slots->last[parity][nb.self][1] = l1;
+        __syncthreads();
+        const R r0 = slots->first[parity][nb.right][0], r1 = slots->first[parity][nb.right][1];
+        const R L0 = slots->last[parity][nb.left][0], L1 = slots->last[parity][nb.left][1];
+        b1r = Ops::bond(r0 - l0);
+        b2ra = Ops::bond(r0 - l1);
+        b2rb = Ops::bond(r1 - l0);
+        b1l = Ops::bond(f0 - L0);
+        b2la = Ops::bond(f0 - L1);
+        b2lb = Ops::bond(f1 - L0);
+    } else {
+        R r0 = from_right(f0), r1 = from_right(f1);
+        if constexpr (W > 1) {
+            if (lane == 0) {
+                slots->first[parity][wib][0] = f0;
+                slots->first[parity][wib][1] = f1;
+            }
+            if (lane == 63) {
+                slots->last[parity][wib][0] = l0;
+                slots->last[parity][wib][1] = l1;
+            }
+            __syncthreads();
+            if (lane == 63 && wic + 1 < W) {
+                r0 = slots->first[parity][wib + 1][0];
+                r1 = slots->first[parity][wib + 1][1];
+            }
+        }
+        b1r = Ops::bond(r0 - l0);
+        b2ra = Ops::bond(r0 - l1);
+        b2rb = Ops::bond(r1 - l0);
+        b1l = from_left(b1r);
+        b2la = from_left(b2ra);
+        b2lb = from_left(b2rb);
+        if constexpr (W > 1) {
+            if (lane == 0 && wic > 0) {
+                const R L0 = slots->last[parity][wib - 1][0];
+                const R L1 = slots->last[parity][wib - 1][1];
+                b1l = Ops::bond(f0 - L0);
+                b2la = Ops::bond(f0 - L1);
+                b2lb = Ops::bond(f1 - L0);
+            }
+        }
+    }
+}
+
+// One stage for the S sites of this lane.
 template <int M, int S, int STAGE, int W, int WPB, class R>
 __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S], R (&s)[S],
                                            R (&a)[S], const StepConsts<R> &c,
-                                           EdgeSlots<R, WPB> *slots, int lane, int wib, int wic,
-                                           int parity) {
+                                           SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
+                                           int wic, int parity) {
     const R first = (STAGE == 1) ? q[0] : Q[0];
     const R last = (STAGE == 1) ? q[S - 1] : Q[S - 1];
-    R right = from_right(first);
-    if constexpr (W > 1) {
-        if (lane == 0) slots->first[parity][wib] = first;
-        if (lane == 63) slots->last[parity][wib] = last;
-        __syncthreads();
-        if (lane == 63 && wic + 1 < W) right = slots->first[parity][wib + 1];
-    }
-    const R brS = ModelOps<M, R>::bond(right - last);
-    R bl0 = from_left(brS);
-    if constexpr (W > 1) {
-        if (lane == 0 && wic > 0) bl0 = ModelOps<M, R>::bond(first - slots->last[parity][wib - 1]);
-    }
+    R bl0, brS;
+    edge_bonds<M, W, WPB>(first, last, slots, lane, wib, wic, parity, bl0, brS);
     stage_sites<M, S, STAGE>(Q, X, q, p, s, a, bl0, brS, c);
 }
 
-// The same with next-nearest-neighbour coupling: the right neighbour lane's
-// first two coordinates come in, this lane forms the three bond terms that
-// reach past its last site, and they go to the right neighbour lane as the
-// three that reach past its first site. At a wavefront edge inside the
-// cluster lane 0 forms them itself from the left wavefront's last two
-// coordinates (the same operations on the same values).
+// The same with next-nearest-neighbour coupling.
 template <int M, int S, int STAGE, int W, int WPB, class R>
 __device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
                                                R (&s)[S], R (&a)[S], const StepConsts<R> &c,
-                                               EdgeSlots2<R, WPB> *slots, int lane, int wib,
+                                               SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
                                                int wic, int parity) {
-    using Ops = ModelOps<M, R>;
     const R f0 = (STAGE == 1) ? q[0] : Q[0];
     const R f1 = (STAGE == 1) ? q[1] : Q[1];
     const R l1 = (STAGE == 1) ? q[S - 2] : Q[S - 2];
     const R l0 = (STAGE == 1) ? q[S - 1] : Q[S - 1];
-    R r0 = from_right(f0), r1 = from_right(f1);
-    if constexpr (W > 1) {
-        if (lane == 0) {
-            slots->first[parity][0][wib] = f0;
-            slots->first[parity][1][wib] = f1;
-        }
-        if (lane == 63) {
-            slots->last[parity][0][wib] = l0;
-            slots->last[parity][1][wib] = l1;
-        }
-        __syncthreads();
-        if (lane == 63 && wic + 1 < W) {
-            r0 = slots->first[parity][0][wib + 1];
-            r1 = slots->first[parity][1][wib + 1];
-        }
-    }
-    const R b1rS = Ops::bond(r0 - l0);
-    const R b2rS2 = Ops::bond(r0 - l1);
-    const R b2rS1 = Ops::bond(r1 - l0);
-    R b1l0 = from_left(b1rS), b2lm2 = from_left(b2rS2), b2lm1 = from_left(b2rS1);
-    if constexpr (W > 1) {
-        if (lane == 0 && wic > 0) {
-            const R L0 = slots->last[parity][0][wib - 1];
-            const R L1 = slots->last[parity][1][wib - 1];
-            b1l0 = Ops::bond(f0 - L0);
-            b2lm2 = Ops::bond(f0 - L1);
-            b2lm1 = Ops::bond(f1 - L0);
-        }
-    }
+    R b1l0, b2lm2, b2lm1, b1rS, b2rS2, b2rS1;
+    edge_bonds2<M, W, WPB>(f0, f1, l0, l1, slots, lane, wib, wic, parity, b1l0, b2lm2, b2lm1,
+                           b1rS, b2rS2, b2rS1);
     stage_sites_nnn<M, S, STAGE>(Q, X, q, p, s, a, b1l0, b2lm2, b2lm1, b1rS, b2rS2, b2rS1, c);
 }
 
@@ -167,7 +245,7 @@ __device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], 
 template <int M, int S, int STAGE, int W, int WPB, class R>
 __device__ __forceinline__ void any_lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
                                                R (&s)[S], R (&a)[S], const StepConsts<R> &c,
-                                               SlotsOf<M, R, WPB> *slots, int lane, int wib,
+                                               SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
                                                int wic, int parity) {
     if constexpr (coupling_range<M>() == 2)
         lane_stage_nnn<M, S, STAGE, W, WPB>(Q, X, q, p, s, a, c, slots, lane, wib, wic, parity);
@@ -314,7 +392,7 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, 
 template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false, class C = float>
 __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
                                             int64_t e0, int64_t halo, int64_t keep, int ksteps,
-                                            double dt, SlotsOf<M, R, WPB> *slots, int lane,
+                                            double dt, SlotsOf<M, R, W, WPB> *slots, int lane,
                                             int wib, int wic) {
     constexpr int E = 64 * S * W;
     const int lo = (wic * 64 + lane) * S;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(fused_block_threads(W)) void fused_kernel(FusedPass
     const int wib = threadIdx.x >> 6;                  // wavefront in block
     const int wic = wib % W;                           // wavefront in cluster
     const int64_t cluster = static_cast<int64_t>(blockIdx.x) * CPB + wib / W;
-    __shared__ SlotsOf<M, R, WPB> slots;
+    __shared__ SlotsOf<M, R, W, WPB> slots;
     // W > 1: a block is exactly one cluster and the grid has no extra blocks,
     // so every wavefront reaches every barrier. W = 1: no barriers.
     if (cluster >= a.waves) return;

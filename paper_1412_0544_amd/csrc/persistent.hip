@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
     constexpr int RMAX = kBatchResidentSites;
     constexpr int SPT = RMAX / kBatchThreads;
     constexpr int E = 64 * S * W;
-    __shared__ SlotsOf<M, R, WPB> slots;
+    __shared__ SlotsOf<M, R, W, WPB> slots;
     __shared__ __align__(16) R ring[RES ? 2 * RMAX : 1];
     __shared__ long long claimed;
     const int lane = threadIdx.x & 63;

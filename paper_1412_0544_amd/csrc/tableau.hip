@@ -18,28 +18,17 @@
 namespace chainrk4 {
 namespace {
 
-// Forces F_j at the stage argument Q of this lane's S sites; the neighbour
-// coordinates cross lanes and wavefronts as in lane_stage / lane_stage_nnn,
-// with the same operations, so edge bond terms are bitwise those of the
-// neighbour.
+// Forces F_j at the stage argument Q of this lane's S sites; the bond terms
+// that join two lanes come from the same exchange as in the RK4 cluster pass
+// (edge_bonds / edge_bonds2), so they are bitwise those of the neighbour.
 template <int M, int S, int W, int WPB, class R>
-__device__ __forceinline__ void lane_force(const R (&Q)[S], R (&F)[S], SlotsOf<M, R, WPB> *slots,
-                                           int lane, int wib, int wic, int parity) {
+__device__ __forceinline__ void lane_force(const R (&Q)[S], R (&F)[S],
+                                           SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
+                                           int wic, int parity) {
     using Ops = ModelOps<M, R>;
     if constexpr (coupling_range<M>() == 1) {
-        const R first = Q[0], last = Q[S - 1];
-        R right = from_right(first);
-        if constexpr (W > 1) {
-            if (lane == 0) slots->first[parity][wib] = first;
-            if (lane == 63) slots->last[parity][wib] = last;
-            __syncthreads();
-            if (lane == 63 && wic + 1 < W) right = slots->first[parity][wib + 1];
-        }
-        const R brS = Ops::bond(right - last);
-        R bl = from_left(brS);
-        if constexpr (W > 1) {
-            if (lane == 0 && wic > 0) bl = Ops::bond(first - slots->last[parity][wib - 1]);
-        }
+        R bl, brS;
+        edge_bonds<M, W, WPB>(Q[0], Q[S - 1], slots, lane, wib, wic, parity, bl, brS);
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const R br = (j + 1 < S) ? Ops::bond(Q[j + 1] - Q[j]) : brS;
@@ -47,34 +36,9 @@ __device__ __forceinline__ void lane_force(const R (&Q)[S], R (&F)[S], SlotsOf<M
             bl = br;
         }
     } else {
-        const R f0 = Q[0], f1 = Q[1], l1 = Q[S - 2], l0 = Q[S - 1];
-        R r0 = from_right(f0), r1 = from_right(f1);
-        if constexpr (W > 1) {
-            if (lane == 0) {
-                slots->first[parity][0][wib] = f0;
-                slots->first[parity][1][wib] = f1;
-            }
-            if (lane == 63) {
-                slots->last[parity][0][wib] = l0;
-                slots->last[parity][1][wib] = l1;
-            }
-            __syncthreads();
-            if (lane == 63 && wic + 1 < W) {
-                r0 = slots->first[parity][0][wib + 1];
-                r1 = slots->first[parity][1][wib + 1];
-            }
-        }
-        const R b1rS = Ops::bond(r0 - l0), b2rS2 = Ops::bond(r0 - l1), b2rS1 = Ops::bond(r1 - l0);
-        R b1l = from_left(b1rS), b2lo = from_left(b2rS2), b2hi = from_left(b2rS1);
-        if constexpr (W > 1) {
-            if (lane == 0 && wic > 0) {
-                const R L0 = slots->last[parity][0][wib - 1];
-                const R L1 = slots->last[parity][1][wib - 1];
-                b1l = Ops::bond(f0 - L0);
-                b2lo = Ops::bond(f0 - L1);
-                b2hi = Ops::bond(f1 - L0);
-            }
-        }
+        R b1l, b2lo, b2hi, b1rS, b2rS2, b2rS1;
+        edge_bonds2<M, W, WPB>(Q[0], Q[1], Q[S - 1], Q[S - 2], slots, lane, wib, wic, parity, b1l,
+                               b2lo, b2hi, b1rS, b2rS2, b2rS1);
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const R b1r = (j + 1 < S) ? Ops::bond(Q[j + 1] - Q[j]) : b1rS;
@@ -119,7 +83,7 @@ __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass
     const int wib = threadIdx.x >> 6;
     const int wic = wib % W;
     const int64_t cluster = static_cast<int64_t>(blockIdx.x) * CPB + wib / W;
-    __shared__ SlotsOf<M, R, WPB> slots;
+    __shared__ SlotsOf<M, R, W, WPB> slots;
     if (cluster >= a.waves) return;  // W = 1 only (a W > 1 grid has no extra blocks)
     const int64_t e0 = cluster * a.tile - a.halo;
     const int lo = (wic * 64 + lane) * S;
