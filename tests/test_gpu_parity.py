@@ -267,6 +267,7 @@ def test_fp32_paths_identical_bits():
     for kw in (dict(sites_per_lane=16, kdepth=4, resident=False),
                dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1, resident=False),
                dict(sites_per_lane=4, kdepth=12, waves_per_cluster=8, resident=False),
+               dict(sites_per_lane=16, kdepth=8, waves_per_cluster=4, resident=False),
                dict(sites_per_lane=2, kdepth=5, waves_per_cluster=2),
                dict(sites_per_lane=2, kdepth=9, waves_per_cluster=1),
                dict(method="naive"), dict(resident=True), dict()):
@@ -288,6 +289,7 @@ def test_fp32_fp64_carry_paths_identical_bits():
     outs = []
     for kw in (dict(sites_per_lane=16, kdepth=4), dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1),
                dict(sites_per_lane=4, kdepth=12, waves_per_cluster=8),
+               dict(sites_per_lane=16, kdepth=8, waves_per_cluster=4),
                dict(sites_per_lane=2, kdepth=5, waves_per_cluster=2),
                dict(method="naive"), dict()):
         ch = Chain(q0, p0, 0.01, prec="fp32_kahan64", **kw)
@@ -309,6 +311,7 @@ def test_plain_fp32_control():
     q0, p0 = workloads.chain_ics(n, 14, dtype=np.float32)
     outs = []
     for kw in (dict(sites_per_lane=16, kdepth=4), dict(sites_per_lane=8, kdepth=7, waves_per_cluster=1),
+               dict(sites_per_lane=16, kdepth=32, waves_per_cluster=4),
                dict(sites_per_lane=2, kdepth=5, waves_per_cluster=2), dict(method="naive"), dict()):
         ch = Chain(q0, p0, 0.01, prec="fp32", **kw)
         ch.step(100)
