@@ -40,25 +40,41 @@ __device__ __forceinline__ double block_sum(double v) {
     return s[0];
 }
 
+// Energy of site i: its kinetic and on-site terms and the bond(s) to the right.
+template <int M, class R, bool KAHAN, class C>
+__device__ __forceinline__ double site_energy(const StateRef &y, int64_t n, int64_t i) {
+    const int64_t ip = (i == n - 1) ? 0 : i + 1;
+    double q, p, qn, pn;
+    coords<R, KAHAN, C>(y, i, q, p);
+    coords<R, KAHAN, C>(y, ip, qn, pn);
+    if constexpr (coupling_range<M>() == 2) {
+        double qnn, pnn;
+        coords<R, KAHAN, C>(y, wrap_index(i + 2, n), qnn, pnn);
+        return ModelOps<M, double>::energy2(q, p, qn - q, qnn - q);
+    } else {
+        return ModelOps<M, double>::energy(q, p, qn - q);
+    }
+}
+
+// Each thread sums the sites i0, i0 + stride, i0 + 2*stride, ... in that
+// order. The loads of four consecutive terms are issued together (more bytes
+// in flight per wavefront), and the terms are still added one by one in index
+// order, so the sum is the same bits as a plain strided loop.
 template <int M, class R, bool KAHAN, class C>
 __global__ __launch_bounds__(kEnergyThreads) void energy_partial(StateRef y, int64_t n,
                                                                  double *partials) {
+    constexpr int U = 4;
     double acc = 0.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kEnergyThreads;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kEnergyThreads + threadIdx.x; i < n;
-         i += stride) {
-        const int64_t ip = (i == n - 1) ? 0 : i + 1;
-        double q, p, qn, pn;
-        coords<R, KAHAN, C>(y, i, q, p);
-        coords<R, KAHAN, C>(y, ip, qn, pn);
-        if constexpr (coupling_range<M>() == 2) {
-            double qnn, pnn;
-            coords<R, KAHAN, C>(y, wrap_index(i + 2, n), qnn, pnn);
-            acc += ModelOps<M, double>::energy2(q, p, qn - q, qnn - q);
-        } else {
-            acc += ModelOps<M, double>::energy(q, p, qn - q);
-        }
+    int64_t i = static_cast<int64_t>(blockIdx.x) * kEnergyThreads + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        double e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = site_energy<M, R, KAHAN, C>(y, n, i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += e[u];
     }
+    for (; i < n; i += stride) acc += site_energy<M, R, KAHAN, C>(y, n, i);
     const double s = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
