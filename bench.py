@@ -337,6 +337,11 @@ def main(argv=None):
                    "overlap_factor": plan["overlap_factor"]},
         "hbm_roofline_pct": 100.0 * value / (HBM_PEAK_GBPS * 1e9 / 32),
         "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99)},
+        # the step call of each timed job alone (HIP events on its stream, no
+        # energy): best and median over the jobs, the min-of-M protocol
+        "per_job_device_su_per_s": {"best": n * js / min(gpu),
+                                    "median": n * js / statistics.median(gpu),
+                                    "jobs": len(gpu)},
         "roofline": rl,
         "energy_final": e_final,
     }
