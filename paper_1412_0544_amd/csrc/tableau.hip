@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kNaiveTabThreads) void naive_tab_stage(StateRef y, 
 }
 
 template <int M, class R, bool KAHAN>
-hipError_t naive_tab_dispatch(StateRef y, const NaiveTabBufs &b, int64_t n, double dt,
+hipError_t naive_tab_dispatch(StateRef y, const NaiveTabBufs &b, int64_t n,
+                              double /* dt: already in the coefficients of t */,
                               const TabArgs &t, hipStream_t st) {
     const int64_t blocks = (n + kNaiveTabThreads - 1) / kNaiveTabThreads;
     if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
