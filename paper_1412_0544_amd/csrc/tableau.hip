@@ -12,7 +12,7 @@
 // and only the forces F_l of the stages are kept (in registers). (A^2)_jl is
 // zero for l >= j - 1 and (b^T A)_l for the last stage, so those terms are not
 // formed. The host derives the coefficients, scaled by the step, in FP64 (TabArgs);
-// SMAX (4 or 8) bounds the stage count at compile time.
+// SMAX (4, 6 or 8) bounds the stage count at compile time.
 #include "cluster.hpp"
 
 namespace chainrk4 {
@@ -157,6 +157,12 @@ hipError_t tab_dispatch(int s, int w, const FusedPass &a, const TabArgs &t, hipS
                                    : hipErrorInvalidValue;
         return hipErrorInvalidValue;
     }
+    // 5 or 6 stages (Dormand-Prince 5 without its last, first-same-as-last
+    // stage): registers for 6 forces instead of 8, one more wavefront per SIMD
+    if (t.stages <= 6 && s == 4)
+        return w == 1 ? tab_launch_one<M, R, KAHAN, 4, 1, 6>(a, t, st)
+             : w == 4 ? tab_launch_one<M, R, KAHAN, 4, 4, 6>(a, t, st)
+                      : hipErrorInvalidValue;
     if (t.stages <= kMaxStages && s == 4)
         return w == 1 ? tab_launch_one<M, R, KAHAN, 4, 1, kMaxStages>(a, t, st)
              : w == 4 ? tab_launch_one<M, R, KAHAN, 4, 4, kMaxStages>(a, t, st)
