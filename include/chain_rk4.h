@@ -10,7 +10,7 @@
  *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
  *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
  * the same two with next-nearest-neighbour bonds (the generalisation named in
- * Sec. 4; every site also bonded to its second neighbours, same potential):
+ * Sec. 5; every site also bonded to its second neighbours, same potential):
  *   quartic NNN:  F_i += (q_{i+2} - q_i)^3 - (q_i - q_{i-2})^3
  *   harmonic NNN: F_i += (q_{i+2} - 2 q_i + q_{i-2})
  * and the paper's own test system, the Roessler chain (Sec. 3.1 Eq. 6-7),
@@ -162,7 +162,10 @@ typedef struct chain_rk4_plan {
                                     whole ring stays on chip for all steps */
     int32_t waves_per_cluster, reserved;
     int64_t tile;                /* output sites per cluster and pass */
-    int64_t halo;                /* recomputed sites per side (reach * kdepth) */
+    int64_t halo;                /* recomputed sites per side: reach * kdepth
+                                    rounded up to a whole 16-byte vector of the
+                                    state (2 FP64 or 4 FP32 sites), so every
+                                    cluster starts on a 16-byte boundary */
     int64_t waves;               /* clusters per pass */
     double overlap_factor;       /* sites computed / sites kept per pass,
                                     1 + 2*halo/tile (Sec. 2.3) */
@@ -226,6 +229,16 @@ int chain_rk4_set_stream(chain_rk4 *h, void *stream);
 int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out);
 
 /*
+ * The plan chain_rk4_create (and, for CHAIN_SCHEME_TABLEAU, a following
+ * chain_rk4_set_tableau with tableau `t`) would give descriptor `d`, without
+ * a GPU or a handle: the granularity of Sec. 2.3 the library picks for this
+ * chain. `t` must be given for CHAIN_SCHEME_TABLEAU and be NULL otherwise.
+ * Returns CHAIN_EINVAL where create or set_tableau would.
+ */
+int chain_rk4_plan_for(const chain_rk4_desc *d, const chain_rk4_tableau *t,
+                       chain_rk4_plan *out);
+
+/*
  * Device pointers of the per-site carries (n floats each, or n doubles for
  * CHAIN_FP32_KAHAN64, inside the workspace) that complete the state of a
  * compensated FP32 handle: the compensated coordinate is q - cq, the momentum
@@ -284,8 +297,16 @@ const char *chain_rk4_last_error(void);
  * gives the same bits as when stepped alone (any handle settings, any grid).
  *
  * All handles of a batch share one model (CHAIN_QUARTIC or CHAIN_HARMONIC)
- * and one precision, use CHAIN_FUSED, appear once, and must stay valid while the batch exists; each
- * chain keeps its own dt. Calls that overlap on one batch's workspace race.
+ * and one precision, use CHAIN_FUSED with CHAIN_SCHEME_RK4 (a handle given a
+ * Butcher tableau is rejected with CHAIN_EINVAL), appear once, and must stay
+ * valid while the batch runs them; each chain keeps its own dt. Calls that
+ * overlap on one batch's workspace race.
+ *
+ * A batch is an object rather than a stateless call over handles: its
+ * workspace (progress flags, the work counter, the item tables), the pinned
+ * host staging of those tables and the per-launch timeout words persist
+ * across step calls, so a steady stream of launches (the rounds of a job
+ * server) allocates nothing, and rebind swaps the chain set in place.
  */
 enum chain_batch_flags {
     CHAIN_BATCH_FENCES = 1,         /* hand cluster data between workgroups with
@@ -317,7 +338,10 @@ typedef struct chain_rk4_batch_desc {
 
 typedef struct chain_rk4_batch_plan {
     int32_t sites_per_lane, kdepth, waves_per_cluster, grid_blocks;
-    int64_t halo;            /* recomputed sites per cluster side */
+    int64_t halo;            /* recomputed sites per cluster side: 2 * kdepth
+                                rounded up to a multiple of 4 (tiles start at
+                                multiples of 4 sites, so every cluster starts
+                                on a 16-byte boundary) */
     int64_t tile_max;        /* most sites a cluster keeps per pass */
     int64_t total_clusters;  /* clusters over all tiled chains */
     int64_t resident_chains; /* chains kept on chip for a whole launch */
@@ -343,6 +367,12 @@ int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batc
  */
 int chain_rk4_batch_rebind(chain_rk4_batch *b, chain_rk4 *const *hs, int count);
 
+/* The shape a batch with descriptor `d` would use (sites_per_lane, kdepth,
+ * waves_per_cluster, halo, tile_max; grid_blocks as given, 0 = as many as the
+ * device holds; the cluster counts are 0), without a GPU or handles.
+ * CHAIN_EINVAL for a descriptor chain_rk4_batch_create would reject. */
+int chain_rk4_batch_plan_for(const chain_rk4_batch_desc *d, chain_rk4_batch_plan *out);
+
 /* Clusters a chain of n sites occupies in a batch of the given shape
  * (sites_per_lane and kdepth as in the descriptor, 0 = default) when it is
  * tiled; a ring kept on chip (CHAIN_BATCH_RESIDENT_RINGS) takes none. 0 for
@@ -353,9 +383,23 @@ int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdep
  * (asynchronous; nsteps is read before the call returns). */
 int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps);
 
-/* Synchronise the batch's stream; CHAIN_ETIMEOUT if a wait for a neighbour
- * expired (the result is then invalid; the kernel still terminated). */
+/* Synchronise the batch's stream; CHAIN_ETIMEOUT if, in any launch since the
+ * last chain_rk4_batch_check, a wait for a neighbour expired (the results of
+ * that launch are then invalid; the kernel still terminated). */
 int chain_rk4_batch_check(chain_rk4_batch *b);
+
+/* Id of the last launch chain_rk4_batch_step enqueued (launches are numbered
+ * 0, 1, ... per batch; a step call with every count 0 launches nothing), or
+ * -1 if there was none. */
+int chain_rk4_batch_last_launch(const chain_rk4_batch *b, int64_t *id);
+
+/* Wait for launch `id` alone (not for launches enqueued after it) and return
+ * CHAIN_ETIMEOUT if one of its waits for a neighbour expired, else CHAIN_OK.
+ * Each launch's timeout word is copied to pinned host memory behind it, so
+ * pipelined callers can check round R while round R+1 runs. CHAIN_EINVAL if
+ * `id` was not enqueued or is older than the last 64 launches (their
+ * timeouts are still reported by chain_rk4_batch_check). */
+int chain_rk4_batch_check_launch(chain_rk4_batch *b, int64_t id);
 
 /* Energies of every chain into e_out[count] (host), as chain_rk4_energy. */
 int chain_rk4_batch_energy(chain_rk4_batch *b, double *e_out);

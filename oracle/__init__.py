@@ -139,7 +139,7 @@ def rk4_sites(model: int, q, p, dt: float, steps: int, sites, threads: int = 1):
 
     After ``steps`` RK4 steps a site depends on the initial state within
     4 * range * steps sites of it (``range`` sites per stage, Sec. 2.3 and
-    Sec. 4). On a ring of 2 * 4 * range * steps + 1 sites cut from the chain
+    Sec. 5). On a ring of 2 * 4 * range * steps + 1 sites cut from the chain
     around site i, those sites are the same, so site i comes out exactly as on
     the full ring. Used when the full ring is too long for the oracle; chains
     shorter than the window run whole.

@@ -16,7 +16,7 @@
  * dq_i/dt = p_i, dp_i/dt = F_i):
  *   quartic:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
  *   harmonic: F_i = -q_i + (q_{i+1} - 2 q_i + q_{i-1})
- * Next-nearest-neighbour variants (the generalisation named in Sec. 4): every
+ * Next-nearest-neighbour variants (the generalisation named in Sec. 5): every
  * site is also bonded to its second neighbours, with the same bond potential:
  *   quartic NNN:  F_i = -(q_i + q_i^3) + (q_{i+1} - q_i)^3 - (q_i - q_{i-1})^3
  *                                      + (q_{i+2} - q_i)^3 - (q_i - q_{i-2})^3

@@ -91,6 +91,7 @@ def _declare(lib):
         "chain_rk4_energy": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
         "chain_rk4_set_stream": (ctypes.c_int, [H, VP]),
         "chain_rk4_get_plan": (ctypes.c_int, [H, ctypes.POINTER(Plan)]),
+        "chain_rk4_plan_for": (ctypes.c_int, [D, ctypes.POINTER(Tableau), ctypes.POINTER(Plan)]),
         "chain_rk4_get_carries": (ctypes.c_int, [H, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
         "chain_rk4_destroy": (ctypes.c_int, [H]),
         "chain_rk4_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -104,6 +105,10 @@ def _declare(lib):
         "chain_rk4_batch_clusters": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32,
                                                       ctypes.c_int32]),
         "chain_rk4_batch_check": (ctypes.c_int, [VP]),
+        "chain_rk4_batch_last_launch": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64)]),
+        "chain_rk4_batch_check_launch": (ctypes.c_int, [VP, ctypes.c_int64]),
+        "chain_rk4_batch_plan_for": (ctypes.c_int, [ctypes.POINTER(BatchDesc),
+                                                    ctypes.POINTER(BatchPlan)]),
         "chain_rk4_batch_energy": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),
         "chain_rk4_batch_get_plan": (ctypes.c_int, [VP, ctypes.POINTER(BatchPlan)]),
         "chain_rk4_batch_destroy": (ctypes.c_int, [VP]),

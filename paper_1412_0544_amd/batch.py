@@ -71,6 +71,30 @@ class Batch:
     def check_status(self) -> int:
         return L.lib().chain_rk4_batch_check(self._b)
 
+    def last_launch(self) -> int:
+        """Id of the last launch `step` enqueued (-1 if none)."""
+        i = ctypes.c_int64()
+        L.check(L.lib().chain_rk4_batch_last_launch(self._b, ctypes.byref(i)),
+                "chain_rk4_batch_last_launch")
+        return i.value
+
+    def launch_status(self, launch: int) -> int:
+        """Wait for one launch (not the ones after it); CHAIN_OK or
+        CHAIN_ETIMEOUT (any other status raises)."""
+        rc = L.lib().chain_rk4_batch_check_launch(self._b, int(launch))
+        if rc not in (L.CHAIN_OK, L.CHAIN_ETIMEOUT):
+            L.check(rc, "chain_rk4_batch_check_launch")
+        return rc
+
+    @staticmethod
+    def plan_for(sites_per_lane: int = 0, kdepth: int = 0, flags: int = 0) -> dict:
+        """The shape a batch of these settings uses (no GPU needed)."""
+        d = L.BatchDesc(0, 0, int(sites_per_lane), int(kdepth), 0, int(flags), 0, 0)
+        P = L.BatchPlan()
+        L.check(L.lib().chain_rk4_batch_plan_for(ctypes.byref(d), ctypes.byref(P)),
+                "chain_rk4_batch_plan_for")
+        return {k: getattr(P, k) for k, _ in L.BatchPlan._fields_}
+
     def energies(self) -> list[float]:
         n = len(self.chains)
         out = (ctypes.c_double * n)()

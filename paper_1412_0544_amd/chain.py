@@ -57,6 +57,20 @@ def tableau_reach(model, a, b) -> int:
     return int(r)
 
 
+def plan_for(n: int, dt: float = 0.01, model="quartic", prec="fp64", method="fused",
+             sites_per_lane: int = 0, kdepth: int = 0, waves_per_cluster: int = 0,
+             flags: int = 0, tableau=None) -> dict:
+    """The plan the library gives a chain of these settings (no GPU needed);
+    ``tableau`` is (a, b) of an explicit method, as for ``Chain``."""
+    scheme = L.CHAIN_SCHEME_RK4 if tableau is None else L.CHAIN_SCHEME_TABLEAU
+    d = L.Desc(int(n), _code(MODELS, model), _code(PRECS, prec), float(dt), _code(METHODS, method),
+               int(sites_per_lane), int(kdepth), int(waves_per_cluster), int(flags), scheme)
+    t = None if tableau is None else ctypes.byref(make_tableau(*tableau))
+    P = L.Plan()
+    L.check(L.lib().chain_rk4_plan_for(ctypes.byref(d), t, ctypes.byref(P)), "chain_rk4_plan_for")
+    return {k: getattr(P, k) for k, _ in L.Plan._fields_}
+
+
 class Chain:
     """One periodic chain advanced by the HIP library.
 

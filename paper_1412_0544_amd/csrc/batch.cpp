@@ -23,6 +23,9 @@ size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kDefaultBatchSites = 4;
 constexpr int kDefaultBatchDepth = 32;  // fastest of 16 and 32 on the 4096-chain batch
 constexpr int kSpinLimit = 1 << 22;  // polls (each with a short sleep) before a wait gives up
+// Launches whose timeout word stays readable one by one (a ring of pinned
+// host words, each filled by a copy queued behind its launch).
+constexpr int64_t kLaunchRing = 64;
 
 // Per-chain pass list of a launch: `head` passes first (0 or 2 entries), then
 // `mid` full passes of `depth` steps, then an optional `tail` pass. The pass
@@ -89,11 +92,16 @@ int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
     sh.depth = kdepth ? kdepth : kDefaultBatchDepth;
     const int64_t E = 64 * static_cast<int64_t>(sh.sites) * kBatchWaves;
     // A step's wrong edge values travel 2 sites into a cluster of the
-    // quartic or harmonic chain (dq/dt = p is local). Every cluster keeps at
+    // quartic or harmonic chain (dq/dt = p is local), so the halo covers
+    // 2*depth sites, rounded up to 4: cluster tiles start at multiples of 4
+    // sites, so every cluster origin then sits on a 16-byte boundary of the
+    // FP64 and FP32 state arrays (the lanes' vector accesses need it; a wider
+    // overlap keeps the kept sites exact, Sec. 2.3). Every cluster keeps at
     // least `halo` sites (so only neighbouring clusters overlap), with room to
     // spare for the 4-site rounding.
-    while (E < 8 * static_cast<int64_t>(sh.depth) + 16 && sh.depth > 2) --sh.depth;
-    sh.halo = 2 * static_cast<int64_t>(sh.depth);
+    auto halo_of = [](int depth) { return (2 * static_cast<int64_t>(depth) + 3) / 4 * 4; };
+    while (E < 4 * halo_of(sh.depth) + 16 && sh.depth > 2) --sh.depth;
+    sh.halo = halo_of(sh.depth);
     sh.tile_max = E - 2 * sh.halo;
     *out = sh;
     return CHAIN_OK;
@@ -113,6 +121,8 @@ int check_handles(chain_rk4 *const *hs, int count, int model, int prec) {
         if (!hs[i]) return fail(CHAIN_EINVAL, "handle %d is NULL", i);
         if (hs[i]->d.method != CHAIN_FUSED)
             return fail(CHAIN_EINVAL, "handle %d does not use the fused method", i);
+        if (hs[i]->d.scheme != CHAIN_SCHEME_RK4)
+            return fail(CHAIN_EINVAL, "handle %d: batches run classical RK4 only (no tableau)", i);
         if (hs[i]->d.model != model || hs[i]->d.prec != prec)
             return fail(CHAIN_EINVAL, "handle %d differs in model or precision", i);
         if (hs[i]->d.model != CHAIN_QUARTIC && hs[i]->d.model != CHAIN_HARMONIC)
@@ -188,6 +198,13 @@ struct chain_rk4_batch {
     void *staging = nullptr;       // pinned host copy of the tables
     hipEvent_t staged = nullptr;   // the last table upload has been read
     bool staged_pending = false;
+    // timeout word of each of the last kLaunchRing launches (pinned), and an
+    // event behind the copy of each
+    int32_t *launch_err = nullptr;
+    hipEvent_t launch_done[kLaunchRing] = {};
+    int64_t launches = 0;          // launches enqueued so far (ids 0..launches-1)
+    int64_t folded = 0;            // launches whose word is in pending_error
+    bool pending_error = false;    // a launch since the last check timed out
     // per chain of the current set
     std::vector<char> resident;
     std::vector<int64_t> clusters, uq, ur;
@@ -214,6 +231,14 @@ void bind(chain_rk4_batch *b, chain_rk4 *const *hs, int count) {
     }
 }
 
+// Fold the timeout words of launches [folded, upto) into pending_error;
+// those launches must have completed.
+void fold_through(chain_rk4_batch *b, int64_t upto) {
+    for (; b->folded < upto; ++b->folded)
+        if (__atomic_load_n(&b->launch_err[b->folded % kLaunchRing], __ATOMIC_ACQUIRE) != 0)
+            b->pending_error = true;
+}
+
 bool has_resident_items(const chain_rk4_batch *b) {
     for (char r : b->resident)
         if (r) return true;
@@ -223,6 +248,22 @@ bool has_resident_items(const chain_rk4_batch *b) {
 }  // namespace
 
 extern "C" {
+
+int chain_rk4_batch_plan_for(const chain_rk4_batch_desc *d, chain_rk4_batch_plan *out) {
+    if (!out) return fail(CHAIN_EINVAL, "out is NULL");
+    Shape sh;
+    int rc = check_desc(d, &sh);
+    if (rc != CHAIN_OK) return rc;
+    chain_rk4_batch_plan P{};
+    P.sites_per_lane = sh.sites;
+    P.kdepth = sh.depth;
+    P.waves_per_cluster = kBatchWaves;
+    P.grid_blocks = d->grid_blocks;
+    P.halo = sh.halo;
+    P.tile_max = sh.tile_max;
+    *out = P;
+    return CHAIN_OK;
+}
 
 int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdepth) {
     Shape sh;
@@ -273,6 +314,11 @@ int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batc
     bind(b, hs, count);
     hipError_t e = hipHostMalloc(&b->staging, b->L.table_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&b->launch_err), sizeof(int32_t) * kLaunchRing,
+                          hipHostMallocDefault);
+    for (int64_t i = 0; e == hipSuccess && i < kLaunchRing; ++i)
+        e = hipEventCreateWithFlags(&b->launch_done[i], hipEventDisableTiming);
     if (e != hipSuccess) {
         chain_rk4_batch_destroy(b);
         return hip_fail(e, "batch staging buffer");
@@ -434,15 +480,49 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
             }
         }
     }
+    // this launch's timeout word into its ring slot; the launch that used the
+    // slot before (kLaunchRing launches ago) is folded into the pending error
+    // of chain_rk4_batch_check first
+    const int64_t ring = b->launches % kLaunchRing;
+    if (b->launches >= kLaunchRing) {
+        HIP_TRY(hipEventSynchronize(b->launch_done[ring]));
+        fold_through(b, b->launches - kLaunchRing + 1);
+    }
+    HIP_TRY(hipMemcpyAsync(&b->launch_err[ring], b->ws + b->L.error, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipEventRecord(b->launch_done[ring], b->stream));
+    ++b->launches;
+    return CHAIN_OK;
+}
+
+int chain_rk4_batch_last_launch(const chain_rk4_batch *b, int64_t *id) {
+    if (!b || !id) return fail(CHAIN_EINVAL, "batch and id must be non-NULL");
+    *id = b->launches - 1;
+    return CHAIN_OK;
+}
+
+int chain_rk4_batch_check_launch(chain_rk4_batch *b, int64_t id) {
+    if (!b) return fail(CHAIN_EINVAL, "batch is NULL");
+    if (id < 0 || id >= b->launches)
+        return fail(CHAIN_EINVAL, "launch %lld was not enqueued", (long long)id);
+    if (id < b->launches - kLaunchRing)
+        return fail(CHAIN_EINVAL, "launch %lld is older than the last %lld launches",
+                    (long long)id, (long long)kLaunchRing);
+    const int64_t slot = id % kLaunchRing;
+    HIP_TRY(hipEventSynchronize(b->launch_done[slot]));
+    if (__atomic_load_n(&b->launch_err[slot], __ATOMIC_ACQUIRE) != 0)
+        return fail(CHAIN_ETIMEOUT, "launch %lld: a work item's wait for its neighbours timed out",
+                    (long long)id);
     return CHAIN_OK;
 }
 
 int chain_rk4_batch_check(chain_rk4_batch *b) {
     if (!b) return fail(CHAIN_EINVAL, "batch is NULL");
-    int32_t err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, b->ws + b->L.error, sizeof err, hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    if (err != 0) return fail(CHAIN_ETIMEOUT, "a work item's wait for its neighbours timed out");
+    fold_through(b, b->launches);
+    const bool err = b->pending_error;
+    b->pending_error = false;
+    if (err) return fail(CHAIN_ETIMEOUT, "a work item's wait for its neighbours timed out");
     return CHAIN_OK;
 }
 
@@ -487,6 +567,12 @@ int chain_rk4_batch_destroy(chain_rk4_batch *b) {
         (void)hipEventDestroy(b->staged);
     }
     if (b->staging) (void)hipHostFree(b->staging);
+    // the copy of the last launch's timeout word (and, in stream order, every
+    // earlier one) must land before its host word is freed
+    if (b->launches > 0) (void)hipEventSynchronize(b->launch_done[(b->launches - 1) % kLaunchRing]);
+    for (hipEvent_t ev : b->launch_done)
+        if (ev) (void)hipEventDestroy(ev);
+    if (b->launch_err) (void)hipHostFree(b->launch_err);
     delete b;
     return CHAIN_OK;
 }

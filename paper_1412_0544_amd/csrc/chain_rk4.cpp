@@ -262,6 +262,14 @@ int64_t model_range(int model) {
     return (model == CHAIN_QUARTIC_NNN || model == CHAIN_HARMONIC_NNN) ? 2 : 1;
 }
 
+// Sites in one 16-byte vector of the state arrays (the FP64-carry form's
+// carries need 2, its FP32 coordinates 4). A lane loads and stores its S
+// consecutive sites with 16-byte vector accesses when its cluster does not
+// wrap, so the cluster's first site must sit on such a boundary: the halo is
+// rounded up to a whole number of vectors. A wider overlap than the reach
+// needs keeps the kept sites exact (Sec. 2.3), so the bits do not change.
+int64_t vector_sites(int prec) { return prec == CHAIN_FP64 ? 2 : 4; }
+
 // Cluster shape of the tableau kernel (see launch_tableau).
 bool tableau_shape_ok(int stages, int sites, int waves) {
     if (waves != 1 && waves != 4) return false;
@@ -301,11 +309,29 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages =
                   : static_cast<int>(std::min<int64_t>(
                         kMaxDepth, std::max<int64_t>(1, kDefaultHalo / reach)));
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
-    // the kept part of a cluster must stay positive: E > 2*halo
-    while (E <= 2 * reach * P.depth && P.depth > 1) --P.depth;
-    P.halo = reach * static_cast<int64_t>(P.depth);
+    const int64_t V = vector_sites(d->prec);
+    auto halo_of = [&](int depth) { return (reach * depth + V - 1) / V * V; };
+    // the kept part of a cluster must stay positive: E > 2*halo. E is a
+    // multiple of 128 sites, so the tile, and with it every cluster origin
+    // cluster*tile - halo, stays a whole number of vectors.
+    while (E <= 2 * halo_of(P.depth) && P.depth > 1) --P.depth;
+    P.halo = halo_of(P.depth);
     P.tile = E - 2 * P.halo;
     P.waves = (d->n + P.tile - 1) / P.tile;
+    return P;
+}
+
+chain_rk4_plan public_plan(const chain_rk4_desc &d, const Plan &p) {
+    chain_rk4_plan P{};
+    P.method = d.method;
+    P.resident = p.resident ? 1 : 0;
+    P.sites_per_lane = p.sites;
+    P.kdepth = p.depth;
+    P.waves_per_cluster = p.waves_per_cluster;
+    P.tile = p.tile;
+    P.halo = p.halo;
+    P.waves = p.waves;
+    P.overlap_factor = p.tile > 0 ? 1.0 + 2.0 * double(p.halo) / double(p.tile) : 1.0;
     return P;
 }
 
@@ -546,17 +572,7 @@ int chain_rk4_set_stream(chain_rk4 *h, void *stream) {
 
 int chain_rk4_get_plan(const chain_rk4 *h, chain_rk4_plan *out) {
     if (!h || !out) return fail(CHAIN_EINVAL, "handle and out must be non-NULL");
-    chain_rk4_plan P{};
-    P.method = h->d.method;
-    P.resident = h->plan.resident ? 1 : 0;
-    P.sites_per_lane = h->plan.sites;
-    P.kdepth = h->plan.depth;
-    P.waves_per_cluster = h->plan.waves_per_cluster;
-    P.tile = h->plan.tile;
-    P.halo = h->plan.halo;
-    P.waves = h->plan.waves;
-    P.overlap_factor = h->plan.tile > 0 ? 1.0 + 2.0 * double(h->plan.halo) / double(h->plan.tile) : 1.0;
-    *out = P;
+    *out = public_plan(h->d, h->plan);
     return CHAIN_OK;
 }
 
@@ -613,6 +629,21 @@ void derive_tableau(TabArgs &t, double h) {
     t.hsb *= h;
 }
 
+// Plan of a tableau method: the halo covers the tableau's exact reach.
+int tableau_plan(const chain_rk4_desc *d, const TabArgs &a, Plan *out) {
+    const int64_t reach = std::max<int64_t>(1, tableau_reach_of(a, model_range(d->model)));
+    Plan P = make_plan(d, reach, a.stages);
+    if (d->method == CHAIN_FUSED && !tableau_shape_ok(a.stages, P.sites, P.waves_per_cluster))
+        return fail(CHAIN_EINVAL,
+                    "the tableau kernel runs sites_per_lane 4 or 8 (4 beyond 4 stages) and "
+                    "waves_per_cluster 1 or 4 (got %d, %d for %d stages)",
+                    P.sites, P.waves_per_cluster, a.stages);
+    if (d->method == CHAIN_FUSED && P.tile < 1)
+        return fail(CHAIN_EINVAL, "the cluster is too small for this tableau's reach");
+    *out = P;
+    return CHAIN_OK;
+}
+
 }  // namespace
 
 int64_t chain_rk4_tableau_reach(int32_t model, const chain_rk4_tableau *t) {
@@ -631,21 +662,35 @@ int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t) {
     TabArgs a;
     int rc = check_tableau(t, &a);
     if (rc != CHAIN_OK) return rc;
-    const int64_t reach = std::max<int64_t>(1, tableau_reach_of(a, model_range(h->d.model)));
-    Plan P = make_plan(&h->d, reach, a.stages);
-    if (h->d.method == CHAIN_FUSED && !tableau_shape_ok(a.stages, P.sites, P.waves_per_cluster))
-        return fail(CHAIN_EINVAL,
-                    "the tableau kernel runs sites_per_lane 4 or 8 (4 beyond 4 stages) and "
-                    "waves_per_cluster 1 or 4 (got %d, %d for %d stages)",
-                    P.sites, P.waves_per_cluster, a.stages);
-    if (h->d.method == CHAIN_FUSED && P.tile < 1)
-        return fail(CHAIN_EINVAL, "the cluster is too small for this tableau's reach");
+    Plan P;
+    rc = tableau_plan(&h->d, a, &P);
+    if (rc != CHAIN_OK) return rc;
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
     derive_tableau(a, h->d.dt);
     h->tableau = a;
     h->plan = P;
     h->has_tableau = true;
+    return CHAIN_OK;
+}
+
+int chain_rk4_plan_for(const chain_rk4_desc *d, const chain_rk4_tableau *t,
+                       chain_rk4_plan *out) {
+    if (!out) return fail(CHAIN_EINVAL, "out is NULL");
+    int rc = check_desc(d);
+    if (rc != CHAIN_OK) return rc;
+    Plan P;
+    if (d->scheme == CHAIN_SCHEME_TABLEAU) {
+        if (!t) return fail(CHAIN_EINVAL, "a CHAIN_SCHEME_TABLEAU descriptor needs its tableau");
+        TabArgs a;
+        rc = check_tableau(t, &a);
+        if (rc == CHAIN_OK) rc = tableau_plan(d, a, &P);
+        if (rc != CHAIN_OK) return rc;
+    } else {
+        if (t) return fail(CHAIN_EINVAL, "a tableau is only given with CHAIN_SCHEME_TABLEAU");
+        P = make_plan(d);
+    }
+    *out = public_plan(*d, P);
     return CHAIN_OK;
 }
 

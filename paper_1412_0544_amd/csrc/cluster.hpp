@@ -12,7 +12,10 @@
 namespace chainrk4 {
 
 // Contiguous loads and stores of a lane's S sites with the widest vector
-// access S allows (the caller guarantees the alignment of that width).
+// access S allows. The address must be aligned to that width: the arrays
+// start on 16-byte boundaries, every cluster origin is a whole number of
+// 16-byte vectors (the single-chain and batch planners round the halo up to
+// one), and a lane's first site is S sites past it.
 template <class R, int S>
 __device__ __forceinline__ void load_contig(R (&dst)[S], const R *__restrict__ src) {
     if constexpr (sizeof(R) == 8 && S % 2 == 0) {

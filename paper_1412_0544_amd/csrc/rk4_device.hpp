@@ -8,7 +8,7 @@
 // quartic:  phi(d) = d^3, U'(q) = q + q^3
 // harmonic: phi(d) = d,   U'(q) = q
 // Every bond term phi(d_i) is computed once and used by both sites it joins.
-// The next-nearest-neighbour models (the generalisation of Sec. 4) add bonds
+// The next-nearest-neighbour models (the generalisation of Sec. 5) add bonds
 // to the second neighbours with the same phi:
 //   F_i = ((phi(d_i) - phi(d_{i-1})) + (phi(e_i) - phi(e_{i-2}))) - U'(q_i),
 //   e_i = q_{i+2} - q_i.

@@ -12,6 +12,13 @@ one's finished jobs are retired, so the device does not idle while the host
 does that work. A job's result does not depend on which other jobs share its
 rounds: every chain of a batch gives the same bits as the chain run alone.
 
+Failures: a job with a negative step count (or no sites) is rejected on
+arrival; a job of zero steps is retired at admission with the energy of its
+initial state. Each round's launches report whether a bounded wait for a
+neighbour cluster expired (the results of that launch are then invalid); the
+jobs of such a launch are stopped at the next round boundary and reported
+"failed", without waiting for later rounds that are already queued.
+
 The scheduling policy is independent of the device: `Server` drives an
 executor; `GpuExecutor` runs the HIP library, `SimExecutor` replays the same
 decisions on a simulated clock (for tests without a GPU).
@@ -41,7 +48,8 @@ class JobResult:
     admitted: float = math.nan
     finished: float = math.nan
     energy: float = math.nan
-    status: str = "pending"      # done | rejected | cancelled
+    status: str = "pending"      # done | rejected | cancelled | failed
+    waited_for_memory: bool = False  # admission was held back by the HBM budget
 
     @property
     def latency(self) -> float:
@@ -96,7 +104,7 @@ class Server:
         def arrive(now):
             while arrivals and arrivals[0].arrival <= now:
                 j = arrivals.popleft()
-                if footprint_bytes(j.n, j.prec) > self.budget:
+                if j.steps < 0 or j.n < 1 or footprint_bytes(j.n, j.prec) > self.budget:
                     results[j.jid].status = "rejected"
                     results[j.jid].finished = now
                 else:
@@ -110,22 +118,35 @@ class Server:
                     results[j.jid].status = "cancelled"
                     continue
                 need = footprint_bytes(j.n, j.prec)
-                if len(active) >= self.max_active or self.used + need > self.budget:
+                if len(active) >= self.max_active:
                     break                   # strict FIFO: nobody overtakes the head
+                if self.used + need > self.budget:
+                    results[j.jid].waited_for_memory = True
+                    break
                 queue.popleft()
                 slot = ex.admit(j)
+                self.admission_log.append(j.jid)
+                r = results[j.jid]
+                r.admitted = ex.now()
+                if j.steps == 0:
+                    # nothing to integrate: the energy of the initial state
+                    r.energy = ex.finish(slot)
+                    ex.release(slot)
+                    r.finished = ex.now()
+                    r.status = "done"
+                    continue
                 self.used += need
                 self.peak_used = max(self.peak_used, self.used)
-                self.admission_log.append(j.jid)
-                results[j.jid].admitted = ex.now()
                 active[j.jid] = {"job": j, "slot": slot, "left": j.steps}
 
-        def retire(done_jids, now, cancelled=False):
+        def retire(done_jids, now, stopped=False):
             for jid in done_jids:
                 a = active.pop(jid)
                 r = results[jid]
                 r.finished = now
-                if cancelled:
+                if ex.failed(a["slot"]):
+                    r.status = "failed"         # a launch it ran in timed out
+                elif stopped:
                     r.status = "cancelled"
                 else:
                     r.energy = ex.finish(a["slot"])
@@ -141,8 +162,10 @@ class Server:
                 # an empty server always fits the head (oversized jobs were
                 # rejected on arrival); never spin
                 raise RuntimeError("admission stalled")
-            # cancellations of running jobs take effect at a round boundary
-            stop = [jid for jid in active if jid in self._cancel and
+            # cancellations of running jobs, and jobs whose launch timed out,
+            # take effect at a round boundary
+            stop = [jid for jid in active
+                    if (jid in self._cancel or ex.failed(active[jid]["slot"])) and
                     (inflight is None or jid not in inflight[1])]
             # launch the next round over every job with steps left
             plan = {}
@@ -163,7 +186,7 @@ class Server:
                 retire(inflight[1], t_done)
                 inflight = None
             if stop:
-                retire(stop, ex.now(), cancelled=True)
+                retire(stop, ex.now(), stopped=True)
             if token is not None:
                 inflight = (token, [jid for jid in plan if active[jid]["left"] == 0])
             elif not active and not queue and arrivals:
@@ -190,9 +213,10 @@ def percentiles(xs, qs=(50, 99)):
 
 class SimExecutor:
     """The server's device side on a simulated clock: a round takes
-    (sum of n * steps) / rate seconds after the previous round ends."""
+    (sum of n * steps) / rate seconds after the previous round ends. Rounds
+    whose index (from 0) is in `fail_rounds` report a timed-out launch."""
 
-    def __init__(self, rate: float = 4e11, overhead: float = 20e-6):
+    def __init__(self, rate: float = 4e11, overhead: float = 20e-6, fail_rounds=()):
         self.rate = rate
         self.overhead = overhead
         self.t = 0.0
@@ -200,6 +224,10 @@ class SimExecutor:
         self.slots = {}
         self._next = 0
         self.max_concurrent = 0
+        self.fail_rounds = set(fail_rounds)
+        self._rounds = 0
+        self._failed = set()
+        self.round_jobs = []          # job ids of each round, in launch order
 
     def start(self):
         self.t = 0.0
@@ -226,11 +254,20 @@ class SimExecutor:
             self.slots[slot]["done"] += k
             su += self.slots[slot]["job"].n * k
         self.device_free = start + self.overhead + su / self.rate
-        return self.device_free
+        idx = self._rounds
+        self._rounds += 1
+        self.round_jobs.append({self.slots[slot]["job"].jid for slot, _ in work.values()})
+        return self.device_free, idx, [slot for slot, _ in work.values()]
 
     def wait(self, token):
-        self.t = max(self.t, token)
+        t_done, idx, slots = token
+        self.t = max(self.t, t_done)
+        if idx in self.fail_rounds:
+            self._failed.update(slots)
         return self.t
+
+    def failed(self, slot) -> bool:
+        return slot in self._failed
 
     def finish(self, slot):
         s = self.slots[slot]
@@ -238,6 +275,7 @@ class SimExecutor:
 
     def release(self, slot):
         del self.slots[slot]
+        self._failed.discard(slot)
 
 
 class GpuExecutor:
@@ -245,7 +283,7 @@ class GpuExecutor:
 
     def __init__(self, device="cuda", dt: float = 0.01, quantum: int = 1000,
                  max_active: int = 64, hbm_budget: int = 4 << 30, sites_per_lane: int = 0,
-                 kdepth: int = 0, keep_state_of=()):
+                 kdepth: int = 0, keep_state_of=(), spin_limit: int = 0):
         import torch
 
         from .batch import Batch
@@ -268,6 +306,8 @@ class GpuExecutor:
         self.kept = {}
         self.t0 = None
         self.retire_stream = torch.cuda.Stream(self.device)
+        self.spin_limit = spin_limit   # polls of a bounded wait (0 = library default)
+        self._failed = set()           # slots that ran in a launch that timed out
 
     def start(self):
         self.warm_up()
@@ -282,8 +322,7 @@ class GpuExecutor:
         import workloads
         slots = [self.admit(workloads.Job(-1 - i, 0.0, 300, 1, prec, model, 0))
                  for i, (model, prec) in enumerate((m, p) for m in MODEL_NAMES for p in PREC_NAMES)]
-        for ev in self.launch_round({s: (s, 1) for s in slots}):
-            ev.synchronize()
+        self.wait(self.launch_round({s: (s, 1) for s in slots}))
         for s in slots:
             self.finish(s)
             self.release(s)
@@ -334,20 +373,29 @@ class GpuExecutor:
             if g["batch"] is None:
                 g["batch"] = self.Batch(chains, max_steps=self.quantum, sites_per_lane=self.sites,
                                         kdepth=self.kdepth, max_chains=self.max_active,
-                                        max_clusters=self.max_clusters, stream=g["stream"])
+                                        max_clusters=self.max_clusters, stream=g["stream"],
+                                        spin_limit=self.spin_limit)
             elif g["members"] != members:
                 g["batch"].rebind(chains)
             g["members"] = members
             g["batch"].step([k for _, k in items])
             ev = torch.cuda.Event()
             ev.record(g["stream"])
-            events.append(ev)
+            events.append((ev, g["batch"], g["batch"].last_launch(), members))
         return events
 
     def wait(self, token):
-        for ev in token:
+        """Wait for one round: each group's launch alone (not the rounds
+        queued after it), noting the slots of a launch that timed out."""
+        from ._lib import CHAIN_ETIMEOUT
+        for ev, batch, launch, members in token:
             ev.synchronize()
+            if batch.launch_status(launch) == CHAIN_ETIMEOUT:
+                self._failed.update(members)
         return self.now()
+
+    def failed(self, slot) -> bool:
+        return slot in self._failed
 
     def finish(self, slot):
         s = self.slots[slot]
@@ -364,4 +412,15 @@ class GpuExecutor:
 
     def release(self, slot):
         s = self.slots.pop(slot)
+        self._failed.discard(slot)
+        g = self.groups[s["group"]]
+        if g["members"] is not None and slot in g["members"]:
+            # The group's batch still names this chain: forget its member set
+            # (the next round rebinds before it launches) and drop the batch's
+            # references, so the chain's device memory is freed now and the
+            # HBM actually held stays within what admission counts.
+            g["members"] = None
+            if g["batch"] is not None:
+                g["batch"].chains = []
+                g["batch"]._hs = None
         s["chain"].close()

@@ -131,13 +131,25 @@ def test_fp32_batch_matches_solo(model):
 
 def test_forced_timeout_is_reported_and_kernel_exits():
     """A spin limit of one poll makes items that must wait give up: the call
-    reports CHAIN_ETIMEOUT and the launch still finishes."""
+    reports CHAIN_ETIMEOUT and the launch still finishes. Each launch keeps
+    its own timeout word: launch 0 is still reported after launch 1 has been
+    queued (its word cleared on the device), and chain_rk4_batch_check
+    reports the timeouts of every launch since the previous check, once."""
     chains = make_chains([200000], [80])
     b = Batch(chains, max_steps=400, spin_limit=1)
     b.step(400)
+    first = b.last_launch()
+    b.step(400)
+    assert b.last_launch() == first + 1
+    assert b.launch_status(first) == L.CHAIN_ETIMEOUT
+    assert b.launch_status(first + 1) == L.CHAIN_ETIMEOUT
     assert b.check_status() == L.CHAIN_ETIMEOUT
+    assert b.check_status() == L.CHAIN_OK            # reported once
+    b.step(400)
     with pytest.raises(ChainError):
         b.check()
+    with pytest.raises(ChainError):
+        b.launch_status(b.last_launch() + 1)         # not enqueued
     b.close()
     # the same batch shape with the default limit is fine
     chains = make_chains([200000], [80])
@@ -156,37 +168,59 @@ def test_batch_rejects_bad_arguments():
     naive = Chain(np.zeros(10), np.zeros(10), 0.01, method="naive")
     with pytest.raises(ChainError):
         Batch([naive], max_steps=10)
+    from paper_1412_0544_amd import tableaus
+    tab = Chain(np.zeros(100), np.zeros(100), 0.01, tableau=tableaus.RK4)
+    with pytest.raises(ChainError):
+        Batch([tab], max_steps=10)      # a Butcher tableau: batches run classical RK4
     b = Batch(a, max_steps=10)
+    assert b.last_launch() == -1
     with pytest.raises(ChainError):
         b.step([11])
     with pytest.raises(ChainError):
         b.step([-1])
+    with pytest.raises(ChainError):
+        b.rebind([tab])
+    b.step([0])                         # nothing to do: no launch
+    assert b.last_launch() == -1
 
 
-def test_workload_4096_chains_sampled():
+def test_workload_4096_chains_every_chain():
     """4096 chains, lengths log-uniform in [256, 65536] (seed 4096), ICs per
-    chain from seed 1000 + b, dt = 0.01, 100 steps, one launch: sampled
-    chains against solo runs (bits) and the oracle (1e-10)."""
+    chain from seed 1000 + b, dt = 0.01, 100 steps, one launch at the
+    library's batch shape: every chain against its solo run (bits, compared on
+    the device), and a sample of whole chains against the oracle (1e-10)."""
     lengths = workloads.batch_lengths(4096)
     chains = []
     for i, n in enumerate(lengths):
-        q0, p0 = workloads.chain_ics(int(n), 1000 + i)
+        q0, p0 = workloads.chain_ics_torch(int(n), 1000 + i, "cuda")
         chains.append(Chain(q0, p0, 0.01))
     b = Batch(chains, max_steps=100)
     b.step(100)
     b.check()
+    e = b.energies()
+    bad = []
+    for i, n in enumerate(lengths):
+        q0, p0 = workloads.chain_ics_torch(int(n), 1000 + i, "cuda")
+        ref = Chain(q0, p0, 0.01, sites_per_lane=8, kdepth=5, resident=False)
+        ref.step(100)
+        if not (torch.equal(ref.q, chains[i].q) and torch.equal(ref.p, chains[i].p)):
+            bad.append(i)
+        ref.close()
+    assert not bad, bad[:10]
     rng = np.random.default_rng(1)
-    sample = sorted(set(rng.integers(0, 4096, 12).tolist()) | {int(np.argmin(lengths)),
+    sample = sorted(set(rng.integers(0, 4096, 40).tolist()) | {int(np.argmin(lengths)),
                                                               int(np.argmax(lengths))})
     for i in sample:
         n = int(lengths[i])
-        got = snapshot(chains[i])
-        want = solo(n, 1000 + i, 100)
-        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
         q0, p0 = workloads.chain_ics(n, 1000 + i)
-        sites = np.unique(np.linspace(0, n - 1, 9).astype(np.int64))
-        qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, 0.01, 100, sites, threads=8)
-        assert np.abs(got[0][sites] - qs).max() <= TOL and np.abs(got[1][sites] - ps).max() <= TOL
+        qo, po = oracle.rk4(oracle.QUARTIC, q0, p0, 0.01, 100, threads=8)
+        q, p = (t.cpu().numpy() for t in chains[i].state())
+        assert np.abs(q - qo).max() <= TOL and np.abs(p - po).max() <= TOL, i
+        eo = oracle.energy(oracle.QUARTIC, qo, po)
+        assert abs(e[i] - eo) <= 1e-12 * abs(eo), i
+    b.close()
+    for c in chains:
+        c.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])

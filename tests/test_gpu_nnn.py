@@ -1,6 +1,6 @@
 """Next-nearest-neighbour chains on the GPU against the oracle, through the
 C ABI: every site also bonded to its second neighbours (the generalisation of
-Sec. 4; the overlap per side doubles).
+Sec. 5; the overlap per side doubles).
 
 FP64 bar as for the nearest-neighbour chains: max-abs state error <= 1e-10
 after 100 steps, energy within 1e-12 relative; every GPU path gives the same
@@ -51,7 +51,7 @@ def test_quartic_nnn_fused_matches_oracle(n, sites, waves, depth):
     q0, p0 = workloads.chain_ics(n, 1)
     q, p, e, plan, _ = gpu_run(q0, p0, 0.01, 100, model="quartic_nnn", sites_per_lane=sites,
                                waves_per_cluster=waves, kdepth=depth)
-    assert plan["resident"] == 0 and plan["halo"] == 4 * plan["kdepth"]
+    assert plan["resident"] == 0 and plan["halo"] == 4 * plan["kdepth"]  # a multiple of 2 sites
     qo, po = oracle_run("quartic_nnn", n, 1, 0.01, 100)
     assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
     eo = oracle.energy(oracle.QUARTIC_NNN, qo, po)

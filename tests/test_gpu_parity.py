@@ -51,8 +51,9 @@ def test_fused_tiled_matches_oracle(n, sites, waves, depth):
                             kdepth=depth, resident=False)
     assert plan["resident"] == 0 and plan["sites_per_lane"] == sites
     assert plan["waves_per_cluster"] == waves
-    # a step's edge error reaches 2 sites into the cluster (dq/dt = p is local)
-    assert plan["halo"] == 2 * plan["kdepth"]
+    # a step's edge error reaches 2 sites into the cluster (dq/dt = p is local);
+    # the halo covers that, rounded up to a whole 16-byte vector (2 FP64 sites)
+    assert plan["halo"] == -(-2 * plan["kdepth"] // 2) * 2
     qo, po = oracle_run("quartic", n, 1, 0.01, 100)
     assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
     eo = oracle.energy(oracle.QUARTIC, qo, po)
@@ -197,6 +198,22 @@ def test_full_size_sampled_sites(full_ics):
     qs, ps = oracle.rk4_sites(oracle.QUARTIC, q0, p0, 0.01, 100, sites)
     assert maxerr(q[sites], qs) <= TOL and maxerr(p[sites], ps) <= TOL
     assert np.all(np.isfinite(q)) and np.all(np.isfinite(p))
+
+
+def test_full_size_every_site_against_the_oracle(full_ics):
+    """N = 2^24, dt = 0.01, 100 steps, the default fused plan (the benchmark's
+    launch configuration): every one of the 2^24 sites against the oracle's
+    whole-ring run (Sec. 2.3: every cluster's kept sites are the exact
+    standard RK4 result), and the energy."""
+    import os
+    q0, p0 = full_ics
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 100)
+    assert plan["resident"] == 0 and plan["waves"] > 8000
+    threads = max(1, min(16, os.cpu_count() or 1))
+    qo, po = oracle.rk4(oracle.QUARTIC, q0, p0, 0.01, 100, threads=threads)
+    assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
+    eo = oracle.energy(oracle.QUARTIC, qo, po)
+    assert abs(e - eo) <= 1e-12 * abs(eo)
 
 
 def test_full_size_every_tuned_shape_identical_bits(full_ics):

@@ -42,6 +42,8 @@ def test_served_jobs_equal_alone_runs():
     assert all(r.status == "done" for r in res)
     assert srv.peak_used <= 64 << 20
     assert srv.rounds >= 2
+    # every job was released: no batch still holds a retired chain
+    assert all(g["batch"] is None or not g["batch"].chains for g in ex.groups.values())
     for j, r in zip(jobs, res):
         want, e = alone(j)
         got = ex.kept[j.jid]
@@ -82,3 +84,27 @@ def test_batch_rebind_to_other_chains():
     from paper_1412_0544_amd import ChainError
     with pytest.raises(ChainError):
         b.rebind(too_many)
+
+
+def test_jobs_of_timed_out_launches_fail_and_the_rest_are_exact():
+    """With a spin limit of one poll, launches whose items had to wait for a
+    neighbour report a timeout: their jobs end "failed" (the server reads
+    each round's own timeout word while the next round runs), the server
+    still finishes, and every job reported "done" is the same bits as the job
+    run alone."""
+    jobs = workloads.served_jobs(10, rate=2000.0, seed=17, n_lo=20_000, n_hi=300_000,
+                                 steps_lo=300, steps_hi=1500)
+    keep = [j.jid for j in jobs]
+    ex = GpuExecutor(quantum=300, max_active=4, hbm_budget=256 << 20, keep_state_of=keep,
+                     spin_limit=1)
+    srv = Server(ex, hbm_budget=256 << 20, max_active=4, quantum=300)
+    res = srv.run(jobs)
+    assert all(r.status in ("done", "failed") for r in res)
+    assert any(r.status == "failed" for r in res)
+    assert srv.used == 0 and not ex.slots
+    for j, r in zip(jobs, res):
+        if r.status == "done":
+            want, e = alone(j)
+            for a, b in zip(ex.kept[j.jid], want):
+                assert torch.equal(a, b), j
+            assert r.energy == e

@@ -1,6 +1,6 @@
 """Pins of the oracle's next-nearest-neighbour chains (every site bonded to
 its first and second neighbours with the same bond potential; the
-generalisation of Sec. 4, whose overlap is twice as long) to facts outside
+generalisation of Sec. 5, whose overlap is twice as long) to facts outside
 the oracle: the exact RK4 map of a normal mode, force = -grad H, hand-expanded
 forces on tiny rings, an independent high-order integrator, fourth-order
 convergence, exact symmetries, and the doubled light cone."""

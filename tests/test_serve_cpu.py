@@ -96,3 +96,58 @@ def test_throughput_and_percentiles():
 def test_bad_configuration():
     with pytest.raises(ValueError):
         Server(SimExecutor(), hbm_budget=0)
+
+
+@pytest.mark.timeout(30)
+def test_zero_step_job_is_retired_at_admission():
+    """A job of zero steps finishes at once with the energy of its initial
+    state (the simulated executor reports the steps run: 0) and the server
+    does not wait for a round that will never carry it."""
+    jobs = [Job(0, 0.0, 5000, 0, 0, 0, 1), Job(1, 0.0, 2000, 300, 1, 1, 2),
+            Job(2, 0.01, 3000, 0, 1, 0, 3)]
+    ex = SimExecutor(rate=1e9)
+    srv = Server(ex, hbm_budget=1 << 30, max_active=4, quantum=100)
+    res = srv.run(jobs)
+    assert [r.status for r in res] == ["done", "done", "done"]
+    assert res[0].energy == 0.0 and res[2].energy == 0.0 and res[1].energy == 300
+    assert res[0].finished >= res[0].admitted >= res[0].arrival
+    assert not ex.slots and srv.used == 0
+
+
+@pytest.mark.timeout(30)
+def test_negative_steps_and_empty_chains_are_rejected():
+    jobs = [Job(0, 0.0, 5000, -1, 0, 0, 1), Job(1, 0.0, 0, 10, 0, 0, 2),
+            Job(2, 0.0, 1000, 10, 0, 0, 3)]
+    srv = Server(SimExecutor(rate=1e9), hbm_budget=1 << 30, max_active=4, quantum=100)
+    res = srv.run(jobs)
+    assert [r.status for r in res] == ["rejected", "rejected", "done"]
+
+
+@pytest.mark.timeout(30)
+@pytest.mark.parametrize("bad_round", [0, 3])
+def test_jobs_of_a_timed_out_launch_fail_and_the_rest_complete(bad_round):
+    """A launch whose bounded wait expired makes its jobs' results invalid:
+    they end "failed" (stopped at the next round boundary, or at their end),
+    every other job completes, and all memory is released."""
+    jobs = [Job(i, 0.002 * i, 20_000 + 1000 * i, 700 * (1 + i % 5), 0, 0, i) for i in range(12)]
+    ex = SimExecutor(rate=1e9, fail_rounds={bad_round})
+    srv = Server(ex, hbm_budget=1 << 30, max_active=4, quantum=500)
+    res = srv.run(jobs)
+    failed = [r for r in res if r.status == "failed"]
+    assert failed and all(math.isnan(r.energy) for r in failed)
+    assert all(r.status in ("done", "failed") for r in res)
+    for r in res:
+        if r.status == "done":
+            assert r.energy == r.steps
+    assert not ex.slots and srv.used == 0
+    # exactly the jobs of the failing round failed
+    assert {r.jid for r in failed} == ex.round_jobs[bad_round]
+
+
+def test_memory_waits_are_recorded():
+    blocker = Job(1, 0.0, 300_000, 3000, 0, 0, 2)
+    big = Job(0, 0.0005, 400_000, 200, 0, 0, 1)
+    budget = footprint_bytes(400_000, 0) + footprint_bytes(1000, 0) * 2
+    res = Server(SimExecutor(rate=1e9), hbm_budget=budget, max_active=8,
+                 quantum=100).run([blocker, big])
+    assert res[1].waited_for_memory and not res[0].waited_for_memory
