@@ -30,6 +30,17 @@ CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 # peak (which counts an FMA as two flops).
 VALU_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 / 1e12  # 39.32
 FP64_VECTOR_TFLOPS = 78.6
+# FP32 vector lane-operations per second: the published 157.3 TFLOP/s FP32
+# vector peak counts an FMA as two flops, so 78.6 T lane-ops/s, twice the
+# FP64 rate. The FP32 kernels are built without packed FP32 instructions;
+# their SQ counters show single FP32 VALU instructions retiring faster than
+# one wave64 instruction per 4 cycles per SIMD (the FP64 rate), so this is
+# the ceiling they are measured against.
+FP32_VALU_PEAK_TOPS = 2 * VALU_PEAK_TOPS
+# Algorithmic work of the compensated FP32 update: the 42 operations of RK4
+# plus the compensation (t = y + v, c = (t - y) - v: 3 operations, and the
+# carry subtracted from the increment: 1) for q and p.
+OPS_PER_SU_FP32_KAHAN = 42 + 8
 
 # Algorithmic work of one site-update (one RK4 step of one site), quartic:
 # force 7 ops (bond diff, 2 mul for the cube, q^2, fma, 2 sub) x 4 stages,
@@ -93,20 +104,26 @@ def roofline(n, ksteps, t_launch, model="quartic", prec="fp64"):
     """Roofline of one fused pass of `ksteps` steps over n sites taking t_launch s."""
     bytes_alg = (BYTES_PER_SITE_PASS_ROESSLER if model == "roessler"
                  else BYTES_PER_SITE_PASS[prec]) * n
-    ops_alg = OPS_PER_SU[model] * n * ksteps
+    fp64 = prec == "fp64"
+    ops_su = OPS_PER_SU_FP32_KAHAN if prec == "fp32_kahan" and model == "quartic" else \
+        OPS_PER_SU[model]
+    peak = VALU_PEAK_TOPS if fp64 else FP32_VALU_PEAK_TOPS
+    ops_alg = ops_su * n * ksteps
     t_hbm = bytes_alg / (HBM_PEAK_GBPS * 1e9)
-    t_alu = ops_alg / (VALU_PEAK_TOPS * 1e12)
+    t_alu = ops_alg / (peak * 1e12)
     hbm = {"achieved": bytes_alg / t_launch / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s"}
-    alu = {"achieved": ops_alg / t_launch / 1e12, "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
+    alu = {"achieved": ops_alg / t_launch / 1e12, "peak": peak, "unit": "Tops/s"}
     for d in (hbm, alu):
         d["frac"] = d["achieved"] / d["peak"]
     if t_alu >= t_hbm:
-        ex = EXECUTED_OPS_PER_SU[model] * n * ksteps / t_launch / 1e12
-        r = {"bound": "alu", **alu, "op": "FP64 VALU lane-op (an fma is one op)",
-             "flops_TFLOPs": FLOPS_PER_SU[model] * n * ksteps / t_launch / 1e12,
-             "executed": {"ops_per_su": EXECUTED_OPS_PER_SU[model], "achieved": ex,
-                          "frac": ex / VALU_PEAK_TOPS},
+        r = {"bound": "alu", **alu,
+             "op": ("FP64" if fp64 else "FP32") + " VALU lane-op (an fma is one op)",
              "hbm_view": hbm}
+        if fp64:
+            ex = EXECUTED_OPS_PER_SU[model] * n * ksteps / t_launch / 1e12
+            r["flops_TFLOPs"] = FLOPS_PER_SU[model] * n * ksteps / t_launch / 1e12
+            r["executed"] = {"ops_per_su": EXECUTED_OPS_PER_SU[model], "achieved": ex,
+                             "frac": ex / VALU_PEAK_TOPS}
     else:
         r = {"bound": "hbm", **hbm, "alu_view": alu}
     r["algorithmic_per_launch"] = {"bytes": bytes_alg, "ops": ops_alg, "sites": n, "ksteps": ksteps}
@@ -148,13 +165,39 @@ def fused_launches(plan, steps):
     return m
 
 
-def cpu_baseline(n, dt, target_s=12.0, chunk=20):
-    """The oracle (as it stands) on the host cores: the same chain and ICs,
-    advanced in chunks of `chunk` steps until about `target_s` seconds."""
+# The paper's own CPU measurements (Sec. 3.2.1-3.2.2): one core each, the
+# Roessler chain (three FP64 coordinates per site) at N = 2^20, T = 50 steps,
+# the best of 10 runs. Site-updates/s are derived as Perf * 2^20. Context
+# only: other hardware and another model than the quartic chain above.
+PAPER_CPU = [
+    {"hardware": "Intel Xeon E5 at 3.8 GHz (turbo), one core, ICC 15.0",
+     "version": "standard RK4", "steps_per_s": "< 30", "site_updates_per_s": "< 3.1e7"},
+    {"hardware": "Intel Xeon E5 at 3.8 GHz (turbo), one core, ICC 15.0",
+     "version": "granular + SIMD (AVX)", "steps_per_s": "about 90",
+     "site_updates_per_s": "about 9.4e7"},
+    {"hardware": "AMD Opteron 6272 at 2.1 GHz, one core, clang 3.4",
+     "version": "standard RK4", "steps_per_s": "about 10", "site_updates_per_s": "about 1.05e7"},
+    {"hardware": "AMD Opteron 6272 at 2.1 GHz, one core, clang 3.4",
+     "version": "granular + SIMD", "steps_per_s": "about 30", "site_updates_per_s": "about 3e7"},
+]
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(n, dt, threads, target_s, chunk):
+    """Advance the seed-0 chain in chunks of `chunk` steps until about
+    `target_s` seconds; (site-updates/s, steps, seconds)."""
     import oracle
     import workloads
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, os.cpu_count() or 1))
     q, p = workloads.chain_ics(n, 0)
     oracle.rk4(oracle.QUARTIC, q, p, dt, 1, threads=threads)      # first touch, thread start
     steps = 0
@@ -165,9 +208,27 @@ def cpu_baseline(n, dt, target_s=12.0, chunk=20):
         el = time.perf_counter() - t
         if el >= target_s:
             break
-    return {"value": n * steps / el, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+    return n * steps / el, steps, el
+
+
+def cpu_baseline(n, dt, target_s=12.0, chunk=20, single_s=8.0, single_chunk=2):
+    """The oracle (as it stands: plain C, FP64, whole-ring sweeps, -O3 for
+    generic x86-64) on the host cores: the same chain and ICs, on every
+    thread the run may use and on one thread, plus the paper's CPU numbers
+    for context."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    v, steps, el = time_oracle(n, dt, threads, target_s, chunk)
+    v1, steps1, el1 = time_oracle(n, dt, 1, single_s, single_chunk)
+    return {"value": v, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"quartic chain N={n}, {steps} RK4 steps from the seed-0 initial state "
-                      f"in chunks of {chunk}, {threads} OpenMP threads, {el:.1f} s"}
+                      f"in chunks of {chunk}, {threads} OpenMP threads, {el:.1f} s",
+            "single_thread": {"value": v1, "unit": "site-updates/s", "cores": 1,
+                              "sample": f"the same chain, {steps1} RK4 steps in chunks of "
+                                        f"{single_chunk}, one thread, {el1:.1f} s"},
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "build": "gcc -O3 -std=c99 -fopenmp -ffp-contract=off (generic x86-64)",
+            "paper_cpu_context": PAPER_CPU}
 
 
 def main(argv=None):
@@ -187,7 +248,8 @@ def main(argv=None):
                     help="end with device copies of known size (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=60, help="served jobs (0 = skip)")
+    ap.add_argument("--serve-jobs", type=int, default=500,
+                    help="served jobs per load (0 = skip)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="only sweep N = 2^10..2^26, fused vs per-stage, T = 50, best of 10")
     ap.add_argument("--plan-sweep", action="store_true",
@@ -210,6 +272,22 @@ def main(argv=None):
                     help="chain length of --roessler (the paper's is 2^20)")
     ap.add_argument("--roessler-steps", type=int, default=50,
                     help="steps per timed call of --roessler (the paper's T is 50)")
+    ap.add_argument("--prec", default="fp64",
+                    choices=("fp64", "fp32_kahan", "fp32_kahan64", "fp32"),
+                    help="precision of the timed chain (the headline line is FP64; the "
+                         "others from the FP32-rounded initial state, for profiling)")
+    ap.add_argument("--batch", action="store_true",
+                    help="only the 4096-chain batch (one persistent launch per precision)")
+    ap.add_argument("--batch-steps", type=int, default=2000,
+                    help="steps of the timed launch of --batch")
+    ap.add_argument("--batch-precs", default="fp64,fp32_kahan",
+                    help="precisions of --batch, comma separated")
+    ap.add_argument("--batch-shape", default="",
+                    help="sites per lane and depth of --batch as S,K (default: the batch "
+                         "autotuner's pick)")
+    ap.add_argument("--batch-host-ics", action="store_true",
+                    help="draw the --batch initial states on the host (the same values; far "
+                         "fewer device launches, for profiled runs)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -256,12 +334,28 @@ def main(argv=None):
                           "unit": "steps/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
                           "config": {"workload": f"Roessler chain N={rn}, dt=0.01, T={rs} steps, "
                                                  "best of 10"},
-                          "roessler": variant_roessler(dev, n=rn, steps=rs, sweep=args.sweep)}),
+                          "roessler": variant_roessler(dev, n=rn, steps=rs, sweep=args.sweep),
+                          "copy_probe_bytes": copy_probe(dev) if args.copy_probe else None}),
+              flush=True)
+        return 0
+    if args.batch:
+        print(json.dumps({"metric": "site-updates/sec of one persistent launch over 4096 chains",
+                          "unit": "site-updates/s", "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": "4096 quartic chains, N log-uniform [256, 65536], "
+                                                 f"dt=0.01, {args.batch_steps} steps"},
+                          "batch4096": variant_batch(
+                              0.01, dev, steps=args.batch_steps, precs=args.batch_precs.split(","),
+                              extras=False, host_ics=args.batch_host_ics,
+                              shape=tuple(int(x) for x in args.batch_shape.split(","))
+                              if args.batch_shape else None),
+                          "copy_probe_bytes": copy_probe(dev) if args.copy_probe else None}),
               flush=True)
         return 0
     n, dt, js = args.n, 0.01, args.job_steps
     log(f"[bench] generating ICs n={n}")
     q0, p0 = workloads.chain_ics(n, 0)
+    if args.prec != "fp64":
+        q0, p0 = q0.astype(np.float32), p0.astype(np.float32)
     qd = torch.from_numpy(q0).to(dev)
     pd = torch.from_numpy(p0).to(dev)
     if args.nnn:
@@ -292,12 +386,12 @@ def main(argv=None):
                                         use_cache=False)
         sweep = {f"s{s}_w{w}_k{k}": v for (s, w, k), v in sorted(table.items())}
     else:
-        probe = Chain(qd, pd, dt, resident=False, device=dev).plan()
+        probe = Chain(qd, pd, dt, prec=args.prec, resident=False, device=dev).plan()
         S, W, K = probe["sites_per_lane"], probe["waves_per_cluster"], probe["kdepth"]
     log(f"[bench] plan S={S} W={W} K={K}")
 
-    ch = Chain(qd, pd, dt, sites_per_lane=S, waves_per_cluster=W, kdepth=K, resident=False,
-               device=dev)
+    ch = Chain(qd, pd, dt, prec=args.prec, sites_per_lane=S, waves_per_cluster=W, kdepth=K,
+               resident=False, device=dev)
     plan = ch.plan()
     time_jobs(ch, js, args.warmup)
     log(f"[bench] timing {args.steps} jobs of {js} steps")
@@ -308,11 +402,12 @@ def main(argv=None):
     value = su / wall
     launches = fused_launches(plan, js)
     t_launch = statistics.mean(gpu) / launches
-    rl = roofline(n, js / launches, t_launch)
+    rl = roofline(n, js / launches, t_launch, prec=args.prec)
     rl["launches_per_job"] = launches
     rl["traffic"] = None
     mt = MEASURED_TRAFFIC
-    if (kernel_sources_sha256() == mt["sha256"] and (S, W, plan["halo"]) == mt["shape"]
+    if (args.prec == "fp64" and kernel_sources_sha256() == mt["sha256"]
+            and (S, W, plan["halo"]) == mt["shape"]
             and n == mt["n"]):
         rl["traffic"] = mt["bytes_per_launch"]
         rl["traffic_vs_algorithmic"] = mt["bytes_per_launch"] / rl["algorithmic_per_launch"]["bytes"]
@@ -328,10 +423,11 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.prec == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": "quartic chain, N=2^24, periodic, q,p~U[-1,1) seed 0, dt=0.01, "
                                "1000 RK4 steps per job + energy",
+                   "precision": args.prec,
                    "n": n, "job_steps": js, "sites_per_lane": S, "waves_per_cluster": W,
                    "kdepth": K, "tile": plan["tile"], "halo": plan["halo"],
                    "overlap_factor": plan["overlap_factor"]},
@@ -352,13 +448,7 @@ def main(argv=None):
         out["variants"] = variants(qd, pd, dt, n, dev, (S, W), serve_jobs=args.serve_jobs)
 
     if args.copy_probe:
-        # plain device copies of known size, for scaling the HBM byte counters
-        src = torch.empty(1 << 26, dtype=torch.float64, device=dev)   # 512 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = src.numel() * 8
+        out["copy_probe_bytes"] = copy_probe(dev)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -369,6 +459,18 @@ def main(argv=None):
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
     return 0
+
+
+def copy_probe(dev):
+    """Three plain device copies of 512 MiB, for scaling the HBM byte
+    counters of a profiled run; returns the bytes of one copy."""
+    import torch
+    src = torch.empty(1 << 26, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 8
 
 
 def ev_seconds(fn, stream):
@@ -408,7 +510,18 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
             drift.append((ch.energy() - e0) / e0)
         out[name] = {"su_per_s": n * steps / t, "rel_drift_final": drift[-1],
                      "rel_drift_max_abs": float(np.max(np.abs(drift))),
-                     "rel_drift_samples": drift[:: max(1, len(drift) // 20)]}
+                     "rel_drift_samples": drift[:: max(1, len(drift) // 20)],
+                     "plan": {k: v for k, v in ch.plan().items()
+                              if k in ("sites_per_lane", "waves_per_cluster", "kdepth", "halo")}}
+        if prec in ("fp32_kahan", "fp32", "fp64"):
+            ops = {"fp64": OPS_PER_SU["quartic"], "fp32": OPS_PER_SU["quartic"],
+                   "fp32_kahan": OPS_PER_SU_FP32_KAHAN}[prec]
+            peak = VALU_PEAK_TOPS if prec == "fp64" else FP32_VALU_PEAK_TOPS
+            a = ops * n * steps / t / 1e12
+            out[name]["roofline"] = {
+                "bound": "alu", "achieved": a, "peak": peak, "unit": "Tops/s", "frac": a / peak,
+                "ops_per_su": ops, "op": ("FP64" if prec == "fp64" else "FP32") +
+                " VALU lane-op (an fma is one op)", "timed": "device time of the step calls"}
         ch.close()
     # the drift again at a step exact in FP32 (2^-7): the FP32 stages then
     # advance by the same step as the final combination
@@ -444,10 +557,12 @@ def variant_precision(n, dt, dev, steps=10_000, every=100):
     return out
 
 
-def variant_batch(dt, dev, steps=2000, count=4096):
+def variant_batch(dt, dev, steps=2000, count=4096, precs=("fp64", "fp32_kahan"), extras=True,
+                  shape=None, host_ics=False):
     """4096 chains, lengths log-uniform in [256, 65536], one persistent
     launch of `steps` steps, FP64 and FP32 with compensated update, at the
-    shape the batch autotuner picks."""
+    shape the batch autotuner picks; with `extras`, also the resident-ring
+    form and one step call per chain."""
     import torch
     import workloads
     from paper_1412_0544_amd import Batch, Chain, autotune
@@ -455,24 +570,45 @@ def variant_batch(dt, dev, steps=2000, count=4096):
     lengths = workloads.batch_lengths(count)
     tot = int(lengths.sum())
     out = {"chains": count, "sites": tot, "steps": steps}
-    for prec in ("fp64", "fp32_kahan"):
+    for prec in precs:
         dtype = torch.float64 if prec == "fp64" else torch.float32
-        chains = [Chain(*workloads.chain_ics_torch(int(n_), 1000 + i, dev, dtype), dt, prec=prec,
-                        device=dev) for i, n_ in enumerate(lengths)]
-        # the batch autotuner picks (sites per lane, depth) on these chains
-        (S, K), table = autotune.tune_batch(chains, use_cache=False)
-        out[f"{prec}_autotune_su_per_s"] = {f"s{s_}_k{k_}": v for (s_, k_), v in table.items()}
+        if host_ics:
+            import numpy as np
+            npt = np.float64 if prec == "fp64" else np.float32
+            chains = [Chain(*workloads.chain_ics(int(n_), 1000 + i, dtype=npt), dt, prec=prec,
+                            device=dev) for i, n_ in enumerate(lengths)]
+        else:
+            chains = [Chain(*workloads.chain_ics_torch(int(n_), 1000 + i, dev, dtype), dt,
+                            prec=prec, device=dev) for i, n_ in enumerate(lengths)]
+        if shape:
+            S, K = shape
+        else:
+            # the batch autotuner picks (sites per lane, depth) on these chains
+            (S, K), table = autotune.tune_batch(chains, use_cache=False)
+            out[f"{prec}_autotune_su_per_s"] = {f"s{s_}_k{k_}": v for (s_, k_), v in table.items()}
         b = Batch(chains, max_steps=steps, sites_per_lane=S, kdepth=K)
         b.step(24)
         b.check()
         t = ev_seconds(lambda: b.step(steps), chains[0].stream)
         b.check()
         plan = b.plan()
+        ops = OPS_PER_SU["quartic"] if prec == "fp64" else OPS_PER_SU_FP32_KAHAN
+        peak = VALU_PEAK_TOPS if prec == "fp64" else FP32_VALU_PEAK_TOPS
+        a = ops * tot * steps / t / 1e12
+        E = 64 * S * plan["waves_per_cluster"]
         out[prec] = {"su_per_s": tot * steps / t, "ms": t * 1e3, "sites_per_lane": S,
                      "kdepth": K, "grid_blocks": plan["grid_blocks"],
                      "resident_chains": plan["resident_chains"],
-                     "clusters": plan["total_clusters"]}
+                     "clusters": plan["total_clusters"],
+                     "kept_lane_site_frac": tot / (plan["total_clusters"] * E),
+                     "roofline": {"bound": "alu", "achieved": a, "peak": peak, "unit": "Tops/s",
+                                  "frac": a / peak, "ops_per_su": ops,
+                                  "timed": "device time of one persistent launch"}}
         b.close()
+        if not extras:
+            for c in chains:
+                c.close()
+            continue
         # the same with the rings of <= 1024 sites kept on chip for all steps
         b = Batch(chains, max_steps=steps, sites_per_lane=S, kdepth=K,
                   flags=L.CHAIN_BATCH_RESIDENT_RINGS)
@@ -507,10 +643,18 @@ def variant_persistent_single(qd, pd, dt, dev, steps=1000):
     return qd.numel() * steps / t
 
 
-def variant_serving(dt, dev, jobs=60, rho=0.8, rate_su=4e11, budget=4 << 30, quantum=1000,
+# Served jobs: HBM budget of the default run. The largest job (4e6 sites,
+# 32 bytes per site with its workspace) takes 128 MB, so 256 MiB holds two of
+# them; with 4 GiB the server never came near its budget (peak 0.33 GB over
+# 500 jobs at load 0.8), so admission by footprint was never exercised.
+SERVE_BUDGET = 256 << 20
+
+
+def variant_serving(dt, dev, jobs=500, rho=0.8, rate_su=4e11, budget=SERVE_BUDGET, quantum=1000,
                     max_active=64):
     """Poisson arrivals at load rho of `rate_su`; N log-uniform in [1e3, 4e6],
-    steps uniform in [1e3, 1e5], FP64/FP32 and quartic/harmonic each a coin."""
+    steps uniform in [1e3, 1e5], FP64/FP32 and quartic/harmonic each a coin;
+    admission in arrival order while the HBM budget and a slot allow."""
     import workloads
     from paper_1412_0544_amd.serve import GpuExecutor, Server, percentiles
     mean_work = 4.82e5 * 5.05e4
@@ -525,12 +669,18 @@ def variant_serving(dt, dev, jobs=60, rho=0.8, rate_su=4e11, budget=4 << 30, qua
     done = [r for r in res if r.status == "done"]
     su = sum(r.n * r.steps for r in done)
     lat = percentiles([r.latency for r in done])
+    waited = [r for r in done if r.waited_for_memory]
     return {"jobs": jobs, "done": len(done), "arrival_rate_per_s": lam, "rho": rho,
             "hbm_budget_bytes": budget, "quantum": quantum, "max_active": max_active,
             "latency_s": lat, "queue_s": percentiles([r.queue_s for r in done]),
             "service_s": percentiles([r.service_s for r in done]),
+            "rejected": sum(r.status == "rejected" for r in res),
+            "failed": sum(r.status == "failed" for r in res),
+            "waited_for_memory": len(waited),
+            "queue_s_of_memory_waits": percentiles([r.queue_s for r in waited]),
             "jobs_per_s": len(done) / wall, "su_per_s": su / wall, "wall_s": wall,
-            "rounds": srv.rounds, "peak_hbm_bytes": srv.peak_used}
+            "rounds": srv.rounds, "peak_hbm_bytes": srv.peak_used,
+            "peak_hbm_frac_of_budget": srv.peak_used / budget}
 
 
 def size_sweep(dev, dt=0.01, steps=50, trials=10, exps=range(10, 27, 2)):
@@ -820,7 +970,7 @@ def variant_ring1024(dt, dev):
     return {"p50": 1e3 * pct(lat, 50), "gpu_min": 1e3 * min(g)}
 
 
-def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
+def variants(qd, pd, dt, n, dev, sw, serve_jobs=500):
     """Other rows of the hot path, each measured at its own configuration. A
     variant that fails records its error; the others and the headline line
     still come out."""
@@ -851,10 +1001,13 @@ def variants(qd, pd, dt, n, dev, sw, serve_jobs=60):
         lambda: variant_tableaus(qd, pd, dt, n, dev))
     run("quartic_nnn", "next-nearest-neighbour coupling", lambda: variant_nnn(qd, pd, dt, n, dev))
     run("roessler", "Roessler chain, the paper's protocol", lambda: variant_roessler(dev, dt))
+    run("size_sweep", "chain length sweep N = 2^10..2^26 (every 4th power), fused vs per-stage",
+        lambda: size_sweep(dev, trials=3, exps=range(10, 27, 4)))
     if serve_jobs:
         rate = res.get("batch4096", {}).get("fp64", {}).get("su_per_s", 4e11)
-        run("serving", f"serving {serve_jobs} jobs",
-            lambda: variant_serving(dt, dev, jobs=serve_jobs, rate_su=rate))
+        run("serving", f"serving {serve_jobs} jobs at loads 0.5 and 0.8",
+            lambda: {str(rho): variant_serving(dt, dev, jobs=serve_jobs, rho=rho, rate_su=rate)
+                     for rho in (0.5, 0.8)})
     return res
 
 if __name__ == "__main__":

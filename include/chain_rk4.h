@@ -119,13 +119,28 @@ enum chain_flags {
     CHAIN_FLAG_NO_RESIDENT = 2,  /* always run the tiled passes (the default
                                     since the tiled plan measured faster at
                                     every length; kept for compatibility) */
-    CHAIN_FLAG_RESIDENT = 4      /* keep a quartic or harmonic ring of at most
+    CHAIN_FLAG_RESIDENT = 4,     /* keep a quartic or harmonic ring of at most
                                     4096 sites resident on chip in one
                                     workgroup for all steps of a call (one
                                     launch per call, stage arguments in
                                     LDS); CHAIN_EINVAL for longer rings,
                                     other models or schemes, or together
                                     with CHAIN_FLAG_NO_RESIDENT */
+    CHAIN_FLAG_EXCHANGE = 8      /* Roessler chain, fused method: a step call
+                                    of two or more steps holds every cluster
+                                    in registers for all its passes (one
+                                    workgroup each, one launch per call);
+                                    between passes a cluster writes only the
+                                    kept sites its two neighbours read and
+                                    reloads its halo from theirs, instead of
+                                    storing and loading every site (the
+                                    overlap of Sec. 2.3 renewed from memory,
+                                    not the whole cluster). Same results bit
+                                    for bit. The whole chain must be held at
+                                    once: chain_rk4_create returns
+                                    CHAIN_EINVAL if it needs more clusters
+                                    than the device holds, fewer than 3, or
+                                    is no longer than a cluster */
 };
 
 typedef enum chain_status {
@@ -160,7 +175,11 @@ typedef struct chain_rk4_desc {
 typedef struct chain_rk4_plan {
     int32_t method, sites_per_lane, kdepth, resident; /* resident: 1 if the
                                     whole ring stays on chip for all steps */
-    int32_t waves_per_cluster, reserved;
+    int32_t waves_per_cluster;
+    int32_t exchange;            /* 1 if step calls hold every cluster in
+                                    registers and exchange edge sites
+                                    (CHAIN_FLAG_EXCHANGE); tile is then the
+                                    largest kept count of a cluster */
     int64_t tile;                /* output sites per cluster and pass */
     int64_t halo;                /* recomputed sites per side: reach * kdepth
                                     rounded up to a whole 16-byte vector of the
@@ -272,6 +291,15 @@ int chain_rk4_set_tableau(chain_rk4 *h, const chain_rk4_tableau *t);
  * Roessler chain is not covered). No GPU is needed.
  */
 int64_t chain_rk4_tableau_reach(int32_t model, const chain_rk4_tableau *t);
+
+/*
+ * Synchronise the handle's stream and report failures of its step calls
+ * that the launch could not return: CHAIN_ETIMEOUT if, since the last check,
+ * a step call with CHAIN_FLAG_EXCHANGE had a cluster give up waiting for its
+ * neighbours (its results are then invalid; the kernel still finished).
+ * Handles without that flag only synchronise.
+ */
+int chain_rk4_check(chain_rk4 *h);
 
 /* Release a handle (host memory and cached graphs only). NULL is a no-op. */
 int chain_rk4_destroy(chain_rk4 *h);

@@ -16,6 +16,7 @@ CHAIN_QUARTIC_NNN, CHAIN_HARMONIC_NNN = 3, 4
 CHAIN_FP64, CHAIN_FP32_KAHAN, CHAIN_FP32_KAHAN64, CHAIN_FP32 = 0, 1, 2, 3
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT, CHAIN_FLAG_RESIDENT = 1, 2, 4
+CHAIN_FLAG_EXCHANGE = 8
 CHAIN_BATCH_FENCES, CHAIN_BATCH_RESIDENT_RINGS = 1, 2
 CHAIN_SCHEME_RK4, CHAIN_SCHEME_TABLEAU = 0, 1
 CHAIN_MAX_STAGES = 8
@@ -40,7 +41,7 @@ class Desc(ctypes.Structure):
 class Plan(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("sites_per_lane", ctypes.c_int32),
                 ("kdepth", ctypes.c_int32), ("resident", ctypes.c_int32),
-                ("waves_per_cluster", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("waves_per_cluster", ctypes.c_int32), ("exchange", ctypes.c_int32),
                 ("tile", ctypes.c_int64), ("halo", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("overlap_factor", ctypes.c_double)]
 
@@ -94,6 +95,7 @@ def _declare(lib):
         "chain_rk4_plan_for": (ctypes.c_int, [D, ctypes.POINTER(Tableau), ctypes.POINTER(Plan)]),
         "chain_rk4_get_carries": (ctypes.c_int, [H, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
         "chain_rk4_destroy": (ctypes.c_int, [H]),
+        "chain_rk4_check": (ctypes.c_int, [H]),
         "chain_rk4_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "chain_rk4_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(H), ctypes.c_int,
                                                               ctypes.POINTER(BatchDesc)]),

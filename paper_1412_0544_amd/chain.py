@@ -138,6 +138,10 @@ class Chain:
         L.check(L.lib().chain_rk4_step(self._h, int(nsteps)), "chain_rk4_step")
         return self
 
+    def check(self) -> None:
+        """Synchronise the chain's stream (``chain_rk4_check``)."""
+        L.check(L.lib().chain_rk4_check(self._h), "chain_rk4_check")
+
     def energy(self) -> float:
         e = ctypes.c_double()
         L.check(L.lib().chain_rk4_energy(self._h, ctypes.byref(e)), "chain_rk4_energy")
@@ -196,16 +200,20 @@ class RoesslerChain:
 
     def __init__(self, x0, y0, z0, dt: float, method="fused", sites_per_lane: int = 0,
                  kdepth: int = 0, waves_per_cluster: int = 0, graph: bool = False,
-                 device="cuda", stream: torch.cuda.Stream | None = None):
+                 device="cuda", stream: torch.cuda.Stream | None = None,
+                 exchange: bool = False):
         self.device = torch.device(device)
         as_dev = lambda a: torch.as_tensor(a).to(device=self.device,  # noqa: E731
                                                  dtype=torch.float64).contiguous().clone()
         self.x, self.y, self.z = as_dev(x0), as_dev(y0), as_dev(z0)
         if self.x.ndim != 1 or self.x.shape != self.y.shape or self.x.shape != self.z.shape:
             raise ValueError("x0, y0 and z0 must be 1-D of one length")
+        # exchange: every cluster stays in registers for a whole step call,
+        # swapping only edge sites between passes (the whole chain must fit)
+        flags = (L.CHAIN_FLAG_GRAPH if graph else 0) | (L.CHAIN_FLAG_EXCHANGE if exchange else 0)
         self.desc = L.Desc(self.x.numel(), L.CHAIN_ROESSLER, L.CHAIN_FP64, float(dt),
                            _code(METHODS, method), int(sites_per_lane), int(kdepth),
-                           int(waves_per_cluster), L.CHAIN_FLAG_GRAPH if graph else 0, 0)
+                           int(waves_per_cluster), flags, 0)
         lib = L.lib()
         ws = lib.chain_rk4_workspace_bytes(ctypes.byref(self.desc))
         if ws == 0:
@@ -226,6 +234,10 @@ class RoesslerChain:
     def step(self, nsteps: int) -> "RoesslerChain":
         L.check(L.lib().chain_rk4_step(self._h, int(nsteps)), "chain_rk4_step")
         return self
+
+    def check(self) -> None:
+        """Synchronise; raise if a step call's wait for neighbours timed out."""
+        L.check(L.lib().chain_rk4_check(self._h), "chain_rk4_check")
 
     def plan(self) -> dict:
         P = L.Plan()

@@ -154,8 +154,14 @@ int check_desc(const chain_rk4_desc *d) {
         if (d->prec == CHAIN_FP32_KAHAN64 || d->prec == CHAIN_FP32)
             return fail(CHAIN_EINVAL, "tableau methods take CHAIN_FP64 or CHAIN_FP32_KAHAN");
     }
-    if (d->flags & ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT | CHAIN_FLAG_RESIDENT))
+    if (d->flags &
+        ~(CHAIN_FLAG_GRAPH | CHAIN_FLAG_NO_RESIDENT | CHAIN_FLAG_RESIDENT | CHAIN_FLAG_EXCHANGE))
         return fail(CHAIN_EINVAL, "unknown flags 0x%x", d->flags);
+    if ((d->flags & CHAIN_FLAG_EXCHANGE) &&
+        (d->model != CHAIN_ROESSLER || d->method != CHAIN_FUSED || (d->flags & CHAIN_FLAG_RESIDENT)))
+        return fail(CHAIN_EINVAL, "CHAIN_FLAG_EXCHANGE takes the Roessler chain on the fused method");
+    if ((d->flags & CHAIN_FLAG_EXCHANGE) && d->sites_per_lane > 8)
+        return fail(CHAIN_EINVAL, "CHAIN_FLAG_EXCHANGE takes sites_per_lane 4 or 8");
     if (d->flags & CHAIN_FLAG_RESIDENT) {
         if (d->flags & CHAIN_FLAG_NO_RESIDENT)
             return fail(CHAIN_EINVAL, "CHAIN_FLAG_RESIDENT and CHAIN_FLAG_NO_RESIDENT exclude each other");
@@ -171,6 +177,13 @@ int check_desc(const chain_rk4_desc *d) {
     return CHAIN_OK;
 }
 
+// Polls (each with a short sleep) before a cluster of an exchange run gives
+// up waiting for its neighbours: seconds, far beyond any pass.
+constexpr int kExchangeSpinLimit = 1 << 22;
+
+// The cluster plan of a descriptor (defined below, after the reach helpers).
+Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages = 4);
+
 // Arrays of N values the per-stage method of the Hamiltonian chains keeps.
 constexpr int kNaiveArraysHamiltonian = 5;
 
@@ -183,6 +196,7 @@ struct Layout {
     size_t naive_z[5];                // naive, Roessler: the same for z
     size_t naive_tab[(kMaxStages - 1) + 2];  // naive tableau: forces, two arguments
     size_t partials, result;          // energy
+    size_t xflags, xerror;            // CHAIN_FLAG_EXCHANGE: pass counters, timeout word
     size_t total;
 };
 
@@ -221,6 +235,11 @@ Layout layout(const chain_rk4_desc *d) {
     }
     L.partials = take(round_up(kEnergyMaxBlocks * sizeof(double)));
     L.result = take(kAlign);
+    if (d->flags & CHAIN_FLAG_EXCHANGE) {
+        const Plan P = make_plan(d);
+        L.xflags = take(round_up(static_cast<size_t>(P.waves) * sizeof(int32_t)));
+        L.xerror = take(kAlign);
+    }
     L.total = off;
     return L;
 }
@@ -280,7 +299,7 @@ bool tableau_shape_ok(int stages, int sites, int waves) {
 // hold every stage's slope); the fastest in a sweep over S, W, k at N = 2^24.
 int default_sites_tableau(int stages) { return stages <= 4 ? 8 : 4; }
 
-Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages = 4) {
+Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
     Plan P;
     if (d->method != CHAIN_FUSED) return P;
     const bool roessler = d->model == CHAIN_ROESSLER;
@@ -318,7 +337,29 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override = 0, int stages =
     P.halo = halo_of(P.depth);
     P.tile = E - 2 * P.halo;
     P.waves = (d->n + P.tile - 1) / P.tile;
+    if ((d->flags & CHAIN_FLAG_EXCHANGE) && P.tile > 4) {
+        // balanced tiles of 4-site units, as many clusters as a tile of at
+        // most E - 2*halo sites needs (so halo + keep + halo fits a cluster)
+        const int64_t G = (d->n + (P.tile - 4) - 1) / (P.tile - 4);
+        const int64_t units = d->n / 4;
+        P.exchange = true;
+        P.waves = G;
+        P.uq = units / G;
+        P.ur = units % G;
+        P.tile = 4 * (P.uq + 1);          // the largest kept count
+        P.zone = E - P.halo - 4 * P.uq;   // the left neighbour's right halo reaches this far
+    }
     return P;
+}
+
+// Whether an exchange plan is well formed: at least 3 clusters and a chain
+// longer than one cluster (so every halo site lies in a neighbour's kept
+// sites, with one wrap at most), and every cluster keeps at least what its
+// neighbours read (`halo` at its right end, `zone` at its left).
+bool exchange_plan_ok(const Plan &P, int64_t n) {
+    const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;
+    return P.exchange && P.waves >= 3 && P.waves <= INT32_MAX && n > E && P.halo <= 4 * P.uq &&
+           P.zone <= 4 * P.uq;
 }
 
 chain_rk4_plan public_plan(const chain_rk4_desc &d, const Plan &p) {
@@ -328,6 +369,7 @@ chain_rk4_plan public_plan(const chain_rk4_desc &d, const Plan &p) {
     P.sites_per_lane = p.sites;
     P.kdepth = p.depth;
     P.waves_per_cluster = p.waves_per_cluster;
+    P.exchange = p.exchange ? 1 : 0;
     P.tile = p.tile;
     P.halo = p.halo;
     P.waves = p.waves;
@@ -360,6 +402,21 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
                                : launch_naive_step(d.model, d.prec, h->front, h->naive, d.n, d.dt, s);
             if (e != hipSuccess) return hip_fail(e, "naive step launch");
         }
+        return CHAIN_OK;
+    }
+    if (h->plan.exchange && nsteps >= 2) {
+        // one launch: an even number of passes of at most `depth` steps each
+        int64_t passes = (nsteps + h->plan.depth - 1) / h->plan.depth;
+        passes += passes % 2;
+        if (passes > INT32_MAX) return fail(CHAIN_EINVAL, "too many steps in one call");
+        const Plan &P = h->plan;
+        hipError_t e = launch_fill_zero(h->xflags, static_cast<size_t>(P.waves) * sizeof(int32_t), s);
+        if (e != hipSuccess) return hip_fail(e, "clearing the exchange flags");
+        ExchangeRun a{h->front, h->back, d.n, P.uq, P.ur, P.halo, P.zone, nsteps, d.dt,
+                      static_cast<int32_t>(P.waves), static_cast<int32_t>(passes), h->xflags,
+                      h->xerror, kExchangeSpinLimit};
+        e = launch_exchange_roessler(P.sites, P.waves_per_cluster, a, s);
+        if (e != hipSuccess) return hip_fail(e, "exchange launch");
         return CHAIN_OK;
     }
     if (h->plan.resident) {
@@ -517,6 +574,26 @@ int chain_rk4_create3(const chain_rk4_desc *d, void *q, void *p, void *z, void *
     }
     h->partials = reinterpret_cast<double *>(ws + L.partials);
     h->result = reinterpret_cast<double *>(ws + L.result);
+    if (d->flags & CHAIN_FLAG_EXCHANGE) {
+        // every cluster must be held at once, one workgroup each
+        const int cap = exchange_capacity_roessler(h->plan.sites, h->plan.waves_per_cluster);
+        if (!exchange_plan_ok(h->plan, d->n) || cap < h->plan.waves) {
+            const long long G = h->plan.waves;
+            delete h;
+            return fail(CHAIN_EINVAL,
+                        "CHAIN_FLAG_EXCHANGE: %lld clusters for n = %lld; the device holds %d at "
+                        "once, and the plan needs at least 3, each keeping the sites its "
+                        "neighbours read",
+                        G, (long long)d->n, cap);
+        }
+        h->xflags = reinterpret_cast<int32_t *>(ws + L.xflags);
+        h->xerror = reinterpret_cast<int32_t *>(ws + L.xerror);
+        hipError_t e = launch_fill_zero(h->xerror, sizeof(int32_t), h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "clearing the exchange timeout word");
+        }
+    }
     if (has_carries(d->prec)) {
         const size_t cb = round_up(static_cast<size_t>(d->n) * carry_bytes(d->prec));
         hipError_t e = launch_fill_zero(h->front.cq, cb, h->stream);
@@ -689,9 +766,28 @@ int chain_rk4_plan_for(const chain_rk4_desc *d, const chain_rk4_tableau *t,
     } else {
         if (t) return fail(CHAIN_EINVAL, "a tableau is only given with CHAIN_SCHEME_TABLEAU");
         P = make_plan(d);
+        if ((d->flags & CHAIN_FLAG_EXCHANGE) && !exchange_plan_ok(P, d->n))
+            return fail(CHAIN_EINVAL, "CHAIN_FLAG_EXCHANGE: the chain needs at least 3 clusters, "
+                                      "each keeping the sites its neighbours read");
     }
     *out = public_plan(*d, P);
     return CHAIN_OK;
+}
+
+int chain_rk4_check(chain_rk4 *h) {
+    if (!h) return fail(CHAIN_EINVAL, "handle is NULL");
+    if (!h->xerror) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return CHAIN_OK;
+    }
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->xerror, sizeof err, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (err == 0) return CHAIN_OK;
+    hipError_t e = launch_fill_zero(h->xerror, sizeof(int32_t), h->stream);
+    if (e != hipSuccess) return hip_fail(e, "clearing the exchange timeout word");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return fail(CHAIN_ETIMEOUT, "a cluster's wait for its neighbours timed out");
 }
 
 int chain_rk4_destroy(chain_rk4 *h) {

@@ -273,6 +273,38 @@ __device__ __forceinline__ void store_coherent(R *p, R v) {
     __hip_atomic_store((global_ptr<R>)(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Progress flags of clusters handing data to each other inside one launch.
+__device__ __forceinline__ int load_flag(const int32_t *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_flag(int32_t *f, int v) {
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: wait until flags f0, f1, f2 reach `need`. Bounded: past
+// `spin_limit` polls, or once another wait has given up, the error word is
+// set and the caller goes on (its results are then invalid), so every
+// workgroup always finishes.
+__device__ inline bool wait_flags(const int32_t *f0, const int32_t *f1, const int32_t *f2,
+                                  int need, int32_t *error, int spin_limit) {
+    for (int spin = 0;; ++spin) {
+        if (load_flag(f0) >= need && load_flag(f1) >= need && load_flag(f2) >= need) return true;
+        if (spin >= spin_limit || load_flag(error) != 0) {
+            store_flag(error, 1);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Wait until every memory operation this wavefront issued has completed.
+__device__ __forceinline__ void drain_memory() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Registers of one lane's S sites.
 template <class R, bool KAHAN, int S, class C = float>
 struct LaneState {
@@ -346,12 +378,17 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, 
     R *pout = static_cast<R *>(out.p);
     C *cqout = static_cast<C *>(out.cq);
     C *cpout = static_cast<C *>(out.cp);
+    // The lane's sites j in [j0, j1) are kept. Two 32-bit bounds, so that
+    // whatever the compiler precomputes of this test before the step loop
+    // holds two registers, not a 64-bit bound per site.
+    const int j0 = static_cast<int>(keep_lo - lo < 0 ? 0 : (keep_lo - lo > S ? S : keep_lo - lo));
+    const int64_t end = (keep_hi - lo < n - s0) ? keep_hi - lo : n - s0;
+    const int j1 = static_cast<int>(end < 0 ? 0 : (end > S ? S : end));
     if constexpr (COH) {
         R *qb = qout + s0, *pb = pout + s0;
-        const bool all = lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n;
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            if (all || (lo + j >= keep_lo && lo + j < keep_hi && s0 + j < n)) {
+            if (j >= j0 && j < j1) {
                 store_coherent(qb + j, st.q[j]);
                 store_coherent(pb + j, st.p[j]);
                 if constexpr (KAHAN) {
@@ -360,7 +397,7 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, 
                 }
             }
         }
-    } else if (lo >= keep_lo && lo + S <= keep_hi && s0 + S <= n) {
+    } else if (j0 == 0 && j1 == S) {
         store_contig<R, S>(qout + s0, st.q);
         store_contig<R, S>(pout + s0, st.p);
         if constexpr (KAHAN) {
@@ -370,9 +407,8 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, 
     } else {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            const int local = lo + j;
-            const int64_t g = s0 + j;
-            if (local >= keep_lo && local < keep_hi && g < n) {
+            if (j >= j0 && j < j1) {
+                const int64_t g = s0 + j;
                 qout[g] = st.q[j];
                 pout[g] = st.p[j];
                 if constexpr (KAHAN) {
@@ -414,7 +450,15 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
         else
             final_update<S>(st.q, st.p, s, a, c);
     }
-    store_lane<R, KAHAN, S, COH, C>(st, out, n, s0, lo, halo, halo + keep);
+    // The store's per-lane offsets are formed again from the lane id after
+    // the step loop. The empty asm hides that the id is the one used for the
+    // load, so the compiler cannot keep 64-bit offsets and addresses from
+    // before the loop live through it (in the batch kernel they held ten
+    // registers and pushed it past 128).
+    int lane_s = lane;
+    asm volatile("" : "+v"(lane_s));
+    const int lo_s = (wic * 64 + lane_s) * S;
+    store_lane<R, KAHAN, S, COH, C>(st, out, n, e0 + lo_s, lo_s, halo, halo + keep);
 }
 
 // Whole-ring resident run by a block of T threads: thread t owns sites

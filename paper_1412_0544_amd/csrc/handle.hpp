@@ -31,6 +31,11 @@ struct Plan {
     bool resident = false;
     int sites = 0, depth = 0, waves_per_cluster = 0;
     int64_t tile = 0, halo = 0, waves = 0;
+    // CHAIN_FLAG_EXCHANGE: `waves` clusters with balanced tiles (cluster g
+    // keeps 4*uq sites, 4*(uq+1) if g < ur); zone: kept sites at a cluster's
+    // left end that its left neighbour reads
+    bool exchange = false;
+    int64_t uq = 0, ur = 0, zone = 0;
 };
 
 }  // namespace chainrk4
@@ -47,4 +52,6 @@ struct chain_rk4 {
     bool has_tableau = false;     // CHAIN_SCHEME_TABLEAU: set by chain_rk4_set_tableau
     chainrk4::TabArgs tableau{};
     chainrk4::NaiveTabBufs naive_tab{};
+    int32_t *xflags = nullptr;    // CHAIN_FLAG_EXCHANGE: per-cluster pass counters
+    int32_t *xerror = nullptr;    // CHAIN_FLAG_EXCHANGE: sticky timeout word
 };

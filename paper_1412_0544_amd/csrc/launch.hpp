@@ -101,6 +101,36 @@ hipError_t launch_naive_tableau_step(int model, int prec, StateRef y, const Naiv
 constexpr int kModelRoessler = 2;
 hipError_t launch_fused_roessler(int sites_per_lane, int waves_per_cluster, const FusedPass &a,
                                  hipStream_t s);
+
+// A whole step call with every cluster held in registers: one workgroup per
+// cluster for all passes of the call. Between passes a cluster writes the
+// kept sites its two neighbours read into that pass's exchange buffer
+// (device-coherent stores), marks the pass done, waits for its neighbours
+// and reloads its halo from their kept sites. Every cluster must be resident
+// at once. Clusters keep balanced tiles of 4-site units, as in a batch.
+struct ExchangeRun {
+    StateRef front, back;   // front: the caller's buffers (initial and final
+                            // state); pass j exchanges through front (j odd)
+                            // or back (j even)
+    int64_t n;
+    int64_t uq, ur;         // cluster g keeps 4*uq sites, 4*(uq+1) if g < ur;
+                            // the last one also the n % 4 remainder
+    int64_t halo;           // recomputed sites per side, >= reach * steps of a pass
+    int64_t zone;           // kept sites at a cluster's left end that its left
+                            // neighbour reads (its right halo reaches that far)
+    int64_t steps;          // steps of the call: pass j advances steps / passes,
+                            // one more if j < steps % passes
+    double dt;
+    int32_t clusters;       // >= 3
+    int32_t passes;         // even, >= 2 (the last pass ends in front)
+    int32_t *flags;         // per cluster: passes done (zeroed before the launch)
+    int32_t *error;         // set if a bounded wait expires (never cleared here)
+    int32_t spin_limit;     // polls before a wait gives up
+};
+hipError_t launch_exchange_roessler(int sites_per_lane, int waves_per_cluster,
+                                    const ExchangeRun &a, hipStream_t s);
+// Clusters of that shape the current device holds at once (0 on error).
+int exchange_capacity_roessler(int sites_per_lane, int waves_per_cluster);
 hipError_t launch_naive_roessler_step(StateRef y, const NaiveBufs &b, int64_t n, double dt,
                                       hipStream_t s);
 

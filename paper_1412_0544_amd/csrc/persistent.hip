@@ -20,23 +20,6 @@
 namespace chainrk4 {
 namespace {
 
-__device__ __forceinline__ int load_flag(const int32_t *f) {
-    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Thread 0: wait until flags f0, f1, f2 reach `need`.
-__device__ bool wait_flags(const int32_t *f0, const int32_t *f1, const int32_t *f2, int need,
-                           int32_t *error, int spin_limit) {
-    for (int spin = 0;; ++spin) {
-        if (load_flag(f0) >= need && load_flag(f1) >= need && load_flag(f2) >= need) return true;
-        if (spin >= spin_limit || load_flag(error) != 0) {
-            __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-}
-
 // A value every lane holds alike, moved to a scalar register.
 __device__ __forceinline__ long long uniform64(long long x) {
     const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(x));
@@ -66,13 +49,6 @@ __device__ __forceinline__ int pass_steps(const BatchChain &ch, int e, int depth
     if (e < ch.nhead) return e == 0 ? ch.head0 : ch.head1;
     if (ch.tail > 0 && e == ch.passes - 1) return ch.tail;
     return depth;
-}
-
-// Wait until every memory operation this wavefront issued has completed.
-__device__ __forceinline__ void drain_memory() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // COH: cluster data moves through device-coherent loads and stores, and the

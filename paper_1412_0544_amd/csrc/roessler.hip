@@ -3,6 +3,8 @@
 // temporally blocked cluster pass (Sec. 2.3; the overlap of s sites per side
 // carried over `ksteps` steps) and the standard one-kernel-per-stage sweep
 // (Sec. 2.2). Only x couples to the neighbours, so only x crosses lanes.
+#include <atomic>
+
 #include "cluster.hpp"
 
 namespace chainrk4 {
@@ -115,6 +117,124 @@ __global__ __launch_bounds__(roessler_block_threads(W)) void roessler_fused_kern
     }
 }
 
+// A whole step call of the Roessler chain with every cluster held in
+// registers by one workgroup (see ExchangeRun). Each pass is the fused
+// kernel's cluster pass: the same per-site arithmetic and an overlap of at
+// least reach * steps sites per side (Sec. 2.3), so the kept sites are the
+// exact RK4 result and the bits equal the fused path's. Between passes only
+// the kept sites a neighbour reads move through memory, instead of every
+// site of the chain being stored and loaded again: the first `zone` kept
+// sites (the left neighbour's right halo) and the last `halo` (the right
+// neighbour's left halo). They are written with device-coherent stores and
+// read with device-coherent loads, since the neighbour may run on another
+// XCD; a cluster marks its pass done only after its stores completed.
+//
+// Exchange buffers by pass parity: pass j writes into back (j even) or
+// front (j odd), and the call has an even number of passes, so the last pass
+// stores into the caller's buffers. A buffer is written again two passes
+// later, by which time both readers have moved on (a cluster finishing pass
+// j + 2 has waited for its neighbours to finish pass j + 1, which they start
+// only after reading their pass-j halo). The first writes into front come
+// from pass 1, after the neighbours have finished pass 0 and so have read
+// their initial state.
+template <int S, int W>
+__global__ __launch_bounds__(64 * W) void roessler_exchange_kernel(ExchangeRun a) {
+    constexpr int E = 64 * S * W;
+    constexpr int NL = W > 1 ? 64 * W : 1;
+    __shared__ LaneEdges<NL> edges;
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int gl = wib * 64 + lane;
+    const int g = blockIdx.x;
+    const int G = a.clusters;
+    const int64_t start = 4 * (static_cast<int64_t>(g) * a.uq + (g < a.ur ? g : a.ur));
+    const int64_t keep = (g == G - 1) ? a.n - start : 4 * (a.uq + (g < a.ur ? 1 : 0));
+    const int64_t e0 = start - a.halo;
+    const int lo = gl * S;
+    const int64_t s0 = e0 + lo;
+    double x[S], y[S], z[S];
+    load3<S>(x, y, z, a.front, a.n, s0, e0 >= 0 && e0 + E <= a.n);
+    const StepConsts<double> c(a.dt);
+    double X[S], Y[S], Z[S], ax[S], ay[S], az[S];
+    const int64_t base = a.steps / a.passes, extra = a.steps % a.passes;
+    const int left = g == 0 ? G - 1 : g - 1, right = g == G - 1 ? 0 : g + 1;
+    for (int pass = 0;; ++pass) {
+        const int64_t k = base + (pass < extra ? 1 : 0);
+        for (int64_t t = 0; t < k; ++t) {
+            roessler_lane_stage<S, 1, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 0);
+            roessler_lane_stage<S, 2, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 1);
+            roessler_lane_stage<S, 3, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 0);
+            roessler_lane_stage<S, 4, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 1);
+        }
+        if (pass + 1 == a.passes) break;
+        const StateRef ex = (pass & 1) ? a.front : a.back;
+        double *xe = static_cast<double *>(ex.q);
+        double *ye = static_cast<double *>(ex.p);
+        double *ze = ex.z;
+        // Positions again from the lane id, hidden from the compiler, and in
+        // 32 bits inside the cluster: nothing of this is kept live through
+        // the step loop (which holds the kernel at 5 wavefronts per SIMD).
+        int lane_x = gl;
+        asm volatile("" : "+v"(lane_x));
+        const int lx = lane_x * S;
+        const int h = static_cast<int>(a.halo), kp = static_cast<int>(keep);
+        const int zn = static_cast<int>(a.zone);
+        const int64_t sx = e0 + lx;
+        // kept sites never wrap: site sx + j is start + (lx + j - halo) < n
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int local = lx + j;
+            if (local >= h && local < h + kp && (local < h + zn || local >= kp)) {
+                store_coherent(xe + sx + j, x[j]);
+                store_coherent(ye + sx + j, y[j]);
+                store_coherent(ze + sx + j, z[j]);
+            }
+        }
+        drain_memory();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            store_flag(a.flags + g, pass + 1);
+            wait_flags(a.flags + left, a.flags + g, a.flags + right, pass + 1, a.error,
+                       a.spin_limit);
+        }
+        __syncthreads();
+        // halo sites lie within one cluster of the kept ones and n exceeds a
+        // cluster (checked by the host), so one wrap suffices
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int local = lx + j;
+            if (local < h || local >= h + kp) {
+                int64_t i = sx + j;
+                i = i < 0 ? i + a.n : (i >= a.n ? i - a.n : i);
+                x[j] = load_coherent(xe + i);
+                y[j] = load_coherent(ye + i);
+                z[j] = load_coherent(ze + i);
+            }
+        }
+    }
+    // the last pass is odd: its kept sites go to the caller's buffers
+    int lane_s = gl;
+    asm volatile("" : "+v"(lane_s));
+    const int lo_s = lane_s * S;
+    const int64_t s0_s = e0 + lo_s;
+    double *xo = static_cast<double *>(a.front.q);
+    double *yo = static_cast<double *>(a.front.p);
+    if (lo_s >= a.halo && lo_s + S <= a.halo + keep) {
+        store_contig<double, S>(xo + s0_s, x);
+        store_contig<double, S>(yo + s0_s, y);
+        store_contig<double, S>(a.front.z + s0_s, z);
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (lo_s + j >= a.halo && lo_s + j < a.halo + keep) {
+                xo[s0_s + j] = x[j];
+                yo[s0_s + j] = y[j];
+                a.front.z[s0_s + j] = z[j];
+            }
+        }
+    }
+}
+
 constexpr int kNaiveThreads = 256;
 
 // The standard implementation for the Roessler chain: stage j reads its
@@ -180,6 +300,54 @@ hipError_t roessler_launch_one(const FusedPass &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int S, int W>
+hipError_t exchange_launch_one(const ExchangeRun &a, hipStream_t st) {
+    if (a.clusters < 3 || a.passes < 2 || (a.passes & 1)) return hipErrorInvalidValue;
+    roessler_exchange_kernel<S, W><<<dim3(static_cast<unsigned>(a.clusters)), dim3(64 * W), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int S, int W>
+int exchange_capacity_one() {
+    static std::atomic<int> cached[64];  // handles on different threads may ask at once
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, roessler_exchange_kernel<S, W>,
+                                                         64 * W, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        v = per_cu * cus;
+        cached[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+template <int S>
+hipError_t exchange_dispatch_w(int w, const ExchangeRun &a, hipStream_t st) {
+    switch (w) {
+    case 1: return exchange_launch_one<S, 1>(a, st);
+    case 2: return exchange_launch_one<S, 2>(a, st);
+    case 4: return exchange_launch_one<S, 4>(a, st);
+    case 8: return exchange_launch_one<S, 8>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+int exchange_capacity_w(int w) {
+    switch (w) {
+    case 1: return exchange_capacity_one<S, 1>();
+    case 2: return exchange_capacity_one<S, 2>();
+    case 4: return exchange_capacity_one<S, 4>();
+    case 8: return exchange_capacity_one<S, 8>();
+    default: return 0;
+    }
+}
+
 template <int S>
 hipError_t roessler_dispatch_w(int w, const FusedPass &a, hipStream_t st) {
     switch (w) {
@@ -199,6 +367,22 @@ hipError_t launch_fused_roessler(int s, int w, const FusedPass &a, hipStream_t s
     case 8: return roessler_dispatch_w<8>(w, a, st);
     case 16: return roessler_dispatch_w<16>(w, a, st);
     default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_exchange_roessler(int s, int w, const ExchangeRun &a, hipStream_t st) {
+    switch (s) {
+    case 4: return exchange_dispatch_w<4>(w, a, st);
+    case 8: return exchange_dispatch_w<8>(w, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int exchange_capacity_roessler(int s, int w) {
+    switch (s) {
+    case 4: return exchange_capacity_w<4>(w);
+    case 8: return exchange_capacity_w<8>(w);
+    default: return 0;
     }
 }
 

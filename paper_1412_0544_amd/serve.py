@@ -322,7 +322,7 @@ class GpuExecutor:
         import workloads
         slots = [self.admit(workloads.Job(-1 - i, 0.0, 300, 1, prec, model, 0))
                  for i, (model, prec) in enumerate((m, p) for m in MODEL_NAMES for p in PREC_NAMES)]
-        self.wait(self.launch_round({s: (s, 1) for s in slots}))
+        self._wait_round(self.launch_round({s: (s, 1) for s in slots}))
         for s in slots:
             self.finish(s)
             self.release(s)
@@ -384,14 +384,17 @@ class GpuExecutor:
             events.append((ev, g["batch"], g["batch"].last_launch(), members))
         return events
 
-    def wait(self, token):
-        """Wait for one round: each group's launch alone (not the rounds
-        queued after it), noting the slots of a launch that timed out."""
+    def _wait_round(self, token):
         from ._lib import CHAIN_ETIMEOUT
         for ev, batch, launch, members in token:
             ev.synchronize()
             if batch.launch_status(launch) == CHAIN_ETIMEOUT:
                 self._failed.update(members)
+
+    def wait(self, token):
+        """Wait for one round: each group's launch alone (not the rounds
+        queued after it), noting the slots of a launch that timed out."""
+        self._wait_round(token)
         return self.now()
 
     def failed(self, slot) -> bool:

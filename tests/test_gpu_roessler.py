@@ -133,3 +133,70 @@ def test_roessler_rejects_energy_and_batches():
     with pytest.raises(ChainError):
         Batch([ch], max_steps=10)
     ch.close()
+
+
+# The register-resident form (CHAIN_FLAG_EXCHANGE): every cluster stays in
+# registers for a whole step call and swaps only edge sites between passes.
+# The same per-site arithmetic as the fused passes: the same bits.
+@pytest.mark.parametrize("n,sites,waves,depth,steps", [
+    (2051, 4, 2, 1, 2), (4001, 4, 1, 6, 37), (9000, 4, 4, 13, 50), (20011, 4, 4, 25, 50),
+    (30011, 8, 2, 20, 61), (40003, 4, 8, 32, 64), (8195, 4, 4, 16, 1000), (2000, 4, 4, 25, 50),
+    (20011, 4, 4, 25, 1), (20011, 4, 4, 25, 3)])
+def test_exchange_equals_fused_bits(n, sites, waves, depth, steps):
+    ics = workloads.roessler_ics(n, 5)
+    kw = dict(sites_per_lane=sites, waves_per_cluster=waves, kdepth=depth)
+    ref, _ = gpu_run(ics, 0.01, steps, **kw)
+    ch = RoesslerChain(*ics, 0.01, exchange=True, **kw)
+    assert ch.plan()["exchange"] == 1
+    ch.step(steps)
+    ch.check()
+    got = tuple(t.cpu().numpy() for t in ch.state())
+    ch.close()
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b), (n, sites, waves, depth, steps)
+
+
+def test_exchange_against_the_oracle_and_across_calls():
+    n = 12011
+    ics = workloads.roessler_ics(n, 6)
+    ch = RoesslerChain(*ics, 0.01, exchange=True)
+    for k in (30, 1, 69):                     # 100 steps in calls of 30, 1 and 69
+        ch.step(k)
+    ch.check()
+    got = tuple(t.cpu().numpy() for t in ch.state())
+    ch.close()
+    assert maxerr(got, oracle_run(n, 6, 0.01, 100)) <= TOL
+    g = RoesslerChain(*ics, 0.01, exchange=True, graph=True)
+    for _ in range(3):                        # replayed graph, three times
+        g.step(50)
+    g.check()
+    once = RoesslerChain(*ics, 0.01, exchange=True)
+    once.step(150)
+    once.check()
+    for a, b in zip(g.state(), once.state()):
+        assert torch.equal(a, b)
+
+
+def test_exchange_at_the_paper_size_equals_fused():
+    """N = 2^20, T = 50 steps (the paper's protocol) at the library's
+    shape: the whole chain in registers, bit for bit the fused passes."""
+    n = 1 << 20
+    ics = workloads.roessler_ics(n, 0)
+    ref, plan = gpu_run(ics, 0.01, 50)
+    ch = RoesslerChain(*ics, 0.01, exchange=True)
+    p = ch.plan()
+    assert p["exchange"] == 1 and p["waves"] >= 3
+    ch.step(50)
+    ch.check()
+    for a, b in zip((t.cpu().numpy() for t in ch.state()), ref):
+        assert np.array_equal(a, b)
+    ch.close()
+
+
+def test_exchange_refuses_chains_it_cannot_hold():
+    ics = workloads.roessler_ics(1500, 1)
+    with pytest.raises(ChainError):
+        RoesslerChain(*ics, 0.01, exchange=True)          # fewer than 3 clusters
+    big = workloads.roessler_ics(1 << 22, 1)
+    with pytest.raises(ChainError):
+        RoesslerChain(*big, 0.01, exchange=True)          # more clusters than the device holds

@@ -151,3 +151,112 @@ def test_memory_waits_are_recorded():
     res = Server(SimExecutor(rate=1e9), hbm_budget=budget, max_active=8,
                  quantum=100).run([blocker, big])
     assert res[1].waited_for_memory and not res[0].waited_for_memory
+
+
+class _Stream:
+    cuda_stream = 0
+
+
+class _Event:
+    def record(self, stream):
+        pass
+
+    def synchronize(self):
+        pass
+
+
+class _Chain:
+    def __init__(self, q0, p0, dt, **kw):
+        self.q, self.p, self.handle, self.closed = q0, p0, object(), False
+
+    def set_stream(self, stream):
+        pass
+
+    def energy(self):
+        return 1.0
+
+    def carry_tensors(self):
+        return None, None
+
+    def close(self):
+        self.closed = True
+
+
+class _Batch:
+    """Stands in for the library batch: checks the executor's calls."""
+    timed_out = set()       # launch ids that report a timeout
+    launched = []
+
+    def __init__(self, chains, **kw):
+        self.chains, self._hs, self.n = list(chains), object(), 0
+
+    @staticmethod
+    def clusters(n, sites_per_lane=0, kdepth=0):
+        return 1
+
+    def rebind(self, chains):
+        self.chains, self._hs = list(chains), object()
+        return self
+
+    def step(self, ks):
+        assert len(ks) == len(self.chains) and all(not c.closed for c in self.chains)
+        self.n += 1
+        _Batch.launched.append(self)
+
+    def last_launch(self):
+        return self.n - 1
+
+    def launch_status(self, launch):
+        return -6 if (id(self), launch) in _Batch.timed_out else 0
+
+
+@pytest.fixture
+def executor_with_stand_ins(monkeypatch):
+    """GpuExecutor with its device objects replaced, to check its
+    bookkeeping (warm-up, rounds, retire, release, timeouts) on the CPU."""
+    import contextlib
+    import torch
+    from paper_1412_0544_amd import batch as batch_mod, chain as chain_mod, serve
+    monkeypatch.setattr(torch.cuda, "Stream", lambda *a, **k: _Stream())
+    monkeypatch.setattr(torch.cuda, "Event", lambda *a, **k: _Event())
+    monkeypatch.setattr(torch.cuda, "stream", lambda s: contextlib.nullcontext())
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    monkeypatch.setattr(workloads, "chain_ics_torch",
+                        lambda n, seed, dev, dtype=torch.float64: (torch.zeros(n), torch.zeros(n)))
+    monkeypatch.setattr(chain_mod, "Chain", _Chain)
+    monkeypatch.setattr(batch_mod, "Batch", _Batch)
+    _Batch.timed_out, _Batch.launched = set(), []
+    return serve.GpuExecutor
+
+
+@pytest.mark.timeout(60)
+def test_gpu_executor_bookkeeping(executor_with_stand_ins):
+    ex = executor_with_stand_ins(device="cpu", quantum=400, max_active=5, hbm_budget=64 << 20)
+    jobs = workloads.served_jobs(14, rate=400.0, seed=11, n_lo=1000, n_hi=150_000,
+                                 steps_lo=200, steps_hi=2500)
+    srv = Server(ex, hbm_budget=64 << 20, max_active=5, quantum=400)
+    res = srv.run(jobs)
+    assert all(r.status == "done" for r in res)
+    assert srv.used == 0 and not ex.slots
+    # retired chains are dropped from the batches that ran them
+    assert all(g["batch"] is None or not g["batch"].chains for g in ex.groups.values())
+
+
+@pytest.mark.timeout(60)
+def test_gpu_executor_fails_the_jobs_of_a_timed_out_launch(executor_with_stand_ins):
+    ex = executor_with_stand_ins(device="cpu", quantum=300, max_active=4, hbm_budget=64 << 20)
+    jobs = [Job(i, 0.0, 5000, 900, 0, 0, i) for i in range(3)]
+    srv = Server(ex, hbm_budget=64 << 20, max_active=4, quantum=300)
+    orig = _Batch.step
+
+    def step_and_time_out(self, ks):
+        orig(self, ks)
+        if self.n == 2:                  # the second launch of the group times out
+            _Batch.timed_out.add((id(self), self.n - 1))
+    _Batch.step = step_and_time_out
+    try:
+        res = srv.run(jobs)
+    finally:
+        _Batch.step = orig
+    assert [r.status for r in res] == ["failed"] * 3
+    assert srv.used == 0 and not ex.slots
