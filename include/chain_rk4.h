@@ -241,6 +241,30 @@ int chain_rk4_step(chain_rk4 *h, int64_t nsteps);
  */
 int chain_rk4_energy(chain_rk4 *h, double *e_out);
 
+/*
+ * For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): the energy of chain_rk4_energy for a
+ * state in caller buffers, with no handle and no workspace.
+ *   model  CHAIN_QUARTIC, CHAIN_HARMONIC, CHAIN_QUARTIC_NNN or
+ *          CHAIN_HARMONIC_NNN; prec any enum chain_prec.
+ *   n      sites, 1..2^40 (CHAIN_EINVAL beyond).
+ *   q, p   device arrays of n values (double for CHAIN_FP64, float else),
+ *          16-byte aligned; read only.
+ *   cq, cp the carries of a compensated FP32 state (n floats, or n doubles
+ *          for CHAIN_FP32_KAHAN64; each coordinate enters as hi - carry),
+ *          NULL for CHAIN_FP64 and CHAIN_FP32.
+ *   stream where the kernels run; the call synchronises it.
+ * The result is the same bits as chain_rk4_energy of a handle over the same
+ * buffers. The partial sums live in a device array the library owns (1024
+ * partials and the result, about 8.4 KB on each GPU it runs on, kept until the
+ * process ends); the call allocates nothing. Calls that overlap on one GPU
+ * share that array and race. Returns CHAIN_ENONFINITE (with *e_out set) for a
+ * NaN or infinite energy, CHAIN_EDEVICE on a device other than gfx950.
+ */
+int chain_rk4_energy_noalloc(int32_t model, int32_t prec, int64_t n, const void *q,
+                             const void *p, const void *cq, const void *cp, void *stream,
+                             double *e_out);
+
 /* Replace the stream used by later calls on this handle. */
 int chain_rk4_set_stream(chain_rk4 *h, void *stream);
 

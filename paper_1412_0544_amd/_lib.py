@@ -90,6 +90,9 @@ def _declare(lib):
         "chain_rk4_set_tableau": (ctypes.c_int, [H, ctypes.POINTER(Tableau)]),
         "chain_rk4_tableau_reach": (ctypes.c_int64, [ctypes.c_int32, ctypes.POINTER(Tableau)]),
         "chain_rk4_energy": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
+        "chain_rk4_energy_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_int64, VP, VP, VP, VP, VP,
+                                                    ctypes.POINTER(ctypes.c_double)]),
         "chain_rk4_set_stream": (ctypes.c_int, [H, VP]),
         "chain_rk4_get_plan": (ctypes.c_int, [H, ctypes.POINTER(Plan)]),
         "chain_rk4_plan_for": (ctypes.c_int, [D, ctypes.POINTER(Tableau), ctypes.POINTER(Plan)]),

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libchainrk4.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["fused.hip", "persistent.hip", "naive.hip", "energy.hip", "roessler.hip", "tableau.hip",
-           "chain_rk4.cpp", "batch.cpp"]
+           "noalloc.hip", "chain_rk4.cpp", "batch.cpp"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -257,3 +257,18 @@ class RoesslerChain:
             self.close()
         except Exception:
             pass
+
+
+def energy_noalloc(q: torch.Tensor, p: torch.Tensor, model="quartic", prec="fp64", cq=None,
+                   cp=None, stream: torch.cuda.Stream | None = None) -> float:
+    """Energy of a state in device tensors without a handle or workspace
+    (``chain_rk4_energy_noalloc``: the library allocates nothing); the same
+    bits as ``Chain.energy`` over the same state."""
+    stream = stream if stream is not None else torch.cuda.current_stream(q.device)
+    ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+    e = ctypes.c_double()
+    L.check(L.lib().chain_rk4_energy_noalloc(_code(MODELS, model), _code(PRECS, prec), q.numel(),
+                                             ptr(q), ptr(p), ptr(cq), ptr(cp), stream.cuda_stream,
+                                             ctypes.byref(e)),
+            "chain_rk4_energy_noalloc")
+    return e.value
