@@ -71,9 +71,9 @@ BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 # the kernel sources with this sha256 and this cluster shape (sites per lane,
 # wavefronts per cluster, halo) on N = 2^24.
 MEASURED_TRAFFIC = {
-    "sha256": "f8839edcbcd4ec669bb30b825d5aef8f9a22b87d96bab6d6ad5c13a937221cc9",
+    "sha256": "efc0ea5dfde1634b7e78bf3d8e732e3b13150e721146d8020af97fbaa262579b",
     "shape": (8, 4, 64), "n": 1 << 24,
-    "bytes_per_launch": 555337673, "fetch_factor": 0.5000, "write_factor": 1.0000,
+    "bytes_per_launch": 555324021, "fetch_factor": 0.5000, "write_factor": 1.0000,
 }
 
 
@@ -561,8 +561,9 @@ def variant_batch(dt, dev, steps=2000, count=4096, precs=("fp64", "fp32_kahan"),
                   shape=None, host_ics=False):
     """4096 chains, lengths log-uniform in [256, 65536], one persistent
     launch of `steps` steps, FP64 and FP32 with compensated update, at the
-    shape the batch autotuner picks; with `extras`, also the resident-ring
-    form and one step call per chain."""
+    shape the batch autotuner picks, and the same launch with wide clusters
+    only; with `extras`, also the resident-ring form and one step call per
+    chain."""
     import torch
     import workloads
     from paper_1412_0544_amd import Batch, Chain, autotune
@@ -596,11 +597,23 @@ def variant_batch(dt, dev, steps=2000, count=4096, precs=("fp64", "fp32_kahan"),
         peak = VALU_PEAK_TOPS if prec == "fp64" else FP32_VALU_PEAK_TOPS
         a = ops * tot * steps / t / 1e12
         E = 64 * S * plan["waves_per_cluster"]
+        nar = plan["narrow_clusters"]
+        lane_sites = (plan["total_clusters"] - nar) * E + nar * 64 * S
+        # the same launch with wide clusters only (no one-wavefront clusters)
+        bw = Batch(chains, max_steps=steps, sites_per_lane=S, kdepth=K, flags=L.CHAIN_BATCH_WIDE_ONLY)
+        bw.step(24)
+        bw.check()
+        tw = ev_seconds(lambda: bw.step(steps), chains[0].stream)
+        bw.check()
+        pw = bw.plan()
+        bw.close()
         out[prec] = {"su_per_s": tot * steps / t, "ms": t * 1e3, "sites_per_lane": S,
                      "kdepth": K, "grid_blocks": plan["grid_blocks"],
                      "resident_chains": plan["resident_chains"],
-                     "clusters": plan["total_clusters"],
-                     "kept_lane_site_frac": tot / (plan["total_clusters"] * E),
+                     "clusters": plan["total_clusters"], "narrow_clusters": nar,
+                     "kept_lane_site_frac": tot / lane_sites,
+                     "wide_only": {"su_per_s": tot * steps / tw, "clusters": pw["total_clusters"],
+                                   "kept_lane_site_frac": tot / (pw["total_clusters"] * E)},
                      "roofline": {"bound": "alu", "achieved": a, "peak": peak, "unit": "Tops/s",
                                   "frac": a / peak, "ops_per_su": ops,
                                   "timed": "device time of one persistent launch"}}
@@ -746,12 +759,32 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, 
         return {"steps_per_s": steps / w, "su_per_s": n * steps / w,
                 "device_steps_per_s": steps / g, "device_su_per_s": n * steps / g,
                 "plan": {k: plan[k] for k in ("sites_per_lane", "waves_per_cluster", "kdepth",
-                                              "tile", "halo")}}
+                                              "tile", "halo", "waves", "exchange")}}
 
     out = {"n": n, "steps": steps, "trials": trials, "dt": dt}
     log("[bench] Roessler: library plan")
     out["fused"] = measure()
     out["fused_graph"] = measure(graph=True)
+    # the whole chain held in registers for each call, clusters swapping only
+    # edge sites between passes (one launch per call); where the chain fits
+    from paper_1412_0544_amd import ChainError
+    try:
+        out["exchange"] = measure(exchange=True)
+        x = out["exchange"]
+        out["exchange"]["roofline"] = roofline(n, steps, n * steps / x["device_su_per_s"],
+                                               model="roessler")
+        if sweep:
+            xt = {}
+            for w in (4, 8):
+                for k in (6, 8, 10, 13, 17, 25, 32):
+                    try:
+                        xt[f"s4_w{w}_k{k}"] = measure(sites_per_lane=4, waves_per_cluster=w,
+                                                      kdepth=k, exchange=True)["device_su_per_s"]
+                    except ChainError:
+                        pass
+            out["exchange_shapes_device_su_per_s"] = xt
+    except ChainError as e:
+        out["exchange"] = {"not_held": str(e)}
     log("[bench] Roessler: per-stage baseline")
     out["naive"] = measure(method="naive")
     table = {}

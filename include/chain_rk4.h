@@ -340,13 +340,18 @@ const char *chain_rk4_last_error(void);
  * The launch holds as many workgroups as the device keeps resident. They
  * claim work items in a fixed order from a device counter: with
  * CHAIN_BATCH_RESIDENT_RINGS, first one item per short ring (n <= 1024), which
- * stays on chip for all of its steps; then, pass by pass, one item per
- * (chain, cluster), each the same cluster pass as
- * the fused method (a cluster of 64*sites_per_lane*4 sites, 2*kdepth of them
- * recomputed per side, Sec. 2.3). A cluster's pass e starts once its own
- * cluster and its two neighbours have finished pass e-1 (per-cluster progress
- * flags), so passes of different clusters and chains overlap. Every chain
- * gives the same bits as when stepped alone (any handle settings, any grid).
+ * stays on chip for all of its steps; then, pass by pass, the cluster items,
+ * each cluster pass the same as the fused method's (2*kdepth sites, rounded
+ * up to 4, recomputed per side, Sec. 2.3). A chain is cut into wide clusters
+ * of 64*sites_per_lane*4 sites (one workgroup of four wavefronts) followed by
+ * at most three narrow clusters of 64*sites_per_lane sites (one wavefront),
+ * whichever mix covers it in the fewest lane-sites; the last wide cluster of a
+ * chain would otherwise keep only its remainder, and a short chain would fill
+ * a quarter of a wide cluster. An item is one wide cluster or a pack of up to
+ * four narrow clusters. A cluster's pass e starts once its own cluster and its
+ * two neighbours have finished pass e-1 (per-cluster progress flags), so
+ * passes of different clusters and chains overlap. Every chain gives the same
+ * bits as when stepped alone (any handle settings, any grid, either cut).
  *
  * All handles of a batch share one model (CHAIN_QUARTIC or CHAIN_HARMONIC)
  * and one precision, use CHAIN_FUSED with CHAIN_SCHEME_RK4 (a handle given a
@@ -365,11 +370,13 @@ enum chain_batch_flags {
                                        ordinary loads and stores plus agent-scope
                                        cache write-back and invalidation, instead
                                        of device-coherent loads and stores */
-    CHAIN_BATCH_RESIDENT_RINGS = 2  /* keep rings of at most 1024 sites on chip
+    CHAIN_BATCH_RESIDENT_RINGS = 2, /* keep rings of at most 1024 sites on chip
                                        for all their steps (one item each, first);
                                        without it every chain is tiled, and the
                                        launch uses a kernel without the resident
                                        path (fewer registers, more wavefronts) */
+    CHAIN_BATCH_WIDE_ONLY = 4       /* cut chains into wide clusters only (no
+                                       narrow ones); the same results */
 };
 
 typedef struct chain_rk4_batch_desc {
@@ -380,7 +387,7 @@ typedef struct chain_rk4_batch_desc {
     int32_t kdepth;          /* steps per pass, 0 = default (32), else 2..32 */
     int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
                                 once; any value >= 1 gives the same results */
-    int32_t flags;           /* 0, or CHAIN_BATCH_FENCES */
+    int32_t flags;           /* 0, or CHAIN_BATCH_* flags OR-ed */
     int32_t spin_limit;      /* polls before a wait for a neighbour gives up,
                                 0 = default (about 4 s); small values force
                                 CHAIN_ETIMEOUT for failure-path tests */
@@ -394,9 +401,14 @@ typedef struct chain_rk4_batch_plan {
                                 rounded up to a multiple of 4 (tiles start at
                                 multiples of 4 sites, so every cluster starts
                                 on a 16-byte boundary) */
-    int64_t tile_max;        /* most sites a cluster keeps per pass */
+    int64_t tile_max;        /* most sites a wide cluster keeps per pass */
     int64_t total_clusters;  /* clusters over all tiled chains */
     int64_t resident_chains; /* chains kept on chip for a whole launch */
+    int64_t tile_narrow;     /* most sites a narrow cluster keeps per pass; 0 if
+                                the shape has no narrow clusters (a one-wavefront
+                                cluster must keep at least `halo` sites after its
+                                two halos, or with CHAIN_BATCH_WIDE_ONLY) */
+    int64_t narrow_clusters; /* of total_clusters, the narrow ones */
 } chain_rk4_batch_plan;
 
 /* Device workspace bytes (256-byte aligned) of a batch over hs[0..count):
@@ -420,16 +432,32 @@ int chain_rk4_batch_create(chain_rk4 *const *hs, int count, const chain_rk4_batc
 int chain_rk4_batch_rebind(chain_rk4_batch *b, chain_rk4 *const *hs, int count);
 
 /* The shape a batch with descriptor `d` would use (sites_per_lane, kdepth,
- * waves_per_cluster, halo, tile_max; grid_blocks as given, 0 = as many as the
- * device holds; the cluster counts are 0), without a GPU or handles.
+ * waves_per_cluster, halo, tile_max, tile_narrow; grid_blocks as given, 0 = as
+ * many as the device holds; the cluster counts are 0), without a GPU or
+ * handles.
  * CHAIN_EINVAL for a descriptor chain_rk4_batch_create would reject. */
 int chain_rk4_batch_plan_for(const chain_rk4_batch_desc *d, chain_rk4_batch_plan *out);
 
 /* Clusters a chain of n sites occupies in a batch of the given shape
  * (sites_per_lane and kdepth as in the descriptor, 0 = default) when it is
- * tiled; a ring kept on chip (CHAIN_BATCH_RESIDENT_RINGS) takes none. 0 for
+ * tiled, wide and narrow ones (the cut without narrow clusters never has
+ * more); a ring kept on chip (CHAIN_BATCH_RESIDENT_RINGS) takes none. 0 for
  * invalid arguments. Used to size max_clusters. */
 int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdepth);
+
+/*
+ * How a tiled chain of n sites is cut in a batch with descriptor `d` (only
+ * sites_per_lane, kdepth and flags are read): cluster i keeps the sites
+ * [start[i], start[i] + keep[i]) and spans waves[i] wavefronts (4: wide, 1:
+ * narrow). Fills the first min(count, cap) entries of the three arrays (host
+ * memory, owned by the caller; NULL allowed when cap is 0) and returns count,
+ * the number of clusters, or -1 with the last error set for invalid
+ * arguments. Every start is a multiple of 4, the kept ranges tile [0, n) in
+ * order, and with two or more clusters each keeps at least `halo` sites (its
+ * neighbours' halos then lie in the adjacent clusters only).
+ */
+int64_t chain_rk4_batch_layout(int64_t n, const chain_rk4_batch_desc *d, int64_t *start,
+                               int64_t *keep, int32_t *waves, int64_t cap);
 
 /* Advance chain j by nsteps[j] (0..max_steps) steps in one persistent launch
  * (asynchronous; nsteps is read before the call returns). */

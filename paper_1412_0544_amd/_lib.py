@@ -17,7 +17,7 @@ CHAIN_FP64, CHAIN_FP32_KAHAN, CHAIN_FP32_KAHAN64, CHAIN_FP32 = 0, 1, 2, 3
 CHAIN_FUSED, CHAIN_NAIVE = 0, 1
 CHAIN_FLAG_GRAPH, CHAIN_FLAG_NO_RESIDENT, CHAIN_FLAG_RESIDENT = 1, 2, 4
 CHAIN_FLAG_EXCHANGE = 8
-CHAIN_BATCH_FENCES, CHAIN_BATCH_RESIDENT_RINGS = 1, 2
+CHAIN_BATCH_FENCES, CHAIN_BATCH_RESIDENT_RINGS, CHAIN_BATCH_WIDE_ONLY = 1, 2, 4
 CHAIN_SCHEME_RK4, CHAIN_SCHEME_TABLEAU = 0, 1
 CHAIN_MAX_STAGES = 8
 
@@ -63,7 +63,8 @@ class BatchPlan(ctypes.Structure):
     _fields_ = [("sites_per_lane", ctypes.c_int32), ("kdepth", ctypes.c_int32),
                 ("waves_per_cluster", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("halo", ctypes.c_int64), ("tile_max", ctypes.c_int64),
-                ("total_clusters", ctypes.c_int64), ("resident_chains", ctypes.c_int64)]
+                ("total_clusters", ctypes.c_int64), ("resident_chains", ctypes.c_int64),
+                ("tile_narrow", ctypes.c_int64), ("narrow_clusters", ctypes.c_int64)]
 
 
 class ChainError(RuntimeError):
@@ -112,6 +113,10 @@ def _declare(lib):
         "chain_rk4_batch_check": (ctypes.c_int, [VP]),
         "chain_rk4_batch_last_launch": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_int64)]),
         "chain_rk4_batch_check_launch": (ctypes.c_int, [VP, ctypes.c_int64]),
+        "chain_rk4_batch_layout": (ctypes.c_int64, [ctypes.c_int64, ctypes.POINTER(BatchDesc),
+                                                    ctypes.POINTER(ctypes.c_int64),
+                                                    ctypes.POINTER(ctypes.c_int64),
+                                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]),
         "chain_rk4_batch_plan_for": (ctypes.c_int, [ctypes.POINTER(BatchDesc),
                                                     ctypes.POINTER(BatchPlan)]),
         "chain_rk4_batch_energy": (ctypes.c_int, [VP, ctypes.POINTER(ctypes.c_double)]),

@@ -95,6 +95,21 @@ class Batch:
                 "chain_rk4_batch_plan_for")
         return {k: getattr(P, k) for k, _ in L.BatchPlan._fields_}
 
+    @staticmethod
+    def layout(n: int, sites_per_lane: int = 0, kdepth: int = 0, flags: int = 0) -> list:
+        """How a tiled chain of n sites is cut: (start, keep, wavefronts) per
+        cluster (no GPU needed)."""
+        d = L.BatchDesc(0, 0, int(sites_per_lane), int(kdepth), 0, int(flags), 0, 0)
+        lib = L.lib()
+        count = lib.chain_rk4_batch_layout(int(n), ctypes.byref(d), None, None, None, 0)
+        if count < 0:
+            L.check(L.CHAIN_EINVAL, "chain_rk4_batch_layout")
+        start = (ctypes.c_int64 * count)()
+        keep = (ctypes.c_int64 * count)()
+        waves = (ctypes.c_int32 * count)()
+        lib.chain_rk4_batch_layout(int(n), ctypes.byref(d), start, keep, waves, count)
+        return [(int(start[i]), int(keep[i]), int(waves[i])) for i in range(count)]
+
     def energies(self) -> list[float]:
         n = len(self.chains)
         out = (ctypes.c_double * n)()

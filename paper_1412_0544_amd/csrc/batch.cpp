@@ -58,17 +58,6 @@ PassList make_passes(int64_t nsteps, int depth) {
     return L;
 }
 
-// Clusters of a tiled chain: keep at most `tile_max` sites each, in 4-site
-// units split as evenly as possible.
-void split_clusters(int64_t n, int64_t tile_max, int64_t *clusters, int64_t *uq, int64_t *ur) {
-    int64_t G = (n + (tile_max - 4) - 1) / (tile_max - 4);
-    if (G < 1) G = 1;
-    const int64_t units = n / 4;
-    *clusters = G;
-    *uq = units / G;
-    *ur = units % G;
-}
-
 struct Layout {
     size_t flags, counter, error, zero_bytes;  // zeroed before each launch
     size_t chains, item_chain, item_cluster, pass_off, table_bytes;
@@ -79,10 +68,11 @@ struct Layout {
 struct Shape {
     int sites = 0, depth = 0;
     int64_t halo = 0, tile_max = 0;
+    int64_t tile_narrow = 0;       // 0: no narrow clusters
     bool resident_rings = false;   // CHAIN_BATCH_RESIDENT_RINGS
 };
 
-int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
+int make_shape(int32_t sites_per_lane, int32_t kdepth, int32_t flags, Shape *out) {
     if (sites_per_lane != 0 && sites_per_lane != 4 && sites_per_lane != 8 && sites_per_lane != 16)
         return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 4, 8 or 16");
     if (kdepth != 0 && (kdepth < 2 || kdepth > 32))
@@ -91,6 +81,7 @@ int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
     sh.sites = sites_per_lane ? sites_per_lane : kDefaultBatchSites;
     sh.depth = kdepth ? kdepth : kDefaultBatchDepth;
     const int64_t E = 64 * static_cast<int64_t>(sh.sites) * kBatchWaves;
+    const int64_t E1 = 64 * static_cast<int64_t>(sh.sites);
     // A step's wrong edge values travel 2 sites into a cluster of the
     // quartic or harmonic chain (dq/dt = p is local), so the halo covers
     // 2*depth sites, rounded up to 4: cluster tiles start at multiples of 4
@@ -103,15 +94,78 @@ int make_shape(int32_t sites_per_lane, int32_t kdepth, Shape *out) {
     while (E < 4 * halo_of(sh.depth) + 16 && sh.depth > 2) --sh.depth;
     sh.halo = halo_of(sh.depth);
     sh.tile_max = E - 2 * sh.halo;
+    if (!(flags & CHAIN_BATCH_WIDE_ONLY) && E1 >= 4 * sh.halo + 16) sh.tile_narrow = E1 - 2 * sh.halo;
+    sh.resident_rings = (flags & CHAIN_BATCH_RESIDENT_RINGS) != 0;
     *out = sh;
     return CHAIN_OK;
 }
 
+// How a tiled chain is cut: `wide` clusters keeping 4*(uq + (i < ur)) sites,
+// then `narrow` ones keeping 4*(nuq + (j < nur)); the last cluster also keeps
+// the n % 4 remainder.
+struct Cut {
+    int64_t wide = 0, narrow = 0, uq = 0, ur = 0, nuq = 0, nur = 0;
+    int64_t clusters() const { return wide + narrow; }
+};
+
+// The cut of n sites in the fewest lane-sites (ties: fewer clusters). A
+// cluster holds at most cap = tile/4 - 1 units of 4 sites (room for the
+// remainder) and, when the chain has two or more clusters, at least halo/4
+// (each neighbour's halo then lies in the adjacent cluster). Four narrow
+// clusters cost one wide one and hold less, so at most three are used.
+Cut cut_chain(int64_t n, const Shape &sh) {
+    const int64_t E4 = 64 * static_cast<int64_t>(sh.sites) * kBatchWaves;
+    const int64_t E1 = 64 * static_cast<int64_t>(sh.sites);
+    const int64_t U = n / 4, c4 = sh.tile_max / 4 - 1, m = sh.halo / 4;
+    const int64_t c1 = sh.tile_narrow ? sh.tile_narrow / 4 - 1 : 0;
+    Cut best;
+    int64_t best_cost = -1;
+    for (int64_t g1 = 0; g1 <= (sh.tile_narrow ? kMaxNarrow : 0); ++g1) {
+        int64_t g4 = U > g1 * c1 ? (U - g1 * c1 + c4 - 1) / c4 : 0;
+        if (g4 + g1 == 0) g4 = 1;  // n < 4: one wide cluster
+        const int64_t G = g4 + g1;
+        if (G >= 2 && U < G * m) continue;
+        const int64_t cost = g4 * E4 + g1 * E1;
+        if (best_cost >= 0 && (cost > best_cost || (cost == best_cost && G >= best.clusters())))
+            continue;
+        // narrow clusters take what the wide ones cannot hold, but at least
+        // the minimum each; with G >= 2 the wide ones then keep >= m each
+        const int64_t u1 = g1 ? std::max(g1 * m, U - g4 * c4) : 0;
+        const int64_t u4 = U - u1;
+        Cut c;
+        c.wide = g4;
+        c.narrow = g1;
+        if (g4) {
+            c.uq = u4 / g4;
+            c.ur = u4 % g4;
+        }
+        if (g1) {
+            c.nuq = u1 / g1;
+            c.nur = u1 % g1;
+        }
+        best = c;
+        best_cost = cost;
+    }
+    return best;
+}
+
+// Kept range of cluster i of a cut (the same arithmetic as the kernel's).
+void cluster_span(const Cut &c, int64_t n, int64_t i, int64_t *start, int64_t *keep) {
+    int64_t units;
+    if (i < c.wide) {
+        *start = 4 * (i * c.uq + std::min(i, c.ur));
+        units = c.uq + (i < c.ur ? 1 : 0);
+    } else {
+        const int64_t j = i - c.wide;
+        *start = 4 * (c.wide * c.uq + c.ur + j * c.nuq + std::min(j, c.nur));
+        units = c.nuq + (j < c.nur ? 1 : 0);
+    }
+    *keep = (i == c.clusters() - 1) ? n - *start : 4 * units;
+}
+
 int64_t clusters_of(int64_t n, const Shape &sh) {
     if (sh.resident_rings && n <= kBatchResidentSites) return 0;
-    int64_t G, uq, ur;
-    split_clusters(n, sh.tile_max, &G, &uq, &ur);
-    return G;
+    return cut_chain(n, sh).clusters();
 }
 
 // Validate a handle set against a batch's model and precision.
@@ -141,14 +195,12 @@ int check_desc(const chain_rk4_batch_desc *d, Shape *sh) {
     if (!d) return fail(CHAIN_EINVAL, "batch descriptor is NULL");
     if (d->max_steps < 0) return fail(CHAIN_EINVAL, "max_steps must be >= 0");
     if (d->grid_blocks < 0) return fail(CHAIN_EINVAL, "grid_blocks must be >= 0");
-    if ((d->flags & ~(CHAIN_BATCH_FENCES | CHAIN_BATCH_RESIDENT_RINGS)) != 0)
+    if ((d->flags & ~(CHAIN_BATCH_FENCES | CHAIN_BATCH_RESIDENT_RINGS | CHAIN_BATCH_WIDE_ONLY)) != 0)
         return fail(CHAIN_EINVAL, "unknown batch flags");
     if (d->spin_limit < 0) return fail(CHAIN_EINVAL, "spin_limit must be >= 0");
     if (d->max_chains < 0 || d->max_clusters < 0)
         return fail(CHAIN_EINVAL, "max_chains and max_clusters must be >= 0");
-    int rc = make_shape(d->sites_per_lane, d->kdepth, sh);
-    sh->resident_rings = (d->flags & CHAIN_BATCH_RESIDENT_RINGS) != 0;
-    return rc;
+    return make_shape(d->sites_per_lane, d->kdepth, d->flags, sh);
 }
 
 Layout batch_layout(int64_t chains, int64_t clusters, int64_t max_passes) {
@@ -166,8 +218,9 @@ Layout batch_layout(int64_t chains, int64_t clusters, int64_t max_passes) {
     L.zero_bytes = off;
     const size_t t0 = off;
     L.chains = take(sizeof(BatchChain) * static_cast<size_t>(chains));
-    L.item_chain = take(sizeof(int32_t) * nc);
-    L.item_cluster = take(sizeof(int32_t) * nc);
+    // at most one item per cluster, kBatchWaves slots each
+    L.item_chain = take(sizeof(int32_t) * kBatchWaves * nc);
+    L.item_cluster = take(sizeof(int32_t) * kBatchWaves * nc);
     L.pass_off = take(sizeof(int64_t) * static_cast<size_t>(max_passes + 2));
     L.table_bytes = off - t0;
     L.total = off;
@@ -207,8 +260,8 @@ struct chain_rk4_batch {
     bool pending_error = false;    // a launch since the last check timed out
     // per chain of the current set
     std::vector<char> resident;
-    std::vector<int64_t> clusters, uq, ur;
-    int64_t total_clusters = 0;
+    std::vector<Cut> cuts;
+    int64_t total_clusters = 0, narrow_clusters = 0;
 };
 
 namespace {
@@ -216,18 +269,18 @@ namespace {
 void bind(chain_rk4_batch *b, chain_rk4 *const *hs, int count) {
     b->hs.assign(hs, hs + count);
     b->resident.assign(count, 0);
-    b->clusters.assign(count, 0);
-    b->uq.assign(count, 0);
-    b->ur.assign(count, 0);
+    b->cuts.assign(count, Cut{});
     b->total_clusters = 0;
+    b->narrow_clusters = 0;
     for (int i = 0; i < count; ++i) {
         const int64_t n = hs[i]->d.n;
         if (b->sh.resident_rings && n <= kBatchResidentSites) {
             b->resident[i] = 1;
             continue;
         }
-        split_clusters(n, b->sh.tile_max, &b->clusters[i], &b->uq[i], &b->ur[i]);
-        b->total_clusters += b->clusters[i];
+        b->cuts[i] = cut_chain(n, b->sh);
+        b->total_clusters += b->cuts[i].clusters();
+        b->narrow_clusters += b->cuts[i].narrow;
     }
 }
 
@@ -261,14 +314,39 @@ int chain_rk4_batch_plan_for(const chain_rk4_batch_desc *d, chain_rk4_batch_plan
     P.grid_blocks = d->grid_blocks;
     P.halo = sh.halo;
     P.tile_max = sh.tile_max;
+    P.tile_narrow = sh.tile_narrow;
     *out = P;
     return CHAIN_OK;
 }
 
 int64_t chain_rk4_batch_clusters(int64_t n, int32_t sites_per_lane, int32_t kdepth) {
     Shape sh;
-    if (n < 1 || make_shape(sites_per_lane, kdepth, &sh) != CHAIN_OK) return 0;
+    if (n < 1 || make_shape(sites_per_lane, kdepth, 0, &sh) != CHAIN_OK) return 0;
     return clusters_of(n, sh);
+}
+
+int64_t chain_rk4_batch_layout(int64_t n, const chain_rk4_batch_desc *d, int64_t *start,
+                               int64_t *keep, int32_t *waves, int64_t cap) {
+    if (!d) {
+        fail(CHAIN_EINVAL, "batch descriptor is NULL");
+        return -1;
+    }
+    if (n < 1) {
+        fail(CHAIN_EINVAL, "n must be >= 1");
+        return -1;
+    }
+    if (cap < 0 || (cap > 0 && (!start || !keep || !waves))) {
+        fail(CHAIN_EINVAL, "cap must be >= 0, and the arrays non-NULL when cap > 0");
+        return -1;
+    }
+    Shape sh;
+    if (make_shape(d->sites_per_lane, d->kdepth, d->flags, &sh) != CHAIN_OK) return -1;
+    const Cut c = cut_chain(n, sh);
+    for (int64_t i = 0; i < c.clusters() && i < cap; ++i) {
+        cluster_span(c, n, i, &start[i], &keep[i]);
+        waves[i] = i < c.wide ? kBatchWaves : 1;
+    }
+    return c.clusters();
 }
 
 size_t chain_rk4_batch_workspace_bytes(chain_rk4 *const *hs, int count,
@@ -381,32 +459,59 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
     int32_t *item_cluster = reinterpret_cast<int32_t *>(host + (b->L.item_cluster - t0));
     int64_t *pass_off = reinterpret_cast<int64_t *>(host + (b->L.pass_off - t0));
 
+    // Items in chain order: a chain's wide clusters, then its narrow ones
+    // into the open pack (a pack opened by an earlier chain, else a new one
+    // at this point). Every item's first chain is then no later than any
+    // item after it, so the items whose first chain still runs at pass e
+    // are a prefix of the table (first[k]: items before chain k's).
     int64_t w = 0, flag = 0, slot = 0;
+    int64_t pack = -1, pack_used = 0;  // open pack: item index, slots taken
+    std::vector<int64_t> first(tiled.size() + 1, 0);
     for (int64_t i : tiled) {
         chain_rk4 *h = b->hs[i];
+        const Cut &cut = b->cuts[i];
         BatchChain c{};
         c.front = h->front;
         c.back = h->back;
         c.n = h->d.n;
         c.dt = h->d.dt;
-        c.uq = b->uq[i];
-        c.ur = b->ur[i];
-        c.clusters = static_cast<int32_t>(b->clusters[i]);
+        c.uq = cut.uq;
+        c.ur = cut.ur;
+        c.wide = static_cast<int32_t>(cut.wide);
+        c.nuq = static_cast<int32_t>(cut.nuq);
+        c.nur = static_cast<int32_t>(cut.nur);
+        c.clusters = static_cast<int32_t>(cut.clusters());
         c.passes = static_cast<int32_t>(passes[i].count());
         c.nhead = passes[i].nhead;
         c.head0 = passes[i].head0;
         c.head1 = passes[i].head1;
         c.tail = passes[i].tail;
         c.flag_base = static_cast<int32_t>(flag);
-        for (int64_t g = 0; g < b->clusters[i]; ++g) {
-            item_chain[w] = static_cast<int32_t>(slot);
-            item_cluster[w] = static_cast<int32_t>(g);
+        first[slot] = w;
+        for (int64_t g = 0; g < cut.wide; ++g) {
+            item_chain[kBatchWaves * w] = static_cast<int32_t>(slot);
+            item_cluster[kBatchWaves * w] = static_cast<int32_t>(g);
+            item_chain[kBatchWaves * w + 1] = kWideItem;
             ++w;
         }
-        flag += b->clusters[i];
+        for (int64_t g = cut.wide; g < cut.clusters(); ++g) {
+            if (pack < 0 || pack_used == kBatchWaves) {
+                pack = w++;
+                pack_used = 0;
+                for (int v = 0; v < kBatchWaves; ++v) {
+                    item_chain[kBatchWaves * pack + v] = kEmptySlot;
+                    item_cluster[kBatchWaves * pack + v] = 0;
+                }
+            }
+            item_chain[kBatchWaves * pack + pack_used] = static_cast<int32_t>(slot);
+            item_cluster[kBatchWaves * pack + pack_used] = static_cast<int32_t>(g);
+            ++pack_used;
+        }
+        flag += cut.clusters();
         chains[slot++] = c;
     }
     const int64_t n_tiled = slot;
+    first[n_tiled] = w;
     for (int64_t i : res) {
         chain_rk4 *h = b->hs[i];
         BatchChain c{};
@@ -417,17 +522,16 @@ int chain_rk4_batch_step(chain_rk4_batch *b, const int64_t *nsteps) {
         c.nsteps = nsteps[i];
         chains[slot++] = c;
     }
-    // pass_off[e]: items before pass e (a pass holds the clusters of the
-    // chains with more than e passes, a prefix of the ordered list)
+    // pass_off[e]: items before pass e. Pass e holds the items whose first
+    // chain has more than e passes (chains are ordered by pass count); a
+    // pack slot whose chain has no pass e left is skipped by its wavefront.
     const int64_t max_p = tiled.empty() ? 0 : passes[tiled[0]].count();
     pass_off[0] = 0;
     {
         int64_t active = n_tiled, acc = 0;
-        std::vector<int64_t> prefix(n_tiled + 1, 0);
-        for (int64_t k = 0; k < n_tiled; ++k) prefix[k + 1] = prefix[k] + chains[k].clusters;
         for (int64_t e = 0; e < max_p; ++e) {
             while (active > 0 && chains[active - 1].passes <= e) --active;
-            acc += prefix[active];
+            acc += first[active];
             pass_off[e + 1] = acc;
         }
         pass_off[max_p + 1] = acc + 1;  // sentinel for the forward scan
@@ -552,7 +656,9 @@ int chain_rk4_batch_get_plan(const chain_rk4_batch *b, chain_rk4_batch_plan *out
                                                            has_resident_items(b));
     P.halo = b->sh.halo;
     P.tile_max = b->sh.tile_max;
+    P.tile_narrow = b->sh.tile_narrow;
     P.total_clusters = b->total_clusters;
+    P.narrow_clusters = b->narrow_clusters;
     int64_t nres = 0;
     for (char r : b->resident) nres += r;
     P.resident_chains = nres;

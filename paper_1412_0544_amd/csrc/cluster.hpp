@@ -273,6 +273,38 @@ __device__ __forceinline__ void store_coherent(R *p, R v) {
     __hip_atomic_store((global_ptr<R>)(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Device-coherent 16-byte stores. The agent-scope relaxed atomics above are
+// at most 8 bytes wide, and an 8-byte store each costs a 32-byte memory
+// transaction (the batch kernel's stores counted 4x their bytes); a
+// buffer store with the device-scope cache policy (sc1, the same policy
+// those atomics carry) moves 16 bytes at once. The resource covers one
+// cluster's window, so a store can never reach outside it (a buffer access
+// beyond the resource is dropped).
+constexpr int kRawBufferWord3 = 0x00020000;  // 32-bit data, untyped accesses (gfx9 family)
+constexpr int kDeviceCoherent = 16;          // cache policy bit sc1: device scope
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t window_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, kRawBufferWord3);
+}
+
+// Store a lane's S values at byte offset `off` of the window, 16 bytes at a time.
+template <class R, int S>
+__device__ __forceinline__ void store_window(__amdgpu_buffer_rsrc_t r, int off, const R (&src)[S]) {
+    static_assert((S * sizeof(R)) % 16 == 0, "whole 16-byte vectors");
+    constexpr int P = 16 / sizeof(R);
+    using U4 = __attribute__((ext_vector_type(4))) unsigned;
+#pragma unroll
+    for (int m = 0; m < S / P; ++m) {
+        U4 v;
+        if constexpr (P == 2)
+            v = __builtin_bit_cast(U4, make_double2(src[2 * m], src[2 * m + 1]));
+        else
+            v = __builtin_bit_cast(U4, make_float4(src[4 * m], src[4 * m + 1], src[4 * m + 2],
+                                                   src[4 * m + 3]));
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, off + 16 * m, 0, kDeviceCoherent);
+    }
+}
+
 // Progress flags of clusters handing data to each other inside one launch.
 __device__ __forceinline__ int load_flag(const int32_t *f) {
     return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -312,9 +344,20 @@ struct LaneState {
     C cq[KAHAN ? S : 1], cp[KAHAN ? S : 1];   // carries of the compensated update
 };
 
+// Whether the device-coherent accesses of a lane's S sites can go 16 bytes
+// at a time (state and carries in whole 16-byte vectors).
+template <class R, bool KAHAN, int S, class C>
+constexpr bool coherent_vectors() {
+    return (S * sizeof(R)) % 16 == 0 && (!KAHAN || (S * sizeof(C)) % 16 == 0);
+}
+
 // Load this lane's S sites, starting at unwrapped site s0 of a ring of n
 // sites. `contiguous` (uniform over the cluster) says the cluster's sites
-// need no wrap, so vector loads apply.
+// need no wrap, so vector loads apply. The device-coherent form (COH) loads
+// 8 bytes at a time: 16-byte loads would need their four destination
+// registers adjacent, which the state carried through the step loop then
+// keeps (that cost the 8-site FP64 batch kernel 16 registers), and the loads'
+// neighbouring sectors are served from L2 anyway.
 template <class R, bool KAHAN, int S, bool COH = false, class C = float>
 __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S, C> &st, const StateRef &in,
                                           int64_t n, int64_t s0, bool contiguous) {
@@ -373,7 +416,7 @@ __device__ __forceinline__ void load_lane(LaneState<R, KAHAN, S, C> &st, const S
 template <class R, bool KAHAN, int S, bool COH = false, class C = float>
 __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, const StateRef &out,
                                            int64_t n, int64_t s0, int lo, int64_t keep_lo,
-                                           int64_t keep_hi) {
+                                           int64_t keep_hi, int window = 0) {
     R *qout = static_cast<R *>(out.q);
     R *pout = static_cast<R *>(out.p);
     C *cqout = static_cast<C *>(out.cq);
@@ -384,6 +427,24 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, 
     const int j0 = static_cast<int>(keep_lo - lo < 0 ? 0 : (keep_lo - lo > S ? S : keep_lo - lo));
     const int64_t end = (keep_hi - lo < n - s0) ? keep_hi - lo : n - s0;
     const int j1 = static_cast<int>(end < 0 ? 0 : (end > S ? S : end));
+    if constexpr (COH && coherent_vectors<R, KAHAN, S, C>()) {
+        // kept sites never wrap: the window from the cluster origin s0 - lo
+        // is contiguous up to every kept site
+        if (j0 == 0 && j1 == S) {
+            // the resource spans the cluster's window from its origin (which
+            // may lie before the array: only kept sites, inside it, are written)
+            const int64_t e0 = s0 - lo;
+            store_window<R, S>(window_rsrc(qout + e0, window * sizeof(R)), lo * sizeof(R), st.q);
+            store_window<R, S>(window_rsrc(pout + e0, window * sizeof(R)), lo * sizeof(R), st.p);
+            if constexpr (KAHAN) {
+                store_window<C, S>(window_rsrc(cqout + e0, window * sizeof(C)), lo * sizeof(C),
+                                   st.cq);
+                store_window<C, S>(window_rsrc(cpout + e0, window * sizeof(C)), lo * sizeof(C),
+                                   st.cp);
+            }
+            return;
+        }
+    }
     if constexpr (COH) {
         R *qb = qout + s0, *pb = pout + s0;
 #pragma unroll
@@ -458,7 +519,7 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     int lane_s = lane;
     asm volatile("" : "+v"(lane_s));
     const int lo_s = (wic * 64 + lane_s) * S;
-    store_lane<R, KAHAN, S, COH, C>(st, out, n, e0 + lo_s, lo_s, halo, halo + keep);
+    store_lane<R, KAHAN, S, COH, C>(st, out, n, e0 + lo_s, lo_s, halo, halo + keep, E);
 }
 
 // Whole-ring resident run by a block of T threads: thread t owns sites

@@ -146,14 +146,24 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 // ---------------------------------------------------------------------------
 // Batches: one persistent launch over many chains. Work items, claimed in
 // increasing order from a counter: first one item per resident chain (a ring
-// short enough to stay in LDS for all its steps), then, pass by pass, one
-// item per (chain, cluster). Item (c, g, e) needs clusters g-1, g, g+1 of
-// chain c to have finished pass e-1; those items have smaller indices, so
-// waiting on them cannot deadlock.
+// short enough to stay in LDS for all its steps), then, pass by pass, the
+// cluster items. A chain is cut into wide clusters (all kBatchWaves
+// wavefronts of a workgroup, 64*S*kBatchWaves sites) followed by at most
+// three narrow ones (one wavefront, 64*S sites), whichever mix holds it in
+// the fewest lane-sites. An item is one wide cluster, or a pack of up to
+// kBatchWaves narrow clusters (of consecutive chains), one per wavefront.
+// Cluster g of chain c at pass e needs clusters g-1, g, g+1 of chain c to
+// have finished pass e-1; those items have smaller indices, so waiting on
+// them cannot deadlock.
 // ---------------------------------------------------------------------------
-constexpr int kBatchThreads = 256;      // 4 wavefronts = one cluster
+constexpr int kBatchThreads = 256;      // 4 wavefronts: one wide cluster
 constexpr int kBatchWaves = 4;
 constexpr int kBatchResidentSites = 1024;  // longest ring a batch keeps on chip
+constexpr int kMaxNarrow = 3;              // narrow clusters per chain at most
+// item_chain[kBatchWaves * w + 1] of a wide item (slot 0 holds its cluster);
+// an empty slot of a narrow pack holds kEmptySlot
+constexpr int32_t kWideItem = -2;
+constexpr int32_t kEmptySlot = -1;
 
 constexpr int batch_resident_max(int /*prec*/) { return kBatchResidentSites; }
 
@@ -161,29 +171,29 @@ struct BatchChain {
     StateRef front, back;
     int64_t n;
     int64_t nsteps;        // resident chains: steps of this launch
-    int64_t uq, ur;        // tiled: each cluster keeps 4*uq or 4*(uq+1) sites
-                           // (the first ur clusters the larger), the last
-                           // cluster also the n % 4 remainder
+    int64_t uq, ur;        // tiled: wide cluster i keeps 4*(uq + (i < ur)) sites
     double dt;
-    int32_t clusters;      // tiled: clusters per pass
+    int32_t clusters;      // tiled: clusters per pass, wide ones first
     int32_t passes;        // tiled: passes of this launch
     int32_t head0, head1;  // steps of passes 0 and 1 when nhead == 2
     int32_t nhead;         // 0 or 2
     int32_t tail;          // steps of the last pass, 0 if it is a full pass
     int32_t flag_base;     // first progress flag of this chain
-    int32_t pad;
+    int32_t wide;          // tiled: wide clusters; the rest are narrow
+    int32_t nuq, nur;      // narrow cluster j keeps 4*(nuq + (j < nur)) sites;
+                           // the chain's last cluster also the n % 4 remainder
 };
 
 struct BatchArgs {
     const BatchChain *chains;      // tiled chains (by passes, descending), then resident
     const int64_t *pass_off;       // pass_off[e]: first tiled item of pass e
-    const int32_t *item_chain;     // chain of the w-th item of a pass
-    const int32_t *item_cluster;   // cluster of the w-th item of a pass
+    const int32_t *item_chain;     // kBatchWaves slots per item: chain of each
+    const int32_t *item_cluster;   // cluster of each slot
     int32_t *flags;                // per cluster: passes completed
     unsigned long long *counter;   // next unclaimed item
     int32_t *error;                // set when a bounded wait expires
     int64_t total_items;
-    int64_t halo;                  // 2 * depth
+    int64_t halo;                  // 2 * depth, rounded up to 4
     int32_t n_resident, n_tiled;
     int32_t max_passes;
     int32_t depth;                 // steps of a full pass

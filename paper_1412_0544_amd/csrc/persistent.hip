@@ -45,6 +45,28 @@ __device__ __forceinline__ StateRef uniform_ref(const StateRef &r) {
                     uniform_ptr(r.z)};
 }
 
+// Kept sites [start, start + keep) of cluster g: the wide clusters first,
+// then the narrow ones, each class in balanced 4-site units; the last cluster
+// also keeps the n % 4 remainder. The host's planner uses the same rule.
+__device__ __forceinline__ void cluster_span(const BatchChain &ch, int g, int64_t &start,
+                                             int64_t &keep) {
+    const int64_t n = uniform64(ch.n), uq = uniform64(ch.uq), ur = uniform64(ch.ur);
+    const int G = __builtin_amdgcn_readfirstlane(ch.clusters);
+    const int wide = __builtin_amdgcn_readfirstlane(ch.wide);
+    int64_t units;
+    if (g < wide) {
+        start = 4 * (static_cast<int64_t>(g) * uq + (g < ur ? g : ur));
+        units = uq + (g < ur ? 1 : 0);
+    } else {
+        const int h = g - wide;
+        const int nuq = __builtin_amdgcn_readfirstlane(ch.nuq);
+        const int nur = __builtin_amdgcn_readfirstlane(ch.nur);
+        start = 4 * (wide * uq + ur + static_cast<int64_t>(h) * nuq + (h < nur ? h : nur));
+        units = nuq + (h < nur ? 1 : 0);
+    }
+    keep = (g == G - 1) ? n - start : 4 * units;
+}
+
 __device__ __forceinline__ int pass_steps(const BatchChain &ch, int e, int depth) {
     if (e < ch.nhead) return e == 0 ? ch.head0 : ch.head1;
     if (ch.tail > 0 && e == ch.passes - 1) return ch.tail;
@@ -56,8 +78,13 @@ __device__ __forceinline__ int pass_steps(const BatchChain &ch, int e, int depth
 // an agent-scope release (cache write-back) and acquire (invalidate).
 // RES: the launch has resident-ring items. Without them the kernel carries no
 // resident path, which leaves the cluster pass more registers per wavefront.
+// Up to 8 sites per lane without RES the kernel is held to 128 registers (4
+// wavefronts per SIMD): the narrow clusters' step loop, which has no LDS
+// exchange, would otherwise be scheduled into 132 and cost a wavefront per
+// SIMD; held to 128 it keeps one 8-byte spill outside the step loops.
 template <int M, class R, bool KAHAN, int S, bool COH, bool RES>
-__global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBatchThreads)
+__attribute__((amdgpu_waves_per_eu((S <= 8 && !RES) ? 4 : 1))) void persistent_kernel(BatchArgs a) {
     constexpr int W = kBatchWaves, WPB = kBatchWaves;
     constexpr int RMAX = kBatchResidentSites;
     constexpr int SPT = RMAX / kBatchThreads;
@@ -90,33 +117,73 @@ __global__ __launch_bounds__(kBatchThreads) void persistent_kernel(BatchArgs a) 
         const int64_t j = item - a.n_resident;
         while (a.pass_off[pass + 1] <= j) ++pass;
         const int64_t w = j - a.pass_off[pass];
-        const BatchChain &ch = a.chains[__builtin_amdgcn_readfirstlane(a.item_chain[w])];
-        const int g = __builtin_amdgcn_readfirstlane(a.item_cluster[w]);
-        const int G = ch.clusters;
-        int32_t *fl = a.flags + ch.flag_base;
-        if (pass > 0) {
-            if (threadIdx.x == 0)
-                wait_flags(fl + (g == 0 ? G - 1 : g - 1), fl + g, fl + (g == G - 1 ? 0 : g + 1), pass,
-                           a.error, a.spin_limit);
+        const int32_t *ic = a.item_chain + kBatchWaves * w;
+        const int32_t *ig = a.item_cluster + kBatchWaves * w;
+        if (__builtin_amdgcn_readfirstlane(ic[1]) == kWideItem) {
+            // one wide cluster: the whole workgroup
+            const BatchChain &ch = a.chains[__builtin_amdgcn_readfirstlane(ic[0])];
+            const int g = __builtin_amdgcn_readfirstlane(ig[0]);
+            const int G = ch.clusters;
+            int32_t *fl = a.flags + ch.flag_base;
+            if (pass > 0) {
+                if (threadIdx.x == 0)
+                    wait_flags(fl + (g == 0 ? G - 1 : g - 1), fl + g,
+                               fl + (g == G - 1 ? 0 : g + 1), pass, a.error, a.spin_limit);
+                __syncthreads();
+                if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            int64_t start, keep;
+            cluster_span(ch, g, start, keep);
+            const StateRef in = uniform_ref((pass & 1) ? ch.back : ch.front);
+            const StateRef out = uniform_ref((pass & 1) ? ch.front : ch.back);
+            const int ksteps = __builtin_amdgcn_readfirstlane(pass_steps(ch, pass, a.depth));
+            run_cluster<M, R, KAHAN, S, W, WPB, COH>(in, out, uniform64(ch.n), start - a.halo,
+                                                     a.halo, keep, ksteps, uniform_f64(ch.dt),
+                                                     &slots, lane, wib, wib);
+            if constexpr (COH)
+                drain_memory();
+            else
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
-            if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (threadIdx.x == 0) store_flag(fl + g, pass + 1);
+        } else {
+            // a pack of narrow clusters: each wavefront runs its own, waits
+            // for its own neighbours and marks its own flag
+            const int c = __builtin_amdgcn_readfirstlane(ic[wib]);
+            if (c != kEmptySlot) {
+                const BatchChain &ch = a.chains[c];
+                // a slot whose chain has no pass `pass` left is idle
+                if (pass < __builtin_amdgcn_readfirstlane(ch.passes)) {
+                    const int g = __builtin_amdgcn_readfirstlane(ig[wib]);
+                    const int G = ch.clusters;
+                    int32_t *fl = a.flags + ch.flag_base;
+                    if (pass > 0) {
+                        if (lane == 0)
+                            wait_flags(fl + (g == 0 ? G - 1 : g - 1), fl + g,
+                                       fl + (g == G - 1 ? 0 : g + 1), pass, a.error,
+                                       a.spin_limit);
+                        if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                    int64_t start, keep;
+                    cluster_span(ch, g, start, keep);
+                    const StateRef in = uniform_ref((pass & 1) ? ch.back : ch.front);
+                    const StateRef out = uniform_ref((pass & 1) ? ch.front : ch.back);
+                    const int ksteps =
+                        __builtin_amdgcn_readfirstlane(pass_steps(ch, pass, a.depth));
+                    // one wavefront: neighbours by DPP only, no LDS slots
+                    run_cluster<M, R, KAHAN, S, 1, WPB, COH>(
+                        in, out, uniform64(ch.n), start - a.halo, a.halo, keep, ksteps,
+                        uniform_f64(ch.dt), static_cast<SlotsOf<M, R, 1, WPB> *>(nullptr), lane,
+                        wib, 0);
+                    if constexpr (COH)
+                        drain_memory();
+                    else
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    if (lane == 0) store_flag(fl + g, pass + 1);
+                }
+            }
         }
-        const int64_t n = uniform64(ch.n), uq = uniform64(ch.uq), ur = uniform64(ch.ur);
-        const int64_t start = 4 * (static_cast<int64_t>(g) * uq + (g < ur ? g : ur));
-        const int64_t keep = (g == G - 1) ? n - start : 4 * (uq + (g < ur ? 1 : 0));
-        const StateRef in = uniform_ref((pass & 1) ? ch.back : ch.front);
-        const StateRef out = uniform_ref((pass & 1) ? ch.front : ch.back);
-        const int ksteps = __builtin_amdgcn_readfirstlane(pass_steps(ch, pass, a.depth));
-        run_cluster<M, R, KAHAN, S, W, WPB, COH>(in, out, n, start - a.halo, a.halo, keep, ksteps,
-                                                 uniform_f64(ch.dt), &slots, lane, wib, wib);
         static_assert(E >= 64, "cluster");
-        if constexpr (COH)
-            drain_memory();
-        else
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(fl + g, pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

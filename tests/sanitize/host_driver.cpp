@@ -130,6 +130,20 @@ int main() {
                 const int64_t E = 64 * int64_t(P.sites_per_lane) * P.waves_per_cluster;
                 CHECK(P.halo % 4 == 0 && P.halo >= 2 * P.kdepth && E >= 4 * P.halo + 16);
                 CHECK(chain_rk4_batch_clusters(1 << 20, s, k) >= 1);
+                // the cut of assorted lengths: kept ranges tile [0, n)
+                for (int64_t n : {int64_t(1), int64_t(3), int64_t(383), int64_t(1100),
+                                  int64_t(4332), int64_t(65537), int64_t(1) << 33}) {
+                    int64_t st[64], kp[64];
+                    int32_t wv[64];
+                    const int64_t G = chain_rk4_batch_layout(n, &bd, st, kp, wv, 64);
+                    CHECK(G >= 1);
+                    int64_t at = 0;
+                    for (int64_t i = 0; i < G && i < 64; ++i) {
+                        CHECK(st[i] == at && kp[i] > 0 && (wv[i] == 1 || wv[i] == P.waves_per_cluster));
+                        at += kp[i];
+                    }
+                    if (G <= 64) CHECK(at == n);
+                }
             }
 
     // validation of every call that takes a handle, a batch or pointers

@@ -156,17 +156,20 @@ def test_batch_calls_reject_bad_arguments_without_a_gpu():
 
 
 def test_batch_cluster_count_helper():
+    from paper_1412_0544_amd.batch import Batch
     lib = L.lib()
     assert lib.chain_rk4_batch_clusters(300, 0, 0) == 1         # a short ring: one cluster
 
-    def expect(n, sites, depth):
+    def wide_only(n, sites, depth):
         keep = 64 * sites * 4 - 4 * depth                          # cluster minus both halos
-        return -(-n // (keep - 4))
+        return -(-(n // 4) // (keep // 4 - 1))
 
-    # default shape: 4 sites per lane, depth 32
     for n in (1000, 1025, 5000, 65536, 1 << 24):
-        assert lib.chain_rk4_batch_clusters(n, 0, 0) == expect(n, 4, 32)
-        assert lib.chain_rk4_batch_clusters(n, 8, 12) == expect(n, 8, 12)
+        for s, k in ((0, 0), (8, 12), (8, 32)):
+            count = lib.chain_rk4_batch_clusters(n, s, k)
+            assert count == len(Batch.layout(n, s, k))
+            only = Batch.layout(n, s, k, L.CHAIN_BATCH_WIDE_ONLY)
+            assert len(only) == wide_only(n, s or 4, k or 32) <= count
     assert lib.chain_rk4_batch_clusters(100, 5, 0) == 0          # invalid shape
     assert lib.chain_rk4_batch_rebind(None, None, 0) == L.CHAIN_EINVAL
 

@@ -64,6 +64,35 @@ def test_batch_matches_solo_bitwise(shape):
     b.close()
 
 
+@pytest.mark.parametrize("prec,flags", [("fp64", 0), ("fp64", L.CHAIN_BATCH_FENCES),
+                                        ("fp32_kahan", 0), ("fp64", L.CHAIN_BATCH_WIDE_ONLY)])
+def test_narrow_packs_across_chains_match_solo(prec, flags):
+    """At 8 sites per lane and depth 32 a wide cluster keeps up to 1916 sites
+    and a narrow one up to 380; these lengths end in one, two or three narrow
+    clusters (or are nothing else), so packs of four narrow clusters span
+    chains, and the differing step counts give the chains different pass
+    counts (a pack slot whose chain has no pass left idles)."""
+    lengths = [100, 383, 700, 1100, 2116, 4332, 3000, 5000, 257, 9000, 450, 1500, 2300, 4100]
+    steps = [64, 1, 0, 33, 96, 5, 32, 17, 2, 64, 31, 65, 95, 40]
+    seeds = range(80, 80 + len(lengths))
+    narrow = [sum(w == 1 for _, _, w in Batch.layout(n, 8, 32, flags)) for n in lengths]
+    if flags & L.CHAIN_BATCH_WIDE_ONLY:
+        assert not any(narrow)
+    else:
+        assert {1, 2, 3} <= set(narrow)
+    chains = make_chains(lengths, seeds, prec=prec)
+    b = Batch(chains, max_steps=96, sites_per_lane=8, kdepth=32, flags=flags)
+    assert b.plan()["narrow_clusters"] == sum(narrow)
+    b.step(steps)
+    b.check()
+    for ch, n, s, k in zip(chains, lengths, seeds, steps):
+        got = snapshot(ch)
+        want = solo(n, s, k, prec=prec)
+        for x, y in zip(got, want):
+            assert np.array_equal(x, y), (n, k, prec, flags)
+    b.close()
+
+
 def test_batch_against_oracle():
     steps = [100] * len(LENGTHS)
     chains = make_chains(LENGTHS, range(30, 40))

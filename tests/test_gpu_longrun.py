@@ -92,20 +92,33 @@ def test_checkpoint_and_resume_bitwise(prec):
         assert torch.equal(rq, fq) and torch.equal(rp, fp)
 
 
-def test_fp32_kahan_energy_drift_bound():
-    """10^4 steps of the same chain in FP32 with compensated update and in
-    FP64: the relative energy drifts differ by less than 1e-6."""
+def test_fp32_energy_drift_at_dt_001_is_the_measured_one():
+    """10^4 steps of dt = 0.01 (Sec. 2.2 Eq. 4-5) from the same FP32-rounded
+    state, N = 2^20: the relative energy drift of each form, pinned at its
+    measured level (the runs are bitwise reproducible, so the band only has
+    to absorb a change of the arithmetic that keeps its character). Measured:
+    FP64 -1.736e-7 (RK4's own dissipation), both compensated forms -7.50e-8
+    and -7.59e-8 (0.43 of FP64), plain FP32 -2.57e-7 (1.48 of FP64). At this
+    step the compensated forms do not track the FP64 drift: FP32 stages give
+    an O(eps h^2) energy error per step that opposes RK4's. Splitting every
+    stage factor into two FP32 parts, as the final update does, moved it by
+    0.3% (and cost 9% throughput), so the stage factors are not its cause;
+    at a step exact in FP32 the forms agree with FP64 (next test)."""
     n, dt, steps = 1 << 20, 0.01, 10_000
     q, p = workloads.chain_ics_torch(n, 3, "cuda", torch.float32)
     drifts = {}
-    for prec, qq, pp in (("fp64", q.double(), p.double()), ("fp32_kahan", q, p)):
+    for prec, qq, pp in (("fp64", q.double(), p.double()), ("fp32_kahan", q, p),
+                         ("fp32_kahan64", q, p), ("fp32", q, p)):
         ch = Chain(qq, pp, dt, prec=prec)
         e0 = ch.energy()
         ch.step(steps)
         drifts[prec] = (ch.energy() - e0) / e0
         ch.close()
-    assert abs(drifts["fp64"]) < 1e-6
-    assert abs(drifts["fp32_kahan"] - drifts["fp64"]) < 1e-6, drifts
+    ref = drifts["fp64"]
+    assert -1.9e-7 < ref < -1.6e-7, drifts                     # measured -1.736e-7
+    for prec in ("fp32_kahan", "fp32_kahan64"):
+        assert 0.35 < drifts[prec] / ref < 0.52, drifts         # measured 0.432, 0.437
+    assert 1.3 < drifts["fp32"] / ref < 1.7, drifts             # measured 1.478
 
 
 def test_fp32_energy_drift_matches_fp64_at_a_step_exact_in_fp32():
@@ -127,5 +140,6 @@ def test_fp32_energy_drift_matches_fp64_at_a_step_exact_in_fp32():
         ch.close()
     ref = drifts["fp64"]
     assert ref < 0, drifts                       # RK4 dissipates energy here
-    for prec in ("fp32_kahan", "fp32_kahan64"):
-        assert abs(drifts[prec] - ref) <= 0.25 * abs(ref), drifts
+    # measured at N = 2^22: FP32 carries within 6.6% of FP64, FP64 carries 0.7%
+    assert abs(drifts["fp32_kahan"] - ref) <= 0.12 * abs(ref), drifts
+    assert abs(drifts["fp32_kahan64"] - ref) <= 0.02 * abs(ref), drifts
