@@ -330,6 +330,48 @@ __device__ inline bool wait_flags(const int32_t *f0, const int32_t *f1, const in
     }
 }
 
+// Steps with issue priority from progress. A SIMD issues from its oldest
+// wavefront first, so when all of a launch's clusters are resident at once
+// (one round), the youngest wavefronts lag and end their pass alone, at a
+// fraction of the SIMD's rate, while the others have already left. A
+// wavefront that lowers its priority as it advances (four levels over
+// `total` steps) lets the lagging ones catch up, so those of a SIMD finish
+// together. It changes only the order of issue, never a result.
+//
+// Runs body() for the steps done, ..., done + k - 1 of `total`, setting the
+// priority once per run of steps at one level: a branch inside the step loop
+// would split its body and cost registers. total = 0 keeps one level.
+__device__ __forceinline__ void set_priority_level(int q) {
+    switch (q) {
+    case 0: __builtin_amdgcn_s_setprio(3); break;
+    case 1: __builtin_amdgcn_s_setprio(2); break;
+    case 2: __builtin_amdgcn_s_setprio(1); break;
+    default: __builtin_amdgcn_s_setprio(0); break;
+    }
+}
+
+template <class F>
+__device__ __forceinline__ void steps_by_progress(int64_t done, int64_t k, int64_t total,
+                                                  F &&body) {
+    // the three level boundaries, relative to `done`, as 32-bit counts
+    int b[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int64_t x = ((j + 1) * total + 3) / 4 - done;
+        b[j] = static_cast<int>(x < 0 ? 0 : (x > k ? k : x));
+    }
+    const int kk = static_cast<int>(k);
+    int t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int end = q < 3 ? b[q] : kk;
+        if (t < end) {
+            set_priority_level(q);
+            for (; t < end; ++t) body();
+        }
+    }
+}
+
 // Wait until every memory operation this wavefront issued has completed.
 __device__ __forceinline__ void drain_memory() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);

@@ -30,6 +30,8 @@ struct FusedPass {
     int64_t waves;
     double dt;
     int ksteps;
+    int balance;  // set by the launcher: every cluster resident at once, so
+                  // wavefronts take issue priority by progress
 };
 
 // Whole-ring resident run: one workgroup holds the chain on chip for nsteps.

@@ -91,12 +91,12 @@ __global__ __launch_bounds__(roessler_block_threads(W)) void roessler_fused_kern
     load3<S>(x, y, z, a.in, a.n, s0, e0 >= 0 && e0 + E <= a.n);
     const StepConsts<double> c(a.dt);
     double X[S], Y[S], Z[S], ax[S], ay[S], az[S];
-    for (int k = 0; k < a.ksteps; ++k) {
+    steps_by_progress(0, a.ksteps, a.balance ? a.ksteps : 0, [&] {
         roessler_lane_stage<S, 1, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 0);
         roessler_lane_stage<S, 2, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 1);
         roessler_lane_stage<S, 3, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 0);
         roessler_lane_stage<S, 4, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, wib * 64 + lane, 1);
-    }
+    });
     double *xo = static_cast<double *>(a.out.q);
     double *yo = static_cast<double *>(a.out.p);
     const int64_t keep_hi = a.halo + a.tile;
@@ -158,14 +158,19 @@ __global__ __launch_bounds__(64 * W) void roessler_exchange_kernel(ExchangeRun a
     double X[S], Y[S], Z[S], ax[S], ay[S], az[S];
     const int64_t base = a.steps / a.passes, extra = a.steps % a.passes;
     const int left = g == 0 ? G - 1 : g - 1, right = g == G - 1 ? 0 : g + 1;
+    // issue priority by progress over the whole call (not per pass: a
+    // cluster that enters its next pass early must not take precedence over
+    // an unrelated one on the same SIMD still finishing the previous pass)
+    int64_t done = 0;
     for (int pass = 0;; ++pass) {
         const int64_t k = base + (pass < extra ? 1 : 0);
-        for (int64_t t = 0; t < k; ++t) {
+        steps_by_progress(done, k, a.steps, [&] {
             roessler_lane_stage<S, 1, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 0);
             roessler_lane_stage<S, 2, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 1);
             roessler_lane_stage<S, 3, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 0);
             roessler_lane_stage<S, 4, W, NL>(X, Y, Z, x, y, z, ax, ay, az, c, &edges, gl, 1);
-        }
+        });
+        done += k;
         if (pass + 1 == a.passes) break;
         const StateRef ex = (pass & 1) ? a.front : a.back;
         double *xe = static_cast<double *>(ex.q);
@@ -290,13 +295,35 @@ __global__ __launch_bounds__(kNaiveThreads) void roessler_naive_stage(StateRef y
     }
 }
 
+// Workgroups of `Kernel` (blocks of `threads`) the current device holds at
+// once; 0 if the query fails. Cached per device.
+template <auto Kernel>
+int resident_blocks(int threads) {
+    static std::atomic<int> cached[64];  // handles on different threads may ask at once
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kernel, threads, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        v = per_cu * cus;
+        cached[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
 template <int S, int W>
 hipError_t roessler_launch_one(const FusedPass &a, hipStream_t st) {
     constexpr int T = roessler_block_threads(W);
     constexpr int cpb = T / 64 / W;
     const int64_t blocks64 = (a.waves + cpb - 1) / cpb;
     if (blocks64 <= 0 || blocks64 > 0x7fffffff) return hipErrorInvalidValue;
-    roessler_fused_kernel<S, W><<<dim3(static_cast<unsigned>(blocks64)), dim3(T), 0, st>>>(a);
+    FusedPass b = a;
+    b.balance = blocks64 <= resident_blocks<roessler_fused_kernel<S, W>>(T) ? 1 : 0;
+    roessler_fused_kernel<S, W><<<dim3(static_cast<unsigned>(blocks64)), dim3(T), 0, st>>>(b);
     return hipGetLastError();
 }
 
@@ -309,21 +336,7 @@ hipError_t exchange_launch_one(const ExchangeRun &a, hipStream_t st) {
 
 template <int S, int W>
 int exchange_capacity_one() {
-    static std::atomic<int> cached[64];  // handles on different threads may ask at once
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    int v = cached[dev].load(std::memory_order_relaxed);
-    if (v == 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, roessler_exchange_kernel<S, W>,
-                                                         64 * W, 0) != hipSuccess)
-            return 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return 0;
-        v = per_cu * cus;
-        cached[dev].store(v, std::memory_order_relaxed);
-    }
-    return v;
+    return resident_blocks<roessler_exchange_kernel<S, W>>(64 * W);
 }
 
 template <int S>
