@@ -71,9 +71,9 @@ BYTES_PER_SITE_PASS_ROESSLER = 48                       # x, y, z in FP64
 # the kernel sources with this sha256 and this cluster shape (sites per lane,
 # wavefronts per cluster, halo) on N = 2^24.
 MEASURED_TRAFFIC = {
-    "sha256": "efc0ea5dfde1634b7e78bf3d8e732e3b13150e721146d8020af97fbaa262579b",
+    "sha256": "dcb9267a277b740f969501d5d33178e8d0c8762a7610fe492c9b124262cdb409",
     "shape": (8, 4, 64), "n": 1 << 24,
-    "bytes_per_launch": 555324021, "fetch_factor": 0.5000, "write_factor": 1.0000,
+    "bytes_per_launch": 555370506, "fetch_factor": 0.5000, "write_factor": 1.0000,
 }
 
 
@@ -735,10 +735,12 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, 
     """The paper's performance protocol on its own workload (Sec. 3.2): a
     Roessler chain of N = 2^20 from random initial conditions, T = 50 steps
     of dt = 0.01, the best of M = 10 trials, Perf = T / t_wall (Eq. 8). The
-    wall time brackets the step call and a stream synchronisation; the
-    device time (HIP events) is reported beside it. Fused at the library
-    plan (eager and replayed from a graph), at every cluster shape in
-    `shapes`, and the one-kernel-per-stage method."""
+    wall time brackets the step call and a stream synchronisation. Beside it
+    the device time per call (HIP events, best of M) around a run of
+    RUN_CALLS back-to-back calls, which the roofline uses, and around a lone
+    call (which also holds the launch latency). Fused at the library plan
+    (eager and replayed from a graph), the exchange form, every cluster
+    shape in `shapes`, and the one-kernel-per-stage method."""
     import torch
     import workloads
     from paper_1412_0544_amd import RoesslerChain
@@ -748,20 +750,27 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, 
         ch = RoesslerChain(x0, y0, z0, dt, device=dev, **kw)
         ch.step(steps)
         torch.cuda.synchronize()
-        walls, gpus = [], []
+        walls, gpus, runs = [], [], []
         for _ in range(trials):
             t = time.perf_counter()
             gpus.append(ev_seconds(lambda: ch.step(steps), ch.stream))
             walls.append(time.perf_counter() - t)
+        # device time per call in a run of back-to-back calls (events around
+        # the run): a lone call's events also hold the launch latency
+        for _ in range(trials):
+            runs.append(ev_seconds(lambda: [ch.step(steps) for _ in range(RUN_CALLS)],
+                                   ch.stream) / RUN_CALLS)
         plan = ch.plan()
         ch.close()
-        w, g = min(walls), min(gpus)
+        w, g, r = min(walls), min(gpus), min(runs)
         return {"steps_per_s": steps / w, "su_per_s": n * steps / w,
-                "device_steps_per_s": steps / g, "device_su_per_s": n * steps / g,
+                "device_single_call_su_per_s": n * steps / g,
+                "device_steps_per_s": steps / r, "device_su_per_s": n * steps / r,
                 "plan": {k: plan[k] for k in ("sites_per_lane", "waves_per_cluster", "kdepth",
                                               "tile", "halo", "waves", "exchange")}}
 
-    out = {"n": n, "steps": steps, "trials": trials, "dt": dt}
+    RUN_CALLS = 20
+    out = {"n": n, "steps": steps, "trials": trials, "dt": dt, "run_calls": RUN_CALLS}
     # bring the device to its working clock first: the first timed calls of
     # a cold device ran up to 13% slower than the same calls later in the run
     ch = RoesslerChain(x0, y0, z0, dt, device=dev)

@@ -140,7 +140,11 @@ enum chain_flags {
                                     once: chain_rk4_create returns
                                     CHAIN_EINVAL if it needs more clusters
                                     than the device holds, fewer than 3, or
-                                    is no longer than a cluster */
+                                    is no longer than a cluster. Default
+                                    kdepth 13 (edge swaps are cheaper than
+                                    deeper overlap). Progress counters in the
+                                    workspace carry over from call to call;
+                                    a graph-captured call clears them first */
 };
 
 typedef enum chain_status {

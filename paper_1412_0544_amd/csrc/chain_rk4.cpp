@@ -113,6 +113,11 @@ constexpr int kDefaultWavesRoessler = 4;
 // chains keep depth 16.
 constexpr int kRoesslerShortDepth = 25;
 constexpr int64_t kRoesslerShortSites = int64_t(1) << 21;
+// CHAIN_FLAG_EXCHANGE: between passes only the edge sites move, in place of
+// the whole chain's store and reload, so shallower passes (less overlap)
+// pay: depth 13 (halo 52) measured 4.84 against 4.60e11 SU/s for depth 25
+// at N = 2^20 in 50-step calls.
+constexpr int kExchangeDepthRoessler = 13;
 // Default depth: as many steps as a halo of 64 sites per side covers (32 for
 // the NN chains, 16 for the NNN and Roessler chains; the fastest depth of a
 // sweep over S, W, k at N = 2^24 and N = 2^20).
@@ -323,6 +328,8 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
     const bool table_shape = nn && !tab && !d->sites_per_lane && !d->waves_per_cluster;
     P.depth = d->kdepth      ? d->kdepth
               : table_shape ? row.depth
+              : roessler && (d->flags & CHAIN_FLAG_EXCHANGE)
+                  ? kExchangeDepthRoessler
               : roessler && d->n <= kRoesslerShortSites
                   ? kRoesslerShortDepth
                   : static_cast<int>(std::min<int64_t>(
@@ -383,8 +390,9 @@ chain_rk4_plan public_plan(const chain_rk4_desc &d, const Plan &p) {
 
 namespace {
 
-// Enqueue the passes of nsteps on stream s.
-int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
+// Enqueue the passes of nsteps on stream s (`captured`: s is capturing a
+// graph that will be replayed later).
+int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s, bool captured) {
     const chain_rk4_desc &d = h->d;
     if (nsteps == 0) return CHAIN_OK;
     if (d.method == CHAIN_NAIVE && d.scheme == CHAIN_SCHEME_TABLEAU) {
@@ -410,13 +418,30 @@ int enqueue_steps(chain_rk4 *h, int64_t nsteps, hipStream_t s) {
         passes += passes % 2;
         if (passes > INT32_MAX) return fail(CHAIN_EINVAL, "too many steps in one call");
         const Plan &P = h->plan;
-        hipError_t e = launch_fill_zero(h->xflags, static_cast<size_t>(P.waves) * sizeof(int32_t), s);
-        if (e != hipSuccess) return hip_fail(e, "clearing the exchange flags");
+        // The progress counters keep counting over successive calls: every
+        // cluster sets its counter after each pass but the last, so after a
+        // call of `passes` passes all of them hold base + passes - 1, the next
+        // call's base (also after a timed-out wait, which lets its cluster go
+        // on). A call captured into a graph is replayed later, when the
+        // counters have moved on: it clears them and starts from 0, and
+        // every replay leaves the base unknown (step_graph), as does a base
+        // near the top of the 32-bit range.
+        int64_t base = h->xbase;
+        if (captured || base < 0 || base + passes > (int64_t(1) << 30)) {
+            hipError_t e =
+                launch_fill_zero(h->xflags, static_cast<size_t>(P.waves) * sizeof(int32_t), s);
+            if (e != hipSuccess) return hip_fail(e, "clearing the exchange flags");
+            base = 0;
+        }
         ExchangeRun a{h->front, h->back, d.n, P.uq, P.ur, P.halo, P.zone, nsteps, d.dt,
                       static_cast<int32_t>(P.waves), static_cast<int32_t>(passes), h->xflags,
-                      h->xerror, kExchangeSpinLimit};
-        e = launch_exchange_roessler(P.sites, P.waves_per_cluster, a, s);
-        if (e != hipSuccess) return hip_fail(e, "exchange launch");
+                      h->xerror, kExchangeSpinLimit, static_cast<int32_t>(base)};
+        hipError_t e = launch_exchange_roessler(P.sites, P.waves_per_cluster, a, s);
+        if (e != hipSuccess) {
+            h->xbase = -1;
+            return hip_fail(e, "exchange launch");
+        }
+        h->xbase = captured ? -1 : base + passes - 1;
         return CHAIN_OK;
     }
     if (h->plan.resident) {
@@ -479,7 +504,7 @@ int step_graph(chain_rk4 *h, int64_t nsteps) {
         }
         if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_steps(h, nsteps, h->capture);
+        int rc = enqueue_steps(h, nsteps, h->capture, true);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->capture, &g);
         if (rc != CHAIN_OK) {
@@ -493,6 +518,9 @@ int step_graph(chain_rk4 *h, int64_t nsteps) {
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
         it = h->graphs.emplace(nsteps, exec).first;
     }
+    // a replayed exchange call leaves its counters at a value this handle
+    // does not track: the next eager call clears them
+    h->xbase = -1;
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
     return CHAIN_OK;
 }
@@ -623,7 +651,7 @@ int chain_rk4_step(chain_rk4 *h, int64_t nsteps) {
         return fail(CHAIN_EINVAL, "no tableau set (chain_rk4_set_tableau)");
     if (nsteps == 0) return CHAIN_OK;
     if (h->d.flags & CHAIN_FLAG_GRAPH) return step_graph(h, nsteps);
-    return enqueue_steps(h, nsteps, h->stream);
+    return enqueue_steps(h, nsteps, h->stream, false);
 }
 
 int chain_rk4_energy(chain_rk4 *h, double *e_out) {

@@ -53,5 +53,7 @@ struct chain_rk4 {
     chainrk4::TabArgs tableau{};
     chainrk4::NaiveTabBufs naive_tab{};
     int32_t *xflags = nullptr;    // CHAIN_FLAG_EXCHANGE: per-cluster pass counters
+    int64_t xbase = -1;           // value of every counter after the last call, -1 if
+                                  // unknown (cleared before the next call)
     int32_t *xerror = nullptr;    // CHAIN_FLAG_EXCHANGE: sticky timeout word
 };

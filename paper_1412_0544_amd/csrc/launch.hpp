@@ -125,9 +125,10 @@ struct ExchangeRun {
     double dt;
     int32_t clusters;       // >= 3
     int32_t passes;         // even, >= 2 (the last pass ends in front)
-    int32_t *flags;         // per cluster: passes done (zeroed before the launch)
+    int32_t *flags;         // per cluster: base + passes done
     int32_t *error;         // set if a bounded wait expires (never cleared here)
     int32_t spin_limit;     // polls before a wait gives up
+    int32_t base;           // every flag's value when the launch starts
 };
 hipError_t launch_exchange_roessler(int sites_per_lane, int waves_per_cluster,
                                     const ExchangeRun &a, hipStream_t s);

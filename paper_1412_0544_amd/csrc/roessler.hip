@@ -185,21 +185,31 @@ __global__ __launch_bounds__(64 * W) void roessler_exchange_kernel(ExchangeRun a
         const int h = static_cast<int>(a.halo), kp = static_cast<int>(keep);
         const int zn = static_cast<int>(a.zone);
         const int64_t sx = e0 + lx;
-        // kept sites never wrap: site sx + j is start + (lx + j - halo) < n
+        // kept sites never wrap: site sx + j is start + (lx + j - halo) < n.
+        // A lane whose sites all go out stores them 16 bytes at a time (the
+        // resource spans the cluster's window from its origin e0, which may
+        // lie before the array; only kept sites, inside it, are written).
+        if (lx >= h && lx + S <= h + kp && (lx + S <= h + zn || lx >= kp)) {
+            constexpr int bytes = E * static_cast<int>(sizeof(double));
+            store_window<double, S>(window_rsrc(xe + e0, bytes), lx * 8, x);
+            store_window<double, S>(window_rsrc(ye + e0, bytes), lx * 8, y);
+            store_window<double, S>(window_rsrc(ze + e0, bytes), lx * 8, z);
+        } else {
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int local = lx + j;
-            if (local >= h && local < h + kp && (local < h + zn || local >= kp)) {
-                store_coherent(xe + sx + j, x[j]);
-                store_coherent(ye + sx + j, y[j]);
-                store_coherent(ze + sx + j, z[j]);
+            for (int j = 0; j < S; ++j) {
+                const int local = lx + j;
+                if (local >= h && local < h + kp && (local < h + zn || local >= kp)) {
+                    store_coherent(xe + sx + j, x[j]);
+                    store_coherent(ye + sx + j, y[j]);
+                    store_coherent(ze + sx + j, z[j]);
+                }
             }
         }
         drain_memory();
         __syncthreads();
         if (threadIdx.x == 0) {
-            store_flag(a.flags + g, pass + 1);
-            wait_flags(a.flags + left, a.flags + g, a.flags + right, pass + 1, a.error,
+            store_flag(a.flags + g, a.base + pass + 1);
+            wait_flags(a.flags + left, a.flags + g, a.flags + right, a.base + pass + 1, a.error,
                        a.spin_limit);
         }
         __syncthreads();

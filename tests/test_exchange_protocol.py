@@ -36,7 +36,10 @@ def layout(n, P):
     return E, G, uq, ur, P.halo, E - P.halo - 4 * uq
 
 
-def emulate(n, P, steps, rng):
+def emulate(n, P, steps, rng, flags=None, fbase=0, front=None):
+    """One step call. `flags` (per cluster) carry over from the previous
+    call, all at `fbase`; `front` holds (site, passes) tags. Returns the
+    cluster count and the pass count."""
     E, G, uq, ur, halo, zone = layout(n, P)
     assert (G, 4 * (uq + 1), zone) == (P.waves, P.tile, zone)
     passes = -(-steps // P.kdepth)
@@ -44,9 +47,12 @@ def emulate(n, P, steps, rng):
     base, extra = divmod(steps, passes)
     assert all(base + (j < extra) <= P.kdepth for j in range(passes))
     assert halo >= REACH * P.kdepth
-    front = [(i, 0) for i in range(n)]          # the caller's buffers: tags (site, passes)
+    if front is None:
+        front = [(i, 0) for i in range(n)]      # the caller's buffers: tags (site, passes)
+    p0 = front[0][1]
     back = [None] * n
-    flags = [0] * G
+    if flags is None:
+        flags = [0] * G
 
     def cluster(g):
         start = 4 * (g * uq + min(g, ur))
@@ -54,7 +60,7 @@ def emulate(n, P, steps, rng):
         e0 = start - halo
         left, right = (g - 1) % G, (g + 1) % G
         # load: the window, wrapped (any sign; the kernel wraps by index)
-        win = [front[(e0 + loc) % n] for loc in range(E)]
+        win = [(site, p - p0) for site, p in (front[(e0 + loc) % n] for loc in range(E))]
         assert all(t[1] == 0 for t in win)
         for j in range(passes):
             yield ("compute", g, j)
@@ -76,8 +82,8 @@ def emulate(n, P, steps, rng):
                     site = e0 + loc
                     assert 0 <= site < n            # kept sites never wrap
                     ex[site] = win[loc]
-            flags[g] = j + 1
-            while not (flags[left] >= j + 1 and flags[right] >= j + 1):
+            flags[g] = fbase + j + 1
+            while not (flags[left] >= fbase + j + 1 and flags[right] >= fbase + j + 1):
                 yield ("wait", g, j)
             for loc in range(E):
                 if loc < halo or loc >= halo + keep:
@@ -87,7 +93,8 @@ def emulate(n, P, steps, rng):
                     win[loc] = ex[i]
                     assert win[loc] == (i, j + 1), (g, j, loc, win[loc])
         for loc in range(halo, halo + keep):
-            front[e0 + loc] = win[loc]
+            site, p = win[loc]
+            front[e0 + loc] = (site, p + p0)
         yield ("done", g, passes)
 
     runners = {g: cluster(g) for g in range(G)}
@@ -97,7 +104,9 @@ def emulate(n, P, steps, rng):
             next(runners[g])
         except StopIteration:
             del runners[g]
-    assert front == [(i, passes) for i in range(n)]
+    assert front == [(i, p0 + passes) for i in range(n)]
+    # every cluster sets its counter after each pass but the last
+    assert flags == [fbase + passes - 1] * G
     return G, passes
 
 
@@ -112,6 +121,39 @@ def test_exchange_hand_off_in_random_orders(sites, waves, depth, n, steps):
     for seed in range(3):
         G, passes = emulate(n, P, steps, random.Random(seed))
         assert G >= 3 and passes % 2 == 0
+
+
+@pytest.mark.parametrize("sites,waves,depth,n", [(4, 4, 25, 20011), (4, 2, 7, 5003)])
+def test_progress_counters_carry_over_successive_calls(sites, waves, depth, n):
+    """The counters are not cleared between calls: a call starts from the
+    value they all hold after the previous one (base + passes - 1)."""
+    rc, P = plan_for(n, sites, waves, depth)
+    assert rc == L.CHAIN_OK and P.exchange == 1
+    rng = random.Random(5)
+    G = P.waves
+    flags, fbase, front = [0] * G, 0, [(i, 0) for i in range(n)]
+    for steps in (50, 2, 3 * depth + 1, 7, 50):
+        _, passes = emulate(n, P, steps, rng, flags, fbase, front)
+        fbase += passes - 1
+
+
+def test_a_stale_base_lets_a_cluster_read_an_old_halo():
+    """Planted mistake, on the CPU: a call that starts below the counters'
+    value (as a replayed graph would, had it not cleared them) lets some
+    cluster pass its wait before its neighbours' edges are written."""
+    n, sites, waves, depth = 20011, 4, 4, 25
+    rc, P = plan_for(n, sites, waves, depth)
+    assert rc == L.CHAIN_OK
+    caught = 0
+    for seed in range(6):
+        flags = [0] * P.waves
+        front = [(i, 0) for i in range(n)]
+        emulate(n, P, 50, random.Random(seed), flags, 0, front)
+        try:
+            emulate(n, P, 50, random.Random(100 + seed), flags, 0, front)  # stale base 0
+        except AssertionError:
+            caught += 1
+    assert caught > 0
 
 
 def test_exchange_plans_refused_when_clusters_cannot_hand_off():

@@ -177,6 +177,36 @@ def test_exchange_against_the_oracle_and_across_calls():
         assert torch.equal(a, b)
 
 
+def test_exchange_counters_carry_over_many_calls():
+    """The progress counters are not cleared between eager calls (each call
+    starts from the value the last one left): 60 calls of 1 to 7 steps give
+    the bits of one call over the same steps; on a graph handle, two graphs
+    replayed in turn (each clears the counters) give them too."""
+    n = 20011
+    ics = workloads.roessler_ics(n, 7)
+    ks = [1 + (5 * i) % 7 for i in range(60)]
+    many = RoesslerChain(*ics, 0.01, exchange=True)
+    for k in ks:
+        many.step(k)
+    many.check()
+    once = RoesslerChain(*ics, 0.01, exchange=True)
+    once.step(sum(ks))
+    once.check()
+    for a, b in zip(many.state(), once.state()):
+        assert torch.equal(a, b)
+    g = RoesslerChain(*ics, 0.01, exchange=True, graph=True)
+    for k in (50, 26, 50, 26, 50):
+        g.step(k)
+    g.check()
+    ref = RoesslerChain(*ics, 0.01, exchange=True)
+    ref.step(202)
+    ref.check()
+    for a, b in zip(g.state(), ref.state()):
+        assert torch.equal(a, b)
+    for c in (many, once, g, ref):
+        c.close()
+
+
 def test_exchange_at_the_paper_size_equals_fused():
     """N = 2^20, T = 50 steps (the paper's protocol) at the library's
     shape: the whole chain in registers, bit for bit the fused passes."""
