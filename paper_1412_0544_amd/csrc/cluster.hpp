@@ -4,6 +4,7 @@
 // goes through these two functions, so every launch shape gives the same bits.
 #pragma once
 
+#include <atomic>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -535,7 +536,7 @@ template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false, c
 __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
                                             int64_t e0, int64_t halo, int64_t keep, int ksteps,
                                             double dt, SlotsOf<M, R, W, WPB> *slots, int lane,
-                                            int wib, int wic) {
+                                            int wib, int wic, int prio_total = 0) {
     constexpr int E = 64 * S * W;
     const int lo = (wic * 64 + lane) * S;
     const int64_t s0 = e0 + lo;
@@ -543,15 +544,30 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     load_lane<R, KAHAN, S, COH, C>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
     const StepConsts<R> c(dt);
     R Q[S], X[S], s[S], a[S];  // stage argument and the values site_update carries
-    for (int k = 0; k < ksteps; ++k) {
-        any_lane_stage<M, S, 1, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
-        any_lane_stage<M, S, 2, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
-        any_lane_stage<M, S, 3, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
-        any_lane_stage<M, S, 4, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
-        if constexpr (KAHAN)
-            final_update_kahan<S>(st.q, st.p, st.cq, st.cp, s, a, c);
-        else
-            final_update<S>(st.q, st.p, s, a, c);
+    if constexpr (W == 1) {
+        // one-wavefront clusters (short chains, the whole launch resident at
+        // once): issue priority by progress when prio_total > 0
+        steps_by_progress(0, ksteps, prio_total, [&] {
+            any_lane_stage<M, S, 1, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
+            any_lane_stage<M, S, 2, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
+            any_lane_stage<M, S, 3, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
+            any_lane_stage<M, S, 4, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
+            if constexpr (KAHAN)
+                final_update_kahan<S>(st.q, st.p, st.cq, st.cp, s, a, c);
+            else
+                final_update<S>(st.q, st.p, s, a, c);
+        });
+    } else {
+        for (int k = 0; k < ksteps; ++k) {
+            any_lane_stage<M, S, 1, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
+            any_lane_stage<M, S, 2, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
+            any_lane_stage<M, S, 3, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 0);
+            any_lane_stage<M, S, 4, W, WPB>(Q, X, st.q, st.p, s, a, c, slots, lane, wib, wic, 1);
+            if constexpr (KAHAN)
+                final_update_kahan<S>(st.q, st.p, st.cq, st.cp, s, a, c);
+            else
+                final_update<S>(st.q, st.p, s, a, c);
+        }
     }
     // The store's per-lane offsets are formed again from the lane id after
     // the step loop. The empty asm hides that the id is the one used for the
@@ -646,6 +662,26 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
             }
         }
     }
+}
+
+// Workgroups of `Kernel` (blocks of `threads`) the current device holds at
+// once; 0 if the query fails. Cached per device.
+template <auto Kernel>
+int resident_blocks(int threads) {
+    static std::atomic<int> cached[64];  // handles on different threads may ask at once
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kernel, threads, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        v = per_cu * cus;
+        cached[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 }  // namespace chainrk4

@@ -305,26 +305,6 @@ __global__ __launch_bounds__(kNaiveThreads) void roessler_naive_stage(StateRef y
     }
 }
 
-// Workgroups of `Kernel` (blocks of `threads`) the current device holds at
-// once; 0 if the query fails. Cached per device.
-template <auto Kernel>
-int resident_blocks(int threads) {
-    static std::atomic<int> cached[64];  // handles on different threads may ask at once
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    int v = cached[dev].load(std::memory_order_relaxed);
-    if (v == 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kernel, threads, 0) != hipSuccess)
-            return 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return 0;
-        v = per_cu * cus;
-        cached[dev].store(v, std::memory_order_relaxed);
-    }
-    return v;
-}
-
 template <int S, int W>
 hipError_t roessler_launch_one(const FusedPass &a, hipStream_t st) {
     constexpr int T = roessler_block_threads(W);
