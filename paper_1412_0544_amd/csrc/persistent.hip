@@ -162,7 +162,13 @@ __attribute__((amdgpu_waves_per_eu((S <= 8 && !RES) ? 4 : 1))) void persistent_k
                             wait_flags(fl + (g == 0 ? G - 1 : g - 1), fl + g,
                                        fl + (g == G - 1 ? 0 : g + 1), pass, a.error,
                                        a.spin_limit);
-                        if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        // no barrier follows (the wavefront's lanes run
+                        // together): keep the compiler from moving the
+                        // cluster's loads above the wait
+                        if constexpr (COH)
+                            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        else
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     }
                     int64_t start, keep;
                     cluster_span(ch, g, start, keep);
