@@ -2,10 +2,19 @@
 // translation units (argument validation, workspace layout, planning, the
 // batch tables) build and run on a CPU under the sanitizers. No path the
 // host driver takes reaches a launch; each stub fails loudly if one does.
+// Built with RECORD_EXCHANGE, the fill, the exchange launch and its capacity
+// query instead record their calls (exchange_driver.cpp reads them), so the
+// host bookkeeping of the exchange form runs without a GPU.
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include "launch.hpp"
+
+#ifdef RECORD_EXCHANGE
+std::vector<int> recorded_bases, recorded_passes;
+int recorded_fills = 0;
+#endif
 
 namespace chainrk4 {
 
@@ -30,15 +39,31 @@ hipError_t launch_fused_roessler(int, int, const FusedPass &, hipStream_t) { unr
 hipError_t launch_naive_roessler_step(StateRef, const NaiveBufs &, int64_t, double, hipStream_t) {
     unreachable("naive roessler");
 }
+#ifdef RECORD_EXCHANGE
+hipError_t launch_exchange_roessler(int, int, const ExchangeRun &a, hipStream_t) {
+    recorded_bases.push_back(a.base);
+    recorded_passes.push_back(a.passes);
+    return hipSuccess;
+}
+int exchange_capacity_roessler(int, int) { return 1 << 20; }
+#else
 hipError_t launch_exchange_roessler(int, int, const ExchangeRun &, hipStream_t) {
     unreachable("exchange roessler");
 }
 int exchange_capacity_roessler(int, int) { unreachable("exchange capacity"); }
+#endif
 int energy_blocks(int64_t) { unreachable("energy_blocks"); }
 hipError_t launch_energy(int, int, StateRef, int64_t, double *, double *, hipStream_t) {
     unreachable("energy");
 }
+#ifdef RECORD_EXCHANGE
+hipError_t launch_fill_zero(void *, size_t, hipStream_t) {
+    ++recorded_fills;
+    return hipSuccess;
+}
+#else
 hipError_t launch_fill_zero(void *, size_t, hipStream_t) { unreachable("fill_zero"); }
+#endif
 int persistent_capacity(int, int, int, bool) { unreachable("persistent_capacity"); }
 hipError_t launch_persistent(int, int, int, int, const BatchArgs &, hipStream_t) {
     unreachable("persistent");

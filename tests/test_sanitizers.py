@@ -52,3 +52,24 @@ def test_host_library_code_under_sanitizers(tmp_path):
     r = run([exe], env=dict(ENV, ASAN_OPTIONS="abort_on_error=1:detect_leaks=0",
                             HIP_VISIBLE_DEVICES=""), timeout=600)
     assert "all invariants hold" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or
+                    not os.path.exists(os.path.join(ROCM, "include", "hip", "hip_runtime.h")),
+                    reason="needs g++ and the HIP headers")
+def test_exchange_bookkeeping_under_sanitizers(tmp_path):
+    """The exchange form's pass counters over successive calls (the base each
+    launch starts from), with recording launchers in place of the kernels."""
+    exe = str(tmp_path / "exchange_driver")
+    inc = ["-D__HIP_PLATFORM_AMD__", "-DRECORD_EXCHANGE", f"-I{ROCM}/include",
+           f"-I{ROOT}/include", f"-I{CSRC}"]
+    objs = []
+    for src in (os.path.join(CSRC, "chain_rk4.cpp"), os.path.join(CSRC, "batch.cpp"),
+                os.path.join(HERE, "launch_stubs.cpp"), os.path.join(HERE, "exchange_driver.cpp")):
+        obj = str(tmp_path / (os.path.basename(src) + ".o"))
+        run(["g++", "-std=c++17", *SAN, *inc, "-c", src, "-o", obj])
+        objs.append(obj)
+    run(["g++", *SAN, *objs, "-o", exe, f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"])
+    r = run([exe], env=dict(ENV, ASAN_OPTIONS="abort_on_error=1:detect_leaks=0",
+                            HIP_VISIBLE_DEVICES=""), timeout=300)
+    assert "exchange bookkeeping holds" in r.stdout
