@@ -266,7 +266,7 @@ def main(argv=None):
                          "--serve-rho")
     ap.add_argument("--serve-rho", default="0.5,0.8",
                     help="offered loads of --serve, comma separated")
-    ap.add_argument("--serve-rate", type=float, default=5.4e11,
+    ap.add_argument("--serve-rate", type=float, default=6.5e11,
                     help="device capacity (site-updates/s) the loads of --serve refer to")
     ap.add_argument("--roessler-n", type=int, default=1 << 20,
                     help="chain length of --roessler (the paper's is 2^20)")

@@ -387,7 +387,7 @@ typedef struct chain_rk4_batch_desc {
     int64_t max_steps;       /* largest per-chain step count of one step call */
     int64_t max_clusters;    /* capacity for chain_rk4_batch_rebind: clusters
                                 over all tiled chains (0 = what `hs` needs) */
-    int32_t sites_per_lane;  /* 0 = default (4), else 4, 8 or 16 */
+    int32_t sites_per_lane;  /* 0 = default (8), else 4, 8 or 16 */
     int32_t kdepth;          /* steps per pass, 0 = default (32), else 2..32 */
     int32_t grid_blocks;     /* workgroups, 0 = as many as the device holds at
                                 once; any value >= 1 gives the same results */

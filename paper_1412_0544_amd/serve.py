@@ -295,10 +295,12 @@ class GpuExecutor:
         self.sites = sites_per_lane
         self.kdepth = kdepth
         self.max_active = max_active
-        # clusters the budget can hold, plus one partial cluster per slot
+        # clusters the budget can hold, plus the extra clusters a chain's cut
+        # can take beyond its share of sites (a partial four-wavefront
+        # cluster and up to three one-wavefront ones: at most four per slot)
         tile = Batch.clusters(1 << 30, sites_per_lane, kdepth)
         per_cluster_sites = (1 << 30) / max(tile, 1)
-        self.max_clusters = int(hbm_budget / 32 / per_cluster_sites) + 2 * max_active + 8
+        self.max_clusters = int(hbm_budget / 32 / per_cluster_sites) + 4 * max_active + 8
         self.slots = {}
         self._next = 0
         self.groups = {}              # (model, prec) -> {"batch", "stream", "chains"}

@@ -169,7 +169,7 @@ def test_batch_cluster_count_helper():
             count = lib.chain_rk4_batch_clusters(n, s, k)
             assert count == len(Batch.layout(n, s, k))
             only = Batch.layout(n, s, k, L.CHAIN_BATCH_WIDE_ONLY)
-            assert len(only) == wide_only(n, s or 4, k or 32) <= count
+            assert len(only) == wide_only(n, s or 8, k or 32) <= count
     assert lib.chain_rk4_batch_clusters(100, 5, 0) == 0          # invalid shape
     assert lib.chain_rk4_batch_rebind(None, None, 0) == L.CHAIN_EINVAL
 
