@@ -404,6 +404,22 @@ def main(argv=None):
     t_launch = statistics.mean(gpu) / launches
     rl = roofline(n, js / launches, t_launch, prec=args.prec)
     rl["launches_per_job"] = launches
+    # the bandwidth a plain device copy reaches, to read the HBM view against
+    # the achievable as well as the published peak
+    copy = hbm_copy_gbps(dev)
+    rl["hbm_view"]["copy_probe_GBps"] = copy
+    rl["hbm_view"]["frac_of_copy_probe"] = rl["hbm_view"]["achieved"] / copy
+    # the attainable rate of this plan: the lower of the HBM bound at its
+    # depth and the VALU ceiling less the recomputed halo
+    if args.prec in ("fp64", "fp32_kahan"):
+        E = 64 * S * W
+        alu_ceiling = (VALU_PEAK_TOPS if args.prec == "fp64" else FP32_VALU_PEAK_TOPS) * 1e12 / (
+            OPS_PER_SU["quartic"] if args.prec == "fp64" else OPS_PER_SU_FP32_KAHAN)
+        hbm_ceiling = HBM_PEAK_GBPS * 1e9 / BYTES_PER_SITE_PASS[args.prec] * (js / launches)
+        bound = min(hbm_ceiling, alu_ceiling * plan["tile"] / E)
+        rl["attainable"] = {"su_per_s": bound, "frac": value / bound,
+                            "hbm_bound_su_per_s": hbm_ceiling,
+                            "valu_bound_less_halo_su_per_s": alu_ceiling * plan["tile"] / E}
     rl["traffic"] = None
     mt = MEASURED_TRAFFIC
     if (args.prec == "fp64" and kernel_sources_sha256() == mt["sha256"]
@@ -471,6 +487,19 @@ def copy_probe(dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     return src.numel() * 8
+
+
+def hbm_copy_gbps(dev, nbytes=1 << 30, trials=5):
+    """Achievable HBM bandwidth: the best of `trials` device copies of
+    `nbytes` (read and written, so 2*nbytes move), timed with HIP events."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream(dev)
+    dst.copy_(src)
+    t = min(ev_seconds(lambda: dst.copy_(src), st) for _ in range(trials))
+    del src, dst
+    return 2 * nbytes / t / 1e9
 
 
 def ev_seconds(fn, stream):
