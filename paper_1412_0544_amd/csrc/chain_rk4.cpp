@@ -85,22 +85,32 @@ constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 17, 2, 1, 16},
                                    {int64_t(1) << 19, 4, 1, 32},
                                    {int64_t(1) << 21, 8, 1, 32},
                                    {INT64_MAX, 8, 4, 32}};
-// FP32 state (all three FP32 precisions agree): multi-wavefront clusters from
-// 2^18 sites on, where the all-lane LDS exchange leaves room for more sites
-// per lane.
+// FP32 state: multi-wavefront clusters from 2^18 sites on, where the all-lane
+// LDS exchange leaves room for more sites per lane. Plain FP32 takes 16 sites
+// per lane on long chains; the compensated forms stay at 8, where their split
+// stage arguments keep 95 registers (5 wavefronts per SIMD; at 16 they took
+// 169, or spilled under a 128 bound, and ran 5 to 7% slower).
 constexpr ShapeRow kShapeFp32[] = {{int64_t(1) << 17, 2, 1, 16},
                                    {int64_t(1) << 19, 2, 4, 32},
                                    {int64_t(1) << 21, 4, 4, 32},
                                    {int64_t(1) << 23, 8, 4, 32},
                                    {INT64_MAX, 16, 4, 32}};
+constexpr ShapeRow kShapeFp32Kahan[] = {{int64_t(1) << 17, 2, 1, 16},
+                                        {int64_t(1) << 19, 2, 4, 32},
+                                        {int64_t(1) << 21, 4, 4, 32},
+                                        {INT64_MAX, 8, 4, 32}};
+
+template <size_t K>
+ShapeRow row_for(const ShapeRow (&rows)[K], int64_t n) {
+    for (size_t i = 0; i < K; ++i)
+        if (n <= rows[i].max_n) return rows[i];
+    return rows[K - 1];
+}
 
 ShapeRow shape_for(int prec, int64_t n) {
-    const ShapeRow *rows = prec == CHAIN_FP64 ? kShapeFp64 : kShapeFp32;
-    const size_t count = prec == CHAIN_FP64 ? sizeof kShapeFp64 / sizeof kShapeFp64[0]
-                                            : sizeof kShapeFp32 / sizeof kShapeFp32[0];
-    for (size_t i = 0; i < count; ++i)
-        if (n <= rows[i].max_n) return rows[i];
-    return rows[count - 1];
+    if (prec == CHAIN_FP64) return row_for(kShapeFp64, n);
+    if (prec == CHAIN_FP32) return row_for(kShapeFp32, n);
+    return row_for(kShapeFp32Kahan, n);
 }
 // Roessler: nine S-site register arrays per lane instead of six, so fewer
 // sites per lane (the fastest shape at N = 2^20 in a sweep over S, W, k).

@@ -217,9 +217,9 @@ __device__ __forceinline__ void edge_bonds2(R f0, R f1, R l0, R l1,
 }
 
 // One stage for the S sites of this lane.
-template <int M, int S, int STAGE, int W, int WPB, class R>
+template <int M, int S, int STAGE, int W, int WPB, class R, bool SPLIT>
 __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S], R (&s)[S],
-                                           R (&a)[S], const StepConsts<R> &c,
+                                           R (&a)[S], const StepConsts<R, SPLIT> &c,
                                            SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
                                            int wic, int parity) {
     const R first = (STAGE == 1) ? q[0] : Q[0];
@@ -230,9 +230,9 @@ __device__ __forceinline__ void lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&
 }
 
 // The same with next-nearest-neighbour coupling.
-template <int M, int S, int STAGE, int W, int WPB, class R>
+template <int M, int S, int STAGE, int W, int WPB, class R, bool SPLIT>
 __device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
-                                               R (&s)[S], R (&a)[S], const StepConsts<R> &c,
+                                               R (&s)[S], R (&a)[S], const StepConsts<R, SPLIT> &c,
                                                SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
                                                int wic, int parity) {
     const R f0 = (STAGE == 1) ? q[0] : Q[0];
@@ -246,9 +246,9 @@ __device__ __forceinline__ void lane_stage_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], 
 }
 
 // Dispatch on the coupling range of the model.
-template <int M, int S, int STAGE, int W, int WPB, class R>
+template <int M, int S, int STAGE, int W, int WPB, class R, bool SPLIT>
 __device__ __forceinline__ void any_lane_stage(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
-                                               R (&s)[S], R (&a)[S], const StepConsts<R> &c,
+                                               R (&s)[S], R (&a)[S], const StepConsts<R, SPLIT> &c,
                                                SlotsOf<M, R, W, WPB> *slots, int lane, int wib,
                                                int wic, int parity) {
     if constexpr (coupling_range<M>() == 2)
@@ -542,7 +542,7 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     const int64_t s0 = e0 + lo;
     LaneState<R, KAHAN, S, C> st;
     load_lane<R, KAHAN, S, COH, C>(st, in, n, s0, e0 >= 0 && e0 + E <= n);
-    const StepConsts<R> c(dt);
+    const StepConsts<R, KAHAN> c(dt);
     R Q[S], X[S], s[S], a[S];  // stage argument and the values site_update carries
     if constexpr (W == 1) {
         // one-wavefront clusters (short chains, the whole launch resident at
@@ -612,7 +612,7 @@ __device__ __forceinline__ void run_resident(const StateRef &in, const StateRef 
     }
     __syncthreads();
 
-    const StepConsts<R> c(dt);
+    const StepConsts<R, KAHAN> c(dt);
     for (int64_t st = 0; st < nsteps; ++st) {
         // stage s reads its argument from `cur` and publishes the next one
         // (after stage 4: the new coordinates) in `nxt`

@@ -4,7 +4,9 @@
 // fused kernel is measured against, and it uses the same per-site operation
 // order (site_update, site_final), so both give identical bits. What goes
 // through memory: the stage argument (Q2 and Q4 in one array, Q3 in another),
-// F1, F2 and the running sum F1 + F2 + F3.
+// F1, the value site_update carries from stage 2 to 3 (F2; in the compensated
+// FP32 forms also the increment it carries from stage 1 to 2) and the running
+// sum F1 + F2 + F3.
 #include "launch.hpp"
 #include "rk4_device.hpp"
 
@@ -29,7 +31,7 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
     R *sum = static_cast<R *>(b.k2q);  // F1 + F2 (+ F3)
     // stage argument: q, Q2, Q3, Q4
     const R *arg = STAGE == 1 ? yq : STAGE == 3 ? Qb : Qa;
-    const StepConsts<R> c(dt);
+    const StepConsts<R, KAHAN> c(dt);
 
     const R Qj = arg[i];
     R F;
@@ -51,8 +53,10 @@ __global__ __launch_bounds__(kNaiveThreads) void naive_stage(StateRef y, NaiveBu
         site_update<1>(F, Qj, Qo, X, qj, pj, sj, a, c);
         Qa[i] = Qo;
         F1[i] = a;
+        if constexpr (KAHAN) F2[i] = X;
     } else if constexpr (STAGE == 2) {
         sj = F1[i];
+        if constexpr (KAHAN) X = F2[i];
         site_update<2>(F, Qj, Qo, X, qj, pj, sj, a, c);
         Qb[i] = Qo;
         F2[i] = X;

@@ -92,8 +92,9 @@ __device__ __forceinline__ R site_force2(R b1l, R b1r, R b2l, R b2r, R q) {
 }
 
 // Step constants in the working precision. The products of two step factors
-// (hh2, hhh, h26) are formed in FP64 and rounded once.
-template <class R>
+// (hh2, hhh, h26) are formed in FP64 and rounded once. SPLIT selects the
+// stage arguments of the compensated FP32 forms (site_update).
+template <class R, bool SPLIT = false>
 struct StepConsts {
     R h, hh, h6;
     R hh2;       // (h/2)^2
@@ -202,20 +203,43 @@ __device__ __forceinline__ R from_left(R x) { return dpp<kDppWaveShr1>(x); }
 //   X   F2 (stage 2 to 3)
 //   s   F1 + F2 + F3 (stages 1 to 3)
 //   a   F1 (stages 1 to 4); after stage 4, F1 + 2F2 + 2F3 + F4
+//
+// The compensated FP32 forms (SPLIT) take the step factor of the stage
+// arguments in two parts as well: where dt is not an FP32 number, R(dt)
+// differs from dt by up to 3e-8 relative, and stage arguments formed with it
+// perturb the method's second-order condition (sum b_j c_j = 1/2) by that
+// much. On an oscillation of frequency w that is an energy gain of about
+// 3e-8 (w h)^2 per step, the same in every step: at dt = 0.01 over 10^4 steps
+// as large as RK4's own dissipation. The two parts only help if the small one
+// is added before the increment meets q (q + lo p rounds back to q), so the
+// increment is formed apart, u = hi p + lo p, and added to q last:
+//   Q2 = q + u/2,  X = u + h (h/2) F2 (stage 2 to 3),  Q4 = q + X,
+// two operations more per site and step (X carries u from stage 1 to 2).
 // ---------------------------------------------------------------------------
-template <int STAGE, class R>
+template <int STAGE, class R, bool SPLIT>
 __device__ __forceinline__ void site_update(R F, R Qj, R &Qo, R &X, R qj, R pj, R &s, R &a,
-                                            const StepConsts<R> &c) {
+                                            const StepConsts<R, SPLIT> &c) {
     if (STAGE == 1) {
         a = F;
         s = F;
-        Qo = fma_r(c.hh, pj, qj);
+        if constexpr (SPLIT) {
+            X = fma_r(c.h, pj, c.hlo * pj);
+            Qo = fma_r(static_cast<R>(0.5), X, qj);
+        } else {
+            Qo = fma_r(c.hh, pj, qj);
+        }
     } else if (STAGE == 2) {
         Qo = fma_r(c.hh2, s, Qj);
-        X = F;
+        if constexpr (SPLIT)
+            X = fma_r(c.hhh, F, X);
+        else
+            X = F;
         s = s + F;
     } else if (STAGE == 3) {
-        Qo = fma_r(c.hhh, X, fma_r(c.h, pj, qj));
+        if constexpr (SPLIT)
+            Qo = qj + X;
+        else
+            Qo = fma_r(c.hhh, X, fma_r(c.h, pj, qj));
         s = s + F;
     } else {
         a = fma_r(static_cast<R>(2), s, F) - a;
@@ -230,9 +254,9 @@ __device__ __forceinline__ void site_update(R F, R Qj, R &Qo, R &X, R qj, R pj, 
 // scales the same term of every step alike, an error the carry cannot undo.
 // For h that is a first-order error; for h^2/6 it is an energy drift of order
 // eps h^2 per step, which a split removes too (one more fused multiply-add).
-template <class R, bool KAHAN, class C>
+template <class R, bool KAHAN, class C, bool SPLIT>
 __device__ __forceinline__ void site_final(R &q, R &p, C &cq, C &cp, R s, R a,
-                                           const StepConsts<R> &c) {
+                                           const StepConsts<R, SPLIT> &c) {
     if constexpr (!KAHAN) {
         q = fma_r(c.h26, s, fma_r(c.h, p, q));
         p = fma_r(c.h6, a, p);
@@ -254,10 +278,10 @@ __device__ __forceinline__ void site_final(R &q, R &p, C &cq, C &cp, R s, R a,
 //   bl0     bond term left of site 0; brS bond term right of site S-1
 // Stage 1 reads its argument from q (Q is an output only).
 // ---------------------------------------------------------------------------
-template <int M, int S, int STAGE, class R>
+template <int M, int S, int STAGE, class R, bool SPLIT>
 __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
                                             R (&s)[S], R (&a)[S], R bl0, R brS,
-                                            const StepConsts<R> &c) {
+                                            const StepConsts<R, SPLIT> &c) {
     R bl = bl0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -279,10 +303,11 @@ __device__ __forceinline__ void stage_sites(R (&Q)[S], R (&X)[S], R (&q)[S], R (
 // (S >= 2). The edge bond terms come from the neighbour lanes:
 //   b1l0 = phi(Q_0 - Q_{-1}),  b2lm2 = phi(Q_0 - Q_{-2}),  b2lm1 = phi(Q_1 - Q_{-1}),
 //   b1rS = phi(Q_S - Q_{S-1}), b2rS2 = phi(Q_S - Q_{S-2}), b2rS1 = phi(Q_{S+1} - Q_{S-1}).
-template <int M, int S, int STAGE, class R>
+template <int M, int S, int STAGE, class R, bool SPLIT>
 __device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&X)[S], R (&q)[S], R (&p)[S],
                                                 R (&s)[S], R (&a)[S], R b1l0, R b2lm2, R b2lm1,
-                                                R b1rS, R b2rS2, R b2rS1, const StepConsts<R> &c) {
+                                                R b1rS, R b2rS2, R b2rS1,
+                                                const StepConsts<R, SPLIT> &c) {
     static_assert(S >= 2, "a lane holds at least two sites");
     R b1l = b1l0, b2l_lo = b2lm2, b2l_hi = b2lm1;  // phi of bonds (j-1, j), (j-2, j), (j-1, j+1)
 #pragma unroll
@@ -303,9 +328,9 @@ __device__ __forceinline__ void stage_sites_nnn(R (&Q)[S], R (&X)[S], R (&q)[S],
 
 // The end of the step (Eq. 5) for the S sites of a lane: without
 // compensation, and with the carries of the compensated FP32 forms.
-template <int S, class R>
+template <int S, class R, bool SPLIT>
 __device__ __forceinline__ void final_update(R (&q)[S], R (&p)[S], const R (&s)[S],
-                                             const R (&a)[S], const StepConsts<R> &c) {
+                                             const R (&a)[S], const StepConsts<R, SPLIT> &c) {
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         R unused = 0;
@@ -313,19 +338,19 @@ __device__ __forceinline__ void final_update(R (&q)[S], R (&p)[S], const R (&s)[
     }
 }
 
-template <int S, class C>
+template <int S, class C, bool SPLIT>
 __device__ __forceinline__ void final_update_kahan(float (&q)[S], float (&p)[S], C (&cq)[S],
                                                    C (&cp)[S], const float (&s)[S],
                                                    const float (&a)[S],
-                                                   const StepConsts<float> &c) {
+                                                   const StepConsts<float, SPLIT> &c) {
 #pragma unroll
     for (int j = 0; j < S; ++j) site_final<float, true, C>(q[j], p[j], cq[j], cp[j], s[j], a[j], c);
 }
 
 // Same arithmetic for one site held alone (resident kernel).
-template <int M, int STAGE, class R>
+template <int M, int STAGE, class R, bool SPLIT>
 __device__ __forceinline__ void stage_one(R Qm, R Qj, R Qp, R qj, R pj, R &X, R &s, R &a, R &Qn,
-                                          const StepConsts<R> &c) {
+                                          const StepConsts<R, SPLIT> &c) {
     const R bl = ModelOps<M, R>::bond(Qj - Qm);
     const R br = ModelOps<M, R>::bond(Qp - Qj);
     const R F = site_force<M, R>(bl, br, Qj);

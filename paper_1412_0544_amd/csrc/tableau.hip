@@ -64,14 +64,38 @@ struct Coef {
 
 // acc += x * F. FP64 rounds once; the compensated FP32 form takes x in two
 // parts, since a coefficient rounded once to FP32 would scale the same term
-// of every step alike (an error the carry of the update cannot undo).
+// of every step alike (an error the carry of the update cannot undo). The
+// product (hi + lo) F is rounded once before it meets the sum: acc + lo F
+// would round back to acc, losing the small part in every step.
 template <class R, bool KAHAN>
 __device__ __forceinline__ R coef_fma(const Coef<R> &x, R F, R acc, bool first) {
     if constexpr (KAHAN) {
-        return first ? fma_r(x.hi, F, x.lo * F) : fma_r(x.hi, F, fma_r(x.lo, F, acc));
+        const R t = fma_r(x.hi, F, x.lo * F);
+        return first ? t : acc + t;
     } else {
         return first ? x.hi * F : fma_r(x.hi, F, acc);
     }
+}
+
+// The stage argument Q_j = q + hc_j p + sum_l g_jl F_l at one site, the sum
+// taken in stage order. FP64 accumulates into q. The compensated FP32 form
+// takes hc_j in two parts and forms the increment apart, adding it to q last:
+// a factor rounded once to FP32 would offset every stage argument alike (an
+// energy term of the same sign in every step), and its small part added to q
+// directly would round away.
+template <class R, bool KAHAN>
+__device__ __forceinline__ R stage_start(const Coef<R> &hc, R q, R p) {
+    if constexpr (KAHAN)
+        return fma_r(hc.hi, p, hc.lo * p);
+    else
+        return fma_r(hc.hi, p, q);
+}
+template <class R, bool KAHAN>
+__device__ __forceinline__ R stage_end(R x, R q) {
+    if constexpr (KAHAN)
+        return q + x;
+    else
+        return x;
 }
 
 template <int M, class R, bool KAHAN, int S, int W, int SMAX>
@@ -100,13 +124,13 @@ __global__ __launch_bounds__(tab_block_threads(W)) void tableau_kernel(FusedPass
             if (j == 0) {
                 lane_force<M, S, W, WPB>(st.q, F[0], &slots, lane, wib, wic, parity);
             } else {
-                const R hc = static_cast<R>(t.hc[j]);
+                const Coef<R> hc(t.hc[j]);
 #pragma unroll
                 for (int i = 0; i < S; ++i) {
-                    R x = fma_r(hc, st.p[i], st.q[i]);
+                    R x = stage_start<R, KAHAN>(hc, st.q[i], st.p[i]);
 #pragma unroll
                     for (int l = 0; l + 1 < j; ++l) x = fma_r(static_cast<R>(t.g[j][l]), F[l][i], x);
-                    Q[i] = x;
+                    Q[i] = stage_end<R, KAHAN>(x, st.q[i]);
                 }
                 lane_force<M, S, W, WPB>(Q, F[j], &slots, lane, wib, wic, parity);
             }
@@ -210,9 +234,9 @@ __global__ __launch_bounds__(kNaiveTabThreads) void naive_tab_stage(StateRef y, 
     const int s = t.stages;
     if (j + 1 < s) {
         static_cast<R *>(b.kp[j])[i] = Fj;
-        R x = fma_r(static_cast<R>(t.hc[j + 1]), pi, qi);
+        R x = stage_start<R, KAHAN>(Coef<R>(t.hc[j + 1]), qi, pi);
         for (int l = 0; l < j; ++l) x = fma_r(static_cast<R>(t.g[j + 1][l]), Fm(l), x);
-        next[i] = x;
+        next[i] = stage_end<R, KAHAN>(x, qi);
     } else {
         R fq = static_cast<R>(0), fp = static_cast<R>(0);
         for (int m = 0; m < s; ++m) {

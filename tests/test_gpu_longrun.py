@@ -92,18 +92,16 @@ def test_checkpoint_and_resume_bitwise(prec):
         assert torch.equal(rq, fq) and torch.equal(rp, fp)
 
 
-def test_fp32_energy_drift_at_dt_001_is_the_measured_one():
+def test_fp32_energy_drift_at_dt_001_tracks_fp64():
     """10^4 steps of dt = 0.01 (Sec. 2.2 Eq. 4-5) from the same FP32-rounded
-    state, N = 2^20: the relative energy drift of each form, pinned at its
-    measured level (the runs are bitwise reproducible, so the band only has
-    to absorb a change of the arithmetic that keeps its character). Measured:
-    FP64 -1.736e-7 (RK4's own dissipation), both compensated forms -7.50e-8
-    and -7.59e-8 (0.43 of FP64), plain FP32 -2.57e-7 (1.48 of FP64). At this
-    step the compensated forms do not track the FP64 drift: FP32 stages give
-    an O(eps h^2) energy error per step that opposes RK4's. Splitting every
-    stage factor into two FP32 parts, as the final update does, moved it by
-    0.3% (and cost 9% throughput), so the stage factors are not its cause;
-    at a step exact in FP32 the forms agree with FP64 (next test)."""
+    state, N = 2^20: the compensated forms drift as FP64 does (RK4's own
+    dissipation), plain FP32 does not. dt = 0.01 is no FP32 number; stage
+    arguments formed with the rounded step would add an energy gain of the
+    same sign in every step (0.43 of the FP64 drift was left with it), so
+    the compensated forms take that step in two parts (site_update). The
+    runs are bitwise reproducible; the bands absorb a change of arithmetic
+    that keeps its character. Measured: FP64 -1.736e-7, compensated forms
+    1.0023 and 0.9997 of it, plain FP32 1.478 of it."""
     n, dt, steps = 1 << 20, 0.01, 10_000
     q, p = workloads.chain_ics_torch(n, 3, "cuda", torch.float32)
     drifts = {}
@@ -114,20 +112,18 @@ def test_fp32_energy_drift_at_dt_001_is_the_measured_one():
         ch.step(steps)
         drifts[prec] = (ch.energy() - e0) / e0
         ch.close()
+    print("drifts at dt = 0.01", drifts)
     ref = drifts["fp64"]
     assert -1.9e-7 < ref < -1.6e-7, drifts                     # measured -1.736e-7
     for prec in ("fp32_kahan", "fp32_kahan64"):
-        assert 0.35 < drifts[prec] / ref < 0.52, drifts         # measured 0.432, 0.437
+        assert abs(drifts[prec] / ref - 1) < 0.03, drifts
     assert 1.3 < drifts["fp32"] / ref < 1.7, drifts             # measured 1.478
 
 
 def test_fp32_energy_drift_matches_fp64_at_a_step_exact_in_fp32():
-    """At dt = 2^-7 the FP32 stages advance by exactly the step of the final
-    combination, so over 10^4 steps the systematic RK4 energy drift of both
-    FP32 variants is the FP64 one (measured within 6% at N = 2^24). At a
-    step FP32 cannot hold (0.01), the stage step is off by a relative 2e-8,
-    an error of order eps*h^2 per step in the energy that opposes the RK4
-    drift; this test does not use such a step."""
+    """At dt = 2^-7, a step FP32 holds exactly (the small part of the split
+    step is zero), over 10^4 steps the systematic RK4 energy drift of both
+    compensated forms is the FP64 one."""
     n, dt, steps = 1 << 22, 2.0 ** -7, 10_000
     q, p = workloads.chain_ics_torch(n, 4, "cuda", torch.float32)
     drifts = {}
@@ -138,8 +134,9 @@ def test_fp32_energy_drift_matches_fp64_at_a_step_exact_in_fp32():
         ch.step(steps)
         drifts[prec] = (ch.energy() - e0) / e0
         ch.close()
+    print("drifts at dt = 2^-7", drifts)
     ref = drifts["fp64"]
     assert ref < 0, drifts                       # RK4 dissipates energy here
-    # measured at N = 2^22: FP32 carries within 6.6% of FP64, FP64 carries 0.7%
+    # measured at N = 2^22: FP32 carries within 6.6% of FP64, FP64 carries 0.55%
     assert abs(drifts["fp32_kahan"] - ref) <= 0.12 * abs(ref), drifts
     assert abs(drifts["fp32_kahan64"] - ref) <= 0.02 * abs(ref), drifts
