@@ -5,9 +5,12 @@
 // Eq. 2 written for a chain with coordinates q and momenta p:
 //   dq_i/dt = p_i,  dp_i/dt = F_i = (phi(d_i) - phi(d_{i-1})) - U'(q_i),
 //   d_i = q_{i+1} - q_i  (the bond to the right neighbour).
-// quartic:  phi(d) = d^3, U'(q) = q + q^3
+// quartic:  phi(d) = d^3, U'(q) = q + q^3 = q (1 + q^2)
 // harmonic: phi(d) = d,   U'(q) = q
 // Every bond term phi(d_i) is computed once and used by both sites it joins.
+// The quartic on-site term is taken as q (1 + q^2) and subtracted from the
+// bond difference by one fused multiply-add: 6 operations per site and stage
+// (bond 3, 1 + q^2, difference, fma) instead of 7 for q + q^3 formed apart.
 // The next-nearest-neighbour models (the generalisation of Sec. 5) add bonds
 // to the second neighbours with the same phi:
 //   F_i = ((phi(d_i) - phi(d_{i-1})) + (phi(e_i) - phi(e_{i-2}))) - U'(q_i),
@@ -43,7 +46,11 @@ struct ModelOps;
 template <class R>
 struct ModelOps<kQuartic, R> {
     __device__ __forceinline__ static R bond(R d) { return (d * d) * d; }
-    __device__ __forceinline__ static R onsite(R q) { return fma_r(q * q, q, q); }
+    // t - U'(q) with U'(q) = q (1 + q^2): one rounding for 1 + q^2, one for
+    // the fused product and difference
+    __device__ __forceinline__ static R force(R t, R q) {
+        return fma_r(-fma_r(q, q, static_cast<R>(1)), q, t);
+    }
     // energy density of the site and its right bond, in FP64
     __device__ __forceinline__ static double energy(double q, double p, double d) {
         double q2 = q * q, d2 = d * d;
@@ -54,7 +61,7 @@ struct ModelOps<kQuartic, R> {
 template <class R>
 struct ModelOps<kHarmonic, R> {
     __device__ __forceinline__ static R bond(R d) { return d; }
-    __device__ __forceinline__ static R onsite(R q) { return q; }
+    __device__ __forceinline__ static R force(R t, R q) { return t - q; }
     __device__ __forceinline__ static double energy(double q, double p, double d) {
         return 0.5 * (p * p) + 0.5 * (q * q) + 0.5 * (d * d);
     }
@@ -80,7 +87,7 @@ struct ModelOps<kHarmonicNNN, R> : ModelOps<kHarmonic, R> {
 // Force on a site from its left bond term, right bond term and coordinate.
 template <int M, class R>
 __device__ __forceinline__ R site_force(R bl, R br, R q) {
-    return (br - bl) - ModelOps<M, R>::onsite(q);
+    return ModelOps<M, R>::force(br - bl, q);
 }
 
 // NNN force from the four bond terms that meet at the site:
@@ -88,7 +95,7 @@ __device__ __forceinline__ R site_force(R bl, R br, R q) {
 // b2l = phi(q_i - q_{i-2}), b2r = phi(q_{i+2} - q_i).
 template <int M, class R>
 __device__ __forceinline__ R site_force2(R b1l, R b1r, R b2l, R b2r, R q) {
-    return ((b1r - b1l) + (b2r - b2l)) - ModelOps<M, R>::onsite(q);
+    return ModelOps<M, R>::force((b1r - b1l) + (b2r - b2l), q);
 }
 
 // Step constants in the working precision. The products of two step factors
