@@ -759,8 +759,8 @@ def size_sweep(dev, dt=0.01, steps=50, trials=10, exps=range(10, 27, 2)):
 
 
 def roessler_shapes():
-    return [(s, w, k) for s in (4, 8) for w in (1, 2, 4, 8) for k in (8, 16, 25, 32)
-            if 64 * s * w > 16 * k]
+    return [(s, w, k) for s in (4, 6, 8) for w in (1, 2, 4, 8) for k in (8, 13, 16, 21, 25, 32)
+            if 64 * s * w > 16 * k and (s != 6 or w == 4)]
 
 
 def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, sweep=True):
@@ -824,11 +824,12 @@ def variant_roessler(dev, dt=0.01, n=1 << 20, steps=50, trials=10, shapes=None, 
                                                model="roessler")
         if sweep:
             xt = {}
-            for w in (4, 8):
-                for k in (6, 8, 10, 13, 17, 25, 32):
+            for s_, w in ((4, 4), (4, 8), (6, 4), (6, 2), (8, 2)):
+                for k in (6, 8, 10, 13, 17, 21, 25, 32):
                     try:
-                        xt[f"s4_w{w}_k{k}"] = measure(sites_per_lane=4, waves_per_cluster=w,
-                                                      kdepth=k, exchange=True)["device_su_per_s"]
+                        xt[f"s{s_}_w{w}_k{k}"] = measure(sites_per_lane=s_, waves_per_cluster=w,
+                                                         kdepth=k,
+                                                         exchange=True)["device_su_per_s"]
                     except ChainError:
                         pass
             out["exchange_shapes_device_su_per_s"] = xt

@@ -112,22 +112,29 @@ ShapeRow shape_for(int prec, int64_t n) {
     if (prec == CHAIN_FP32) return row_for(kShapeFp32, n);
     return row_for(kShapeFp32Kahan, n);
 }
-// Roessler: nine S-site register arrays per lane instead of six, so fewer
-// sites per lane (the fastest shape at N = 2^20 in a sweep over S, W, k).
-constexpr int kDefaultSitesRoessler = 4;
+// Roessler: nine S-site register arrays per lane instead of six (92
+// registers at 4 sites per lane, 128 at 6, 166 at 8). Fused passes, from
+// sweeps over S, W, k: chains up to 2^21 sites take 4 sites per lane at
+// depth 25 (halo 100; at N = 2^20 the chain fills the chip about once, so
+// each pass pays its load and store with little overlap, and fewer, deeper
+// passes measured faster: 3.7 against 3.4e11 SU/s for 50-step calls at depth
+// 16); longer chains 8 sites per lane at depth 25 (5.50 against 4.88e11 SU/s
+// for 4 sites per lane at depth 16, N = 2^24).
 constexpr int kDefaultWavesRoessler = 4;
-// Roessler chains up to 2^21 sites: depth 25 (halo 100). At N = 2^20 the
-// chain fills the chip about once, so each pass pays its load and store
-// with little overlap; fewer, deeper passes measured faster (3.7 against
-// 3.4e11 SU/s for 50-step calls, 4.1 against 3.8e11 for 1000 steps). Longer
-// chains keep depth 16.
-constexpr int kRoesslerShortDepth = 25;
+constexpr int kRoesslerDepth = 25;
 constexpr int64_t kRoesslerShortSites = int64_t(1) << 21;
+constexpr int kRoesslerShortSitesPerLane = 4;
+constexpr int kRoesslerLongSitesPerLane = 8;
 // CHAIN_FLAG_EXCHANGE: between passes only the edge sites move, in place of
 // the whole chain's store and reload, so shallower passes (less overlap)
 // pay: depth 13 (halo 52) measured 4.84 against 4.60e11 SU/s for depth 25
-// at N = 2^20 in 50-step calls.
+// at N = 2^20 in 50-step calls. Every cluster stays resident for the call,
+// so the chip's share of each SIMD sets the pace: 2^20 sites are 1024 per
+// SIMD, which 4 sites per lane hold in 5 wavefronts of 256 (1280 lane-sites
+// per SIMD with the halo), and 6 sites per lane in 3 of 384 (1152; 735
+// clusters, about 3 per CU): 5.21 against 4.96e11 SU/s at depth 13.
 constexpr int kExchangeDepthRoessler = 13;
+constexpr int kExchangeSitesRoessler = 6;
 // Default depth: as many steps as a halo of 64 sites per side covers (32 for
 // the NN chains, 16 for the NNN and Roessler chains; the fastest depth of a
 // sweep over S, W, k at N = 2^24 and N = 2^20).
@@ -152,10 +159,16 @@ int check_desc(const chain_rk4_desc *d) {
     if (!std::isfinite(d->dt)) return fail(CHAIN_EINVAL, "dt must be finite");
     if (d->method != CHAIN_FUSED && d->method != CHAIN_NAIVE)
         return fail(CHAIN_EINVAL, "unknown method %d", d->method);
-    if (d->sites_per_lane != 0 && !valid_sites(d->sites_per_lane))
+    if (d->model == CHAIN_ROESSLER) {
+        // six sites per lane (128 registers, 4 wavefronts per SIMD) is built
+        // for the Roessler kernels only
+        if (d->sites_per_lane != 0 && d->sites_per_lane != 6 &&
+            (d->sites_per_lane == 2 || !valid_sites(d->sites_per_lane)))
+            return fail(CHAIN_EINVAL, "the Roessler kernel takes sites_per_lane 0, 4, 6, 8 or 16 (got %d)",
+                        d->sites_per_lane);
+    } else if (d->sites_per_lane != 0 && !valid_sites(d->sites_per_lane)) {
         return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 2, 4, 8 or 16 (got %d)", d->sites_per_lane);
-    if (d->sites_per_lane == 2 && d->model == CHAIN_ROESSLER)
-        return fail(CHAIN_EINVAL, "the Roessler kernel takes sites_per_lane 4, 8 or 16");
+    }
     if (d->kdepth < 0 || d->kdepth > kMaxDepth)
         return fail(CHAIN_EINVAL, "kdepth must be in 0..%d (got %d)", kMaxDepth, d->kdepth);
     if (d->waves_per_cluster != 0 && !valid_waves(d->waves_per_cluster))
@@ -176,7 +189,7 @@ int check_desc(const chain_rk4_desc *d) {
         (d->model != CHAIN_ROESSLER || d->method != CHAIN_FUSED || (d->flags & CHAIN_FLAG_RESIDENT)))
         return fail(CHAIN_EINVAL, "CHAIN_FLAG_EXCHANGE takes the Roessler chain on the fused method");
     if ((d->flags & CHAIN_FLAG_EXCHANGE) && d->sites_per_lane > 8)
-        return fail(CHAIN_EINVAL, "CHAIN_FLAG_EXCHANGE takes sites_per_lane 4 or 8");
+        return fail(CHAIN_EINVAL, "CHAIN_FLAG_EXCHANGE takes sites_per_lane 4, 6 or 8");
     if (d->flags & CHAIN_FLAG_RESIDENT) {
         if (d->flags & CHAIN_FLAG_NO_RESIDENT)
             return fail(CHAIN_EINVAL, "CHAIN_FLAG_RESIDENT and CHAIN_FLAG_NO_RESIDENT exclude each other");
@@ -326,7 +339,10 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
     }
     const ShapeRow row = shape_for(d->prec, d->n);
     P.sites = d->sites_per_lane ? d->sites_per_lane
-              : roessler        ? kDefaultSitesRoessler
+              : roessler && (d->flags & CHAIN_FLAG_EXCHANGE)
+                  ? kExchangeSitesRoessler
+              : roessler        ? (d->n <= kRoesslerShortSites ? kRoesslerShortSitesPerLane
+                                                               : kRoesslerLongSitesPerLane)
               : tab             ? default_sites_tableau(stages)
               : nn              ? row.sites
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
@@ -340,8 +356,7 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
               : table_shape ? row.depth
               : roessler && (d->flags & CHAIN_FLAG_EXCHANGE)
                   ? kExchangeDepthRoessler
-              : roessler && d->n <= kRoesslerShortSites
-                  ? kRoesslerShortDepth
+              : roessler ? kRoesslerDepth
                   : static_cast<int>(std::min<int64_t>(
                         kMaxDepth, std::max<int64_t>(1, kDefaultHalo / reach)));
     const int64_t E = 64 * static_cast<int64_t>(P.sites) * P.waves_per_cluster;

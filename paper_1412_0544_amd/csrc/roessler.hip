@@ -367,6 +367,7 @@ hipError_t roessler_dispatch_w(int w, const FusedPass &a, hipStream_t st) {
 hipError_t launch_fused_roessler(int s, int w, const FusedPass &a, hipStream_t st) {
     switch (s) {
     case 4: return roessler_dispatch_w<4>(w, a, st);
+    case 6: return roessler_dispatch_w<6>(w, a, st);
     case 8: return roessler_dispatch_w<8>(w, a, st);
     case 16: return roessler_dispatch_w<16>(w, a, st);
     default: return hipErrorInvalidValue;
@@ -376,6 +377,7 @@ hipError_t launch_fused_roessler(int s, int w, const FusedPass &a, hipStream_t s
 hipError_t launch_exchange_roessler(int s, int w, const ExchangeRun &a, hipStream_t st) {
     switch (s) {
     case 4: return exchange_dispatch_w<4>(w, a, st);
+    case 6: return exchange_dispatch_w<6>(w, a, st);
     case 8: return exchange_dispatch_w<8>(w, a, st);
     default: return hipErrorInvalidValue;
     }
@@ -384,6 +386,7 @@ hipError_t launch_exchange_roessler(int s, int w, const ExchangeRun &a, hipStrea
 int exchange_capacity_roessler(int s, int w) {
     switch (s) {
     case 4: return exchange_capacity_w<4>(w);
+    case 6: return exchange_capacity_w<6>(w);
     case 8: return exchange_capacity_w<8>(w);
     default: return 0;
     }

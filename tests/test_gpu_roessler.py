@@ -40,7 +40,8 @@ def maxerr(a, b):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257, 1000, 5003, 20011])
 @pytest.mark.parametrize("sites,waves,depth", [(4, 1, 1), (8, 2, 3), (16, 1, 8), (4, 8, 16),
-                                               (4, 4, 12), (8, 4, 16), (16, 8, 12)])
+                                               (4, 4, 12), (8, 4, 16), (16, 8, 12), (6, 4, 13),
+                                               (6, 1, 5)])
 def test_fused_matches_oracle(n, sites, waves, depth):
     ics = workloads.roessler_ics(n, 1)
     got, plan = gpu_run(ics, 0.01, 100, sites_per_lane=sites, waves_per_cluster=waves,
@@ -63,7 +64,8 @@ def test_shapes_depths_and_step_splits_identical_bits():
     n = 3 * 2048 + 77
     ics = workloads.roessler_ics(n, 3)
     ref, _ = gpu_run(ics, 0.01, 37)
-    for s, w, k in [(4, 1, 1), (4, 2, 5), (8, 8, 16), (16, 4, 7), (8, 1, 2)]:
+    for s, w, k in [(4, 1, 1), (4, 2, 5), (8, 8, 16), (16, 4, 7), (8, 1, 2), (6, 4, 21),
+                    (6, 2, 9)]:
         got, _ = gpu_run(ics, 0.01, 37, sites_per_lane=s, waves_per_cluster=w, kdepth=k)
         for a, b in zip(ref, got):
             assert np.array_equal(a, b), (s, w, k)
@@ -141,7 +143,8 @@ def test_roessler_rejects_energy_and_batches():
 @pytest.mark.parametrize("n,sites,waves,depth,steps", [
     (2051, 4, 2, 1, 2), (4001, 4, 1, 6, 37), (9000, 4, 4, 13, 50), (20011, 4, 4, 25, 50),
     (30011, 8, 2, 20, 61), (40003, 4, 8, 32, 64), (8195, 4, 4, 16, 1000), (2000, 4, 4, 25, 50),
-    (20011, 4, 4, 25, 1), (20011, 4, 4, 25, 3)])
+    (20011, 4, 4, 25, 1), (20011, 4, 4, 25, 3), (9000, 6, 4, 13, 50), (30011, 6, 4, 21, 61),
+    (20011, 6, 2, 8, 37)])
 def test_exchange_equals_fused_bits(n, sites, waves, depth, steps):
     ics = workloads.roessler_ics(n, 5)
     kw = dict(sites_per_lane=sites, waves_per_cluster=waves, kdepth=depth)
