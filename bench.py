@@ -1019,7 +1019,7 @@ def plan_sweep(dev, dt=0.01, steps=64, exps=range(10, 27, 2), precs=("fp64", "fp
 
             if n <= 4096:
                 table["resident"] = timed(resident=True)
-            for s_ in (2, 4, 8, 16):
+            for s_ in ((2, 4, 6, 8, 16) if prec == "fp64" else (2, 4, 8, 16)):
                 for w in (1, 2, 4, 8):
                     for k in (4, 8, 16, 24, 32):
                         if 64 * s_ * w > 4 * k + 16:

@@ -164,9 +164,11 @@ typedef struct chain_rk4_desc {
     double dt;               /* step size; finite, may be negative (reversal) */
     int32_t method;          /* enum chain_method */
     int32_t sites_per_lane;  /* fused: sites per GPU lane, 0 = default, else
-                                2, 4, 8 or 16; CHAIN_ROESSLER takes 4, 6, 8
-                                or 16 (6, 8 or 4 with CHAIN_FLAG_EXCHANGE);
-                                the tableau kernel takes 4 or 8 */
+                                2, 4, 8 or 16; 6 for classical RK4 of the
+                                FP64 quartic and harmonic chains;
+                                CHAIN_ROESSLER takes 4, 6, 8 or 16 (4, 6 or 8
+                                with CHAIN_FLAG_EXCHANGE); the tableau kernel
+                                takes 4 or 8 */
     int32_t kdepth;          /* fused: RK4 steps per pass over memory, 0 =
                                 default, else 1..32 */
     int32_t waves_per_cluster; /* fused: wavefronts that share one cluster

@@ -166,8 +166,15 @@ int check_desc(const chain_rk4_desc *d) {
             (d->sites_per_lane == 2 || !valid_sites(d->sites_per_lane)))
             return fail(CHAIN_EINVAL, "the Roessler kernel takes sites_per_lane 0, 4, 6, 8 or 16 (got %d)",
                         d->sites_per_lane);
+    } else if (d->sites_per_lane == 6) {
+        // six sites per lane: the classical RK4 pass of the FP64 nearest-
+        // neighbour chains (96 registers, 5 wavefronts per SIMD)
+        if ((d->model != CHAIN_QUARTIC && d->model != CHAIN_HARMONIC) || d->prec != CHAIN_FP64 ||
+            d->scheme != CHAIN_SCHEME_RK4 || d->method != CHAIN_FUSED)
+            return fail(CHAIN_EINVAL, "sites_per_lane 6 takes the fused classical RK4 of the FP64 "
+                                      "quartic and harmonic chains (and the Roessler chain)");
     } else if (d->sites_per_lane != 0 && !valid_sites(d->sites_per_lane)) {
-        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 2, 4, 8 or 16 (got %d)", d->sites_per_lane);
+        return fail(CHAIN_EINVAL, "sites_per_lane must be 0, 2, 4, 6, 8 or 16 (got %d)", d->sites_per_lane);
     }
     if (d->kdepth < 0 || d->kdepth > kMaxDepth)
         return fail(CHAIN_EINVAL, "kdepth must be in 0..%d (got %d)", kMaxDepth, d->kdepth);

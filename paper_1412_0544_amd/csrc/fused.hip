@@ -85,6 +85,12 @@ hipError_t fused_dispatch_s(int s, int w, const FusedPass &a, hipStream_t st) {
     switch (s) {
     case 2: return fused_dispatch_w<M, R, KAHAN, 2, C>(w, a, st);
     case 4: return fused_dispatch_w<M, R, KAHAN, 4, C>(w, a, st);
+    case 6:
+        // built for the FP64 nearest-neighbour chains only
+        if constexpr (std::is_same<R, double>::value && !KAHAN && (M == kQuartic || M == kHarmonic))
+            return fused_dispatch_w<M, R, KAHAN, 6, C>(w, a, st);
+        else
+            return hipErrorInvalidValue;
     case 8: return fused_dispatch_w<M, R, KAHAN, 8, C>(w, a, st);
     case 16: return fused_dispatch_w<M, R, KAHAN, 16, C>(w, a, st);
     default: return hipErrorInvalidValue;
