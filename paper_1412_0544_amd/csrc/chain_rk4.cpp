@@ -72,18 +72,29 @@ constexpr int kDefaultSitesFp32 = 16;
 constexpr int kDefaultWaves = 4;
 
 // Cluster shape of the quartic and harmonic chains by chain length: the
-// fastest (S, W, k) of two sweeps over S = 2..16, W = 1..8, k = 4..32 and
+// fastest (S, W, k) of sweeps over S = 2..16, W = 1..8, k = 4..32 and
 // N = 2^10..2^26 on MI355X (the granularity study of Sec. 2.3 and 3.2.1).
 // Short chains want many small one-wavefront clusters (no barriers, every
 // CU busy, few instructions per wavefront and step); long ones want few halo
-// sites per kept site.
+// sites per kept site. FP64, with the 6-operation force: a chain that fills
+// the chip about once is fastest where its sites per SIMD come closest to
+// a whole number of wavefronts (6 sites per lane at 2^18-2^19 and in
+// four-wavefront clusters at 2^21, 10-27% over the shapes before). Long
+// chains keep four-wavefront clusters of 8 sites per lane at depth 32:
+// one-wavefront clusters of 16 (214 registers, 2 wavefronts per SIMD, no
+// barriers) at depth 24 ran 1000-step jobs at N = 2^24 1.6-1.8% faster on
+// two boxes, but a 50-step call then takes 4 passes instead of 2 (N = 2^26:
+// 6.4 against 7.8e11 site-updates/s), and at depth 32 they were level
+// (+2.4% and -0.8%).
 struct ShapeRow {
     int64_t max_n;
     int sites, waves, depth;
 };
-constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 17, 2, 1, 16},
-                                   {int64_t(1) << 19, 4, 1, 32},
-                                   {int64_t(1) << 21, 8, 1, 32},
+constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 16, 2, 1, 16},
+                                   {int64_t(1) << 17, 4, 1, 32},
+                                   {int64_t(1) << 19, 6, 1, 32},
+                                   {int64_t(1) << 20, 8, 1, 32},
+                                   {int64_t(1) << 21, 6, 4, 32},
                                    {INT64_MAX, 8, 4, 32}};
 // FP32 state: multi-wavefront clusters from 2^18 sites on, where the all-lane
 // LDS exchange leaves room for more sites per lane. Plain FP32 takes 16 sites
