@@ -27,12 +27,14 @@ WAVES = (1, 2, 4, 8)
 DEPTHS = (1, 2, 4, 6, 8, 12, 16, 24, 32)
 
 
-def default_candidates(prec: str = "fp64"):
+def default_candidates(prec: str = "fp64", model: str = "quartic"):
     """Shapes worth timing: every cluster size at the deeper depths that keep
     at least half of the cluster (the halo of the quartic and harmonic chains
-    is 2 sites per step and side)."""
+    is 2 sites per step and side); 6 sites per lane is built for the FP64
+    quartic and harmonic chains."""
     out = []
-    for s in SITES:
+    sites = SITES + ((6,) if prec == "fp64" and model in ("quartic", "harmonic") else ())
+    for s in sites:
         for w in WAVES:
             for k in (16, 24, 32):
                 if 64 * s * w >= 8 * k:
@@ -116,7 +118,7 @@ def tune(n: int, model: str = "quartic", prec: str = "fp64", dt: float = 0.01,
         q = (torch.rand(n, generator=g, dtype=torch.float64) * 2 - 1).to(device, dtype)
         p = (torch.rand(n, generator=g, dtype=torch.float64) * 2 - 1).to(device, dtype)
     table = {}
-    for shape in candidates or default_candidates(prec):
+    for shape in candidates or default_candidates(prec, model):
         table[tuple(shape)] = time_shape(q, p, dt, shape, model, prec, steps=steps, device=device)
     best = max(table, key=table.get)
     with _lock:

@@ -176,6 +176,23 @@ def test_graph_replays_match_eager():
     graph.close()
 
 
+@pytest.mark.parametrize("n,shape", [(1 << 17, (4, 1, 32)), ((1 << 18) + 77, (6, 1, 32)),
+                                     (1 << 19, (6, 1, 32)), (1 << 21, (6, 4, 32))])
+def test_library_plans_of_chains_that_fill_the_chip_once(n, shape):
+    """The default plans of chains that fill the chip about once (the rows
+    picked by the granularity study): every site after 100 steps against the
+    oracle's whole-ring run, and the energy."""
+    import os
+    q0, p0 = workloads.chain_ics(n, 6)
+    q, p, e, plan = gpu_run(q0, p0, 0.01, 100)
+    assert (plan["sites_per_lane"], plan["waves_per_cluster"], plan["kdepth"]) == shape
+    threads = max(1, min(16, os.cpu_count() or 1))
+    qo, po = oracle.rk4(oracle.QUARTIC, q0, p0, 0.01, 100, threads=threads)
+    assert maxerr(q, qo) <= TOL and maxerr(p, po) <= TOL
+    eo = oracle.energy(oracle.QUARTIC, qo, po)
+    assert abs(e - eo) <= 1e-12 * abs(eo)
+
+
 FULL = 1 << 24
 
 

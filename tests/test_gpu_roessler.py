@@ -125,6 +125,22 @@ def test_paper_size_sampled_sites():
     assert all(np.all(np.isfinite(g)) for g in got)
 
 
+def test_long_chain_plan_sampled_sites():
+    """N = 2^22 (past the paper's size): the long-chain plan, 8 sites per lane
+    at depth 25, against the oracle's light cones at sampled sites."""
+    n = 1 << 22
+    ics = workloads.roessler_ics(n, 2)
+    got, plan = gpu_run(ics, 0.01, 60)
+    assert (plan["sites_per_lane"], plan["waves_per_cluster"], plan["kdepth"]) == (8, 4, 25)
+    tile = plan["tile"]
+    rng = np.random.default_rng(2)
+    sites = np.unique(np.concatenate([[0, 1, n - 1, tile - 1, tile, 2 * tile],
+                                      rng.integers(0, n, 24)]))
+    want = oracle.roessler_rk4_sites(*ics, 0.01, 60, sites)
+    assert maxerr(tuple(g[sites] for g in got), want) <= TOL
+    assert all(np.all(np.isfinite(g)) for g in got)
+
+
 def test_roessler_rejects_energy_and_batches():
     from paper_1412_0544_amd import Batch
     ch = RoesslerChain(*workloads.roessler_ics(100, 0), 0.01)
