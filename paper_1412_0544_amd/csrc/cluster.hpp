@@ -524,6 +524,68 @@ __device__ __forceinline__ void store_lane(const LaneState<R, KAHAN, S, C> &st, 
     }
 }
 
+// Device-coherent stores of one array of a wavefront's kept sites through a
+// staging area in LDS of 64*S values. Lane l holds S consecutive values, so
+// unstaged, store m of the wavefront writes 16 bytes at every 16*S-th byte:
+// half of each 32-byte sector, and each store counts as a whole sector in
+// memory (those stores moved twice their bytes). Staged, lane l first puts
+// its values in its own S slots; then store m of lane l moves piece 64*m + l
+// (16 bytes), so one store instruction covers 1 KB of consecutive addresses.
+// `keep(pos)` says which cluster-local positions are written; a piece whose
+// values are all kept goes as one 16-byte store, a piece cut by the end of
+// the kept positions (the end of a chain that is not a multiple of 4 sites)
+// value by value. `out_e0` is the array at the cluster origin and `bytes`
+// the window the buffer resource spans (a store beyond it is dropped). Only
+// this wavefront's lanes touch `stage`, so wavefront-scope ordering suffices
+// between its write and reads.
+template <class R, int S, class Keep>
+__device__ __forceinline__ void store_staged(R *stage, const R (&v)[S], R *out_e0, int bytes,
+                                             int lane, int wlo, Keep keep) {
+    constexpr int P = 16 / static_cast<int>(sizeof(R));  // values per 16-byte piece
+    static_assert(S % P == 0, "whole 16-byte pieces per lane");
+    using U4 = __attribute__((ext_vector_type(4))) unsigned;
+    struct Piece {
+        R x[P];
+    };
+#pragma unroll
+    for (int m = 0; m < S / P; ++m) {
+        Piece pc;
+#pragma unroll
+        for (int t = 0; t < P; ++t) pc.x[t] = v[P * m + t];
+        *reinterpret_cast<U4 *>(stage + lane * S + P * m) = __builtin_bit_cast(U4, pc);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const __amdgpu_buffer_rsrc_t r = window_rsrc(out_e0, bytes);
+#pragma unroll
+    for (int m = 0; m < S / P; ++m) {
+        const int c = 64 * m + lane;   // piece of this wavefront
+        const int loc = wlo + P * c;   // cluster-local position of its first value
+        const U4 x = *reinterpret_cast<const U4 *>(stage + P * c);
+        bool all = true, any = false;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const bool k = keep(loc + t);
+            all = all && k;
+            any = any || k;
+        }
+        if (all) {
+            __builtin_amdgcn_raw_buffer_store_b128(x, r, loc * static_cast<int>(sizeof(R)), 0,
+                                                   kDeviceCoherent);
+        } else if (any) {
+            const Piece pc = __builtin_bit_cast(Piece, x);
+#pragma unroll
+            for (int t = 0; t < P; ++t)
+                if (keep(loc + t)) store_coherent(out_e0 + loc + t, pc.x[t]);
+        }
+    }
+    // the next array reuses the staging area
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One cluster pass: the cluster holds sites [e0, e0 + 64*S*W) of the
 // unwrapped ring (wrapped mod n on load), advances them `ksteps` steps and
 // stores the sites at cluster-local positions [halo, halo + keep). The wrong
@@ -536,7 +598,8 @@ template <int M, class R, bool KAHAN, int S, int W, int WPB, bool COH = false, c
 __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &out, int64_t n,
                                             int64_t e0, int64_t halo, int64_t keep, int ksteps,
                                             double dt, SlotsOf<M, R, W, WPB> *slots, int lane,
-                                            int wib, int wic, int prio_total = 0) {
+                                            int wib, int wic, int prio_total = 0,
+                                            R *stage = nullptr) {
     constexpr int E = 64 * S * W;
     const int lo = (wic * 64 + lane) * S;
     const int64_t s0 = e0 + lo;
@@ -576,6 +639,26 @@ __device__ __forceinline__ void run_cluster(const StateRef &in, const StateRef &
     // registers and pushed it past 128).
     int lane_s = lane;
     asm volatile("" : "+v"(lane_s));
+    if constexpr (COH && (!KAHAN || std::is_same<C, R>::value) && (S * sizeof(R)) % 16 == 0) {
+        if (stage) {
+            // kept sites never wrap, and the chain ends at n: the kept range
+            // in cluster-local positions, and each array at the cluster origin
+            const int kl = static_cast<int>(halo);
+            const int kh = static_cast<int>(halo + keep < n - e0 ? halo + keep : n - e0);
+            const int wlo = wic * 64 * S;
+            constexpr int bytes = E * static_cast<int>(sizeof(R));
+            auto kept = [kl, kh](int pos) { return pos >= kl && pos < kh; };
+            store_staged<R, S>(stage, st.q, static_cast<R *>(out.q) + e0, bytes, lane_s, wlo, kept);
+            store_staged<R, S>(stage, st.p, static_cast<R *>(out.p) + e0, bytes, lane_s, wlo, kept);
+            if constexpr (KAHAN) {
+                store_staged<R, S>(stage, st.cq, static_cast<R *>(out.cq) + e0, bytes, lane_s, wlo,
+                                   kept);
+                store_staged<R, S>(stage, st.cp, static_cast<R *>(out.cp) + e0, bytes, lane_s, wlo,
+                                   kept);
+            }
+            return;
+        }
+    }
     const int lo_s = (wic * 64 + lane_s) * S;
     store_lane<R, KAHAN, S, COH, C>(st, out, n, e0 + lo_s, lo_s, halo, halo + keep, E);
 }

@@ -90,7 +90,15 @@ __attribute__((amdgpu_waves_per_eu((S <= 8 && !RES) ? 4 : 1))) void persistent_k
     constexpr int SPT = RMAX / kBatchThreads;
     constexpr int E = 64 * S * W;
     __shared__ SlotsOf<M, R, W, WPB> slots;
-    __shared__ __align__(16) R ring[RES ? 2 * RMAX : 1];
+    // Resident rings use `ring`; cluster items give each wavefront a staging
+    // area for its device-coherent stores. A workgroup runs one item at a
+    // time (a barrier separates them), so the two share one LDS buffer.
+    constexpr bool STAGED = COH && (S * sizeof(R)) % 16 == 0;
+    constexpr int RING = RES ? 2 * RMAX : 1;
+    constexpr int STAGE = STAGED ? WPB * 64 * S : 1;
+    __shared__ __align__(16) R lds_buf[RING > STAGE ? RING : STAGE];
+    R *const ring = lds_buf;
+    R *const stage = lds_buf;
     __shared__ long long claimed;
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -139,7 +147,8 @@ __attribute__((amdgpu_waves_per_eu((S <= 8 && !RES) ? 4 : 1))) void persistent_k
             const int ksteps = __builtin_amdgcn_readfirstlane(pass_steps(ch, pass, a.depth));
             run_cluster<M, R, KAHAN, S, W, WPB, COH>(in, out, uniform64(ch.n), start - a.halo,
                                                      a.halo, keep, ksteps, uniform_f64(ch.dt),
-                                                     &slots, lane, wib, wib);
+                                                     &slots, lane, wib, wib, 0,
+                                                     STAGED ? stage + wib * 64 * S : nullptr);
             if constexpr (COH)
                 drain_memory();
             else
@@ -180,7 +189,7 @@ __attribute__((amdgpu_waves_per_eu((S <= 8 && !RES) ? 4 : 1))) void persistent_k
                     run_cluster<M, R, KAHAN, S, 1, WPB, COH>(
                         in, out, uniform64(ch.n), start - a.halo, a.halo, keep, ksteps,
                         uniform_f64(ch.dt), static_cast<SlotsOf<M, R, 1, WPB> *>(nullptr), lane,
-                        wib, 0);
+                        wib, 0, 0, STAGED ? stage + wib * 64 * S : nullptr);
                     if constexpr (COH)
                         drain_memory();
                     else

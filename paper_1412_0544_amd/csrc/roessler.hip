@@ -142,6 +142,8 @@ __global__ __launch_bounds__(64 * W) void roessler_exchange_kernel(ExchangeRun a
     constexpr int E = 64 * S * W;
     constexpr int NL = W > 1 ? 64 * W : 1;
     __shared__ LaneEdges<NL> edges;
+    // each wavefront's staging area for the edge sites it hands on
+    __shared__ __align__(16) double stage[W * 64 * S];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int gl = wib * 64 + lane;
@@ -185,26 +187,22 @@ __global__ __launch_bounds__(64 * W) void roessler_exchange_kernel(ExchangeRun a
         const int h = static_cast<int>(a.halo), kp = static_cast<int>(keep);
         const int zn = static_cast<int>(a.zone);
         const int64_t sx = e0 + lx;
-        // kept sites never wrap: site sx + j is start + (lx + j - halo) < n.
-        // A lane whose sites all go out stores them 16 bytes at a time (the
-        // resource spans the cluster's window from its origin e0, which may
-        // lie before the array; only kept sites, inside it, are written).
-        if (lx >= h && lx + S <= h + kp && (lx + S <= h + zn || lx >= kp)) {
-            constexpr int bytes = E * static_cast<int>(sizeof(double));
-            store_window<double, S>(window_rsrc(xe + e0, bytes), lx * 8, x);
-            store_window<double, S>(window_rsrc(ye + e0, bytes), lx * 8, y);
-            store_window<double, S>(window_rsrc(ze + e0, bytes), lx * 8, z);
-        } else {
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                const int local = lx + j;
-                if (local >= h && local < h + kp && (local < h + zn || local >= kp)) {
-                    store_coherent(xe + sx + j, x[j]);
-                    store_coherent(ye + sx + j, y[j]);
-                    store_coherent(ze + sx + j, z[j]);
-                }
-            }
-        }
+        // The kept sites the neighbours read: the first `zone` (the left
+        // neighbour's right halo) and the last `halo`. Kept sites never wrap
+        // (site e0 + pos is start + pos - halo < n); the buffer resource spans
+        // the cluster's window from its origin e0, which may lie before the
+        // array, and only kept sites, inside it, are written. Staged through
+        // LDS, each store instruction covers consecutive 16-byte pieces.
+        auto handed = [h, kp, zn](int pos) {
+            return pos >= h && pos < h + kp && (pos < h + zn || pos >= kp);
+        };
+        constexpr int bytes = E * static_cast<int>(sizeof(double));
+        const int wv = lane_x >> 6, ln = lane_x & 63;  // wavefront in the block, lane
+        double *st = stage + wv * 64 * S;
+        const int wlo = wv * 64 * S;                    // the wavefront's first local site
+        store_staged<double, S>(st, x, xe + e0, bytes, ln, wlo, handed);
+        store_staged<double, S>(st, y, ye + e0, bytes, ln, wlo, handed);
+        store_staged<double, S>(st, z, ze + e0, bytes, ln, wlo, handed);
         drain_memory();
         __syncthreads();
         if (threadIdx.x == 0) {
