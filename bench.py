@@ -677,9 +677,12 @@ def variant_batch(dt, dev, steps=2000, count=4096, precs=("fp64", "fp32_kahan"),
 
 
 def variant_persistent_single(qd, pd, dt, dev, steps=1000):
+    """The bench chain as a batch of one: one persistent launch for all the
+    steps of a job (the batch's default shape), against the per-pass fused
+    launches of the headline."""
     from paper_1412_0544_amd import Batch, Chain
     ch = Chain(qd, pd, dt, device=dev)
-    b = Batch([ch], max_steps=steps, sites_per_lane=4, kdepth=16)
+    b = Batch([ch], max_steps=steps)
     b.step(32)
     t = ev_seconds(lambda: b.step(steps), ch.stream)
     b.check()
