@@ -253,3 +253,26 @@ def test_preset_tableaus_are_the_literature_values():
     for name, (a, b) in tableaus.ALL.items():
         (a0, b0), _ = TABLEAUS[name]
         assert np.array_equal(np.array(a), a0) and np.array_equal(np.array(b), b0), name
+
+
+def test_six_sites_per_lane_only_where_it_is_built():
+    """6 sites per lane: the fused classical RK4 of the FP64 quartic and
+    harmonic chains and the Roessler chain (fused and exchange form); every
+    other descriptor is refused before any HIP call."""
+    lib = L.lib()
+    ok = [desc(sites_per_lane=6), desc(model=L.CHAIN_HARMONIC, sites_per_lane=6),
+          desc(model=L.CHAIN_ROESSLER, sites_per_lane=6),
+          desc(n=20000, model=L.CHAIN_ROESSLER, sites_per_lane=6, flags=L.CHAIN_FLAG_EXCHANGE)]
+    bad = [desc(prec=L.CHAIN_FP32_KAHAN, sites_per_lane=6),
+           desc(prec=L.CHAIN_FP32, sites_per_lane=6),
+           desc(model=L.CHAIN_QUARTIC_NNN, sites_per_lane=6),
+           desc(sites_per_lane=6, method=L.CHAIN_NAIVE),
+           desc(sites_per_lane=6, scheme=L.CHAIN_SCHEME_TABLEAU),
+           desc(sites_per_lane=5), desc(sites_per_lane=12)]
+    for d in ok:
+        assert lib.chain_rk4_workspace_bytes(ctypes.byref(d)) > 0
+        P = L.Plan()
+        assert lib.chain_rk4_plan_for(ctypes.byref(d), None, ctypes.byref(P)) == L.CHAIN_OK
+        assert P.sites_per_lane == 6
+    for d in bad:
+        assert lib.chain_rk4_workspace_bytes(ctypes.byref(d)) == 0
