@@ -269,6 +269,8 @@ def main(argv=None):
                          "--serve-rho")
     ap.add_argument("--serve-rho", default="0.5,0.8",
                     help="offered loads of --serve, comma separated")
+    ap.add_argument("--serve-sites", type=int, default=4,
+                    help="sites per lane of the job server's rounds (--serve)")
     ap.add_argument("--serve-rate", type=float, default=6.5e11,
                     help="device capacity (site-updates/s) the loads of --serve refer to")
     ap.add_argument("--roessler-n", type=int, default=1 << 20,
@@ -322,7 +324,8 @@ def main(argv=None):
         for rho in (float(x) for x in args.serve_rho.split(",")):
             log(f"[bench] serving {args.serve_jobs} jobs at load {rho}")
             loads[str(rho)] = variant_serving(0.01, dev, jobs=args.serve_jobs, rho=rho,
-                                              rate_su=args.serve_rate)
+                                              rate_su=args.serve_rate,
+                                              sites_per_lane=args.serve_sites)
         print(json.dumps({"metric": "served-job latency p50/p99 and throughput", "unit": "s",
                           "n_gpus": 1, "data": "synthetic",
                           "config": {"workload": f"{args.serve_jobs} jobs, N log-uniform "
@@ -699,7 +702,7 @@ SERVE_BUDGET = 256 << 20
 
 
 def variant_serving(dt, dev, jobs=500, rho=0.8, rate_su=4e11, budget=SERVE_BUDGET, quantum=1000,
-                    max_active=64):
+                    max_active=64, sites_per_lane=4):
     """Poisson arrivals at load rho of `rate_su`; N log-uniform in [1e3, 4e6],
     steps uniform in [1e3, 1e5], FP64/FP32 and quartic/harmonic each a coin;
     admission in arrival order while the HBM budget and a slot allow."""
@@ -709,7 +712,7 @@ def variant_serving(dt, dev, jobs=500, rho=0.8, rate_su=4e11, budget=SERVE_BUDGE
     lam = rho * rate_su / mean_work
     js = workloads.served_jobs(jobs, lam, seed=5)
     ex = GpuExecutor(device=dev, dt=dt, quantum=quantum, max_active=max_active,
-                     hbm_budget=budget)
+                     hbm_budget=budget, sites_per_lane=sites_per_lane)
     srv = Server(ex, hbm_budget=budget, max_active=max_active, quantum=quantum)
     t0 = time.perf_counter()
     res = srv.run(js)
