@@ -79,7 +79,10 @@ constexpr int kDefaultWaves = 4;
 // sites per kept site. FP64, with the 6-operation force: a chain that fills
 // the chip about once is fastest where its sites per SIMD come closest to
 // a whole number of wavefronts (6 sites per lane at 2^18-2^19 and in
-// four-wavefront clusters at 2^21, 10-27% over the shapes before). Long
+// four-wavefront clusters at 2^21, 10-27% over the shapes before). Up to
+// 2^14 sites the chip is far from full and a call's time is its passes'
+// latency, so passes of 28 steps (halo 56 of each 128-site cluster) beat
+// 16: a 1000-step call on 1024 sites takes 0.26 instead of 0.32 ms. Long
 // chains keep four-wavefront clusters of 8 sites per lane at depth 32:
 // one-wavefront clusters of 16 (214 registers, 2 wavefronts per SIMD, no
 // barriers) at depth 24 ran 1000-step jobs at N = 2^24 1.6-1.8% faster on
@@ -90,7 +93,8 @@ struct ShapeRow {
     int64_t max_n;
     int sites, waves, depth;
 };
-constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 16, 2, 1, 16},
+constexpr ShapeRow kShapeFp64[] = {{int64_t(1) << 14, 2, 1, 28},
+                                   {int64_t(1) << 16, 2, 1, 16},
                                    {int64_t(1) << 17, 4, 1, 32},
                                    {int64_t(1) << 19, 6, 1, 32},
                                    {int64_t(1) << 20, 8, 1, 32},

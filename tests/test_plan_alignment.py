@@ -172,7 +172,8 @@ def test_plan_for_validates_like_create():
     assert (P.halo, P.tile, P.waves) == (64, 1920, -(-(1 << 24) // 1920))
     # chains that fill the chip about once: 6 sites per lane at 2^18-2^19 and
     # in four-wavefront clusters at 2^21
-    for n, shape in ((1 << 16, (2, 1, 16)), (1 << 17, (4, 1, 32)), (1 << 19, (6, 1, 32)),
+    for n, shape in ((1 << 10, (2, 1, 28)), (1 << 14, (2, 1, 28)), ((1 << 14) + 1, (2, 1, 16)),
+                     (1 << 16, (2, 1, 16)), (1 << 17, (4, 1, 32)), (1 << 19, (6, 1, 32)),
                      (1 << 20, (8, 1, 32)), (1 << 21, (6, 4, 32)), ((1 << 21) + 1, (8, 4, 32))):
         rc, P = plan(n, L.CHAIN_QUARTIC, L.CHAIN_FP64, 0, 0, 0)
         assert rc == L.CHAIN_OK
