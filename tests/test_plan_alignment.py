@@ -178,3 +178,10 @@ def test_plan_for_validates_like_create():
         rc, P = plan(n, L.CHAIN_QUARTIC, L.CHAIN_FP64, 0, 0, 0)
         assert rc == L.CHAIN_OK
         assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, n
+    # the FP32 forms: the same short-chain rows, then four-wavefront clusters
+    for prec in (L.CHAIN_FP32_KAHAN, L.CHAIN_FP32):
+        for n, shape in ((1 << 10, (2, 1, 28)), (1 << 14, (2, 1, 28)), (1 << 16, (2, 1, 16)),
+                         (1 << 17, (4, 1, 32)), (1 << 18, (2, 4, 32))):
+            rc, P = plan(n, L.CHAIN_QUARTIC, prec, 0, 0, 0)
+            assert rc == L.CHAIN_OK
+            assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (prec, n)
