@@ -144,6 +144,26 @@ ShapeRow shape_for(int prec, int64_t n) {
 // for 4 sites per lane at depth 16, N = 2^24).
 constexpr int kDefaultWavesRoessler = 4;
 constexpr int kRoesslerDepth = 25;
+// Shorter Roessler chains (fused passes, library shape): one-wavefront
+// clusters while the chip is far from full; a 1000-step call on 2^10..2^14
+// sites took 0.52 instead of 0.86 ms with 4 sites per lane at depth 25 in
+// one wavefront, 0.61 against 0.86 ms at 2^16 at depth 16, and 0.99 against
+// 1.14 ms at 2^18 with 8 sites per lane; from 2^19 on the rows above hold.
+constexpr ShapeRow kShapeRoessler[] = {{int64_t(1) << 14, 4, 1, 25},
+                                       {int64_t(1) << 16, 4, 1, 16},
+                                       {int64_t(1) << 18, 8, 1, 25},
+                                       {int64_t(1) << 21, 4, 4, 25},
+                                       {INT64_MAX, 8, 4, 25}};
+// FP64 chains with second-neighbour bonds (reach 4 per step): the same for
+// short chains (1000-step calls at 2^10..2^14 sites 0.46-0.49 against
+// 2.05 ms with the long-chain shape, 0.64 against 2.07 at 2^16, 1.06
+// against 2.09 at 2^18, 2.85 against 3.59 at 2^20); from 2^21 on four
+// wavefronts of 8 sites per lane at depth 16 (the best of a sweep at 2^22).
+constexpr ShapeRow kShapeNnnFp64[] = {{int64_t(1) << 14, 2, 1, 14},
+                                      {int64_t(1) << 16, 2, 1, 8},
+                                      {int64_t(1) << 18, 4, 1, 16},
+                                      {int64_t(1) << 20, 8, 1, 16},
+                                      {INT64_MAX, 8, 4, 16}};
 constexpr int64_t kRoesslerShortSites = int64_t(1) << 21;
 constexpr int kRoesslerShortSitesPerLane = 4;
 constexpr int kRoesslerLongSitesPerLane = 8;
@@ -367,15 +387,26 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
         return P;
     }
     const ShapeRow row = shape_for(d->prec, d->n);
+    // library shapes by chain length (when neither S nor W is given)
+    const bool free_shape = !d->sites_per_lane && !d->waves_per_cluster;
+    const bool roe_table = roessler && !(d->flags & CHAIN_FLAG_EXCHANGE) && free_shape;
+    const bool nnn_table = (d->model == CHAIN_QUARTIC_NNN || d->model == CHAIN_HARMONIC_NNN) &&
+                           d->prec == CHAIN_FP64 && !tab && free_shape;
+    const ShapeRow rrow = row_for(kShapeRoessler, d->n);
+    const ShapeRow nrow = row_for(kShapeNnnFp64, d->n);
     P.sites = d->sites_per_lane ? d->sites_per_lane
               : roessler && (d->flags & CHAIN_FLAG_EXCHANGE)
                   ? kExchangeSitesRoessler
+              : roe_table       ? rrow.sites
+              : nnn_table       ? nrow.sites
               : roessler        ? (d->n <= kRoesslerShortSites ? kRoesslerShortSitesPerLane
                                                                : kRoesslerLongSitesPerLane)
               : tab             ? default_sites_tableau(stages)
               : nn              ? row.sites
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
+                          : roe_table            ? rrow.waves
+                          : nnn_table            ? nrow.waves
                           : roessler             ? kDefaultWavesRoessler
                           : nn && !tab           ? row.waves
                                                  : kDefaultWaves;
@@ -385,6 +416,8 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
               : table_shape ? row.depth
               : roessler && (d->flags & CHAIN_FLAG_EXCHANGE)
                   ? kExchangeDepthRoessler
+              : roe_table ? rrow.depth
+              : nnn_table ? nrow.depth
               : roessler ? kRoesslerDepth
                   : static_cast<int>(std::min<int64_t>(
                         kMaxDepth, std::max<int64_t>(1, kDefaultHalo / reach)));

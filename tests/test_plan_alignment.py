@@ -178,6 +178,17 @@ def test_plan_for_validates_like_create():
         rc, P = plan(n, L.CHAIN_QUARTIC, L.CHAIN_FP64, 0, 0, 0)
         assert rc == L.CHAIN_OK
         assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, n
+    # the Roessler chain (fused passes) and the FP64 second-neighbour chains
+    for model, rows in ((L.CHAIN_ROESSLER, ((1 << 10, (4, 1, 25)), (1 << 16, (4, 1, 16)),
+                                            (1 << 18, (8, 1, 25)), (1 << 20, (4, 4, 25)),
+                                            (1 << 24, (8, 4, 25)))),
+                        (L.CHAIN_QUARTIC_NNN, ((1 << 10, (2, 1, 14)), (1 << 16, (2, 1, 8)),
+                                               (1 << 18, (4, 1, 16)), (1 << 20, (8, 1, 16)),
+                                               (1 << 24, (8, 4, 16))))):
+        for n, shape in rows:
+            rc, P = plan(n, model, L.CHAIN_FP64, 0, 0, 0)
+            assert rc == L.CHAIN_OK
+            assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (model, n)
     # the FP32 forms: the same short-chain rows, then four-wavefront clusters
     for prec in (L.CHAIN_FP32_KAHAN, L.CHAIN_FP32):
         for n, shape in ((1 << 10, (2, 1, 28)), (1 << 14, (2, 1, 28)), (1 << 16, (2, 1, 16)),
