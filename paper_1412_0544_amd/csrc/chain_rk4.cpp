@@ -164,6 +164,23 @@ constexpr ShapeRow kShapeNnnFp64[] = {{int64_t(1) << 14, 2, 1, 14},
                                       {int64_t(1) << 18, 4, 1, 16},
                                       {int64_t(1) << 20, 8, 1, 16},
                                       {INT64_MAX, 8, 4, 16}};
+// The plain and compensated FP32 forms of those chains (one table for both:
+// their timings rank the shapes alike): 1000-step calls at 2^10..2^14 sites
+// 0.44 against 2.92 ms (compensated) with the long-chain shape, 0.59 against
+// 3.05 at 2^16, 1.12 against 3.07 at 2^18, 2.25 against 3.24 at 2^20 in four
+// wavefronts of 4 sites per lane, 6.32 against 7.26 at 2^22 with 8 per lane;
+// longer chains keep 16 sites per lane.
+constexpr ShapeRow kShapeNnnFp32[] = {{int64_t(1) << 14, 2, 1, 14},
+                                      {int64_t(1) << 16, 2, 1, 8},
+                                      {int64_t(1) << 18, 4, 1, 16},
+                                      {int64_t(1) << 20, 4, 4, 16},
+                                      {int64_t(1) << 22, 8, 4, 16},
+                                      {INT64_MAX, 16, 4, 16}};
+// FP64 tableau passes up to 2^18 sites: one wavefront of 4 sites per lane at
+// the default depth (1000 steps of 2^10..2^16 sites 0.49 against 1.37 ms for
+// the 3/8-rule tableau, 0.68 against 1.62 ms for Dormand-Prince 5; at 2^18
+// 0.78 against 1.40 and 1.22 against 2.00 ms).
+constexpr int64_t kTableauShortSites = int64_t(1) << 18;
 constexpr int64_t kRoesslerShortSites = int64_t(1) << 21;
 constexpr int kRoesslerShortSitesPerLane = 4;
 constexpr int kRoesslerLongSitesPerLane = 8;
@@ -391,9 +408,13 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
     const bool free_shape = !d->sites_per_lane && !d->waves_per_cluster;
     const bool roe_table = roessler && !(d->flags & CHAIN_FLAG_EXCHANGE) && free_shape;
     const bool nnn_table = (d->model == CHAIN_QUARTIC_NNN || d->model == CHAIN_HARMONIC_NNN) &&
-                           d->prec == CHAIN_FP64 && !tab && free_shape;
+                           (d->prec == CHAIN_FP64 || d->prec == CHAIN_FP32 ||
+                            d->prec == CHAIN_FP32_KAHAN) &&
+                           !tab && free_shape;
+    const bool tab_short = tab && free_shape && d->prec == CHAIN_FP64 && d->n <= kTableauShortSites;
     const ShapeRow rrow = row_for(kShapeRoessler, d->n);
-    const ShapeRow nrow = row_for(kShapeNnnFp64, d->n);
+    const ShapeRow nrow = d->prec == CHAIN_FP64 ? row_for(kShapeNnnFp64, d->n)
+                                                 : row_for(kShapeNnnFp32, d->n);
     P.sites = d->sites_per_lane ? d->sites_per_lane
               : roessler && (d->flags & CHAIN_FLAG_EXCHANGE)
                   ? kExchangeSitesRoessler
@@ -401,12 +422,14 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
               : nnn_table       ? nrow.sites
               : roessler        ? (d->n <= kRoesslerShortSites ? kRoesslerShortSitesPerLane
                                                                : kRoesslerLongSitesPerLane)
+              : tab_short       ? 4
               : tab             ? default_sites_tableau(stages)
               : nn              ? row.sites
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
                           : roe_table            ? rrow.waves
                           : nnn_table            ? nrow.waves
+                          : tab_short            ? 1
                           : roessler             ? kDefaultWavesRoessler
                           : nn && !tab           ? row.waves
                                                  : kDefaultWaves;

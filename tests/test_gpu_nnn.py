@@ -125,6 +125,23 @@ def test_fp32_kahan_error_bound_and_identical_bits(n):
     assert maxerr(q, qo) <= 1e-5 and maxerr(p, po) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32"])
+@pytest.mark.parametrize("n,shape", [(100003, (4, 1, 16)), (600011, (4, 4, 16)),
+                                     (1 << 21, (8, 4, 16)), (5000, (2, 1, 14))])
+def test_fp32_library_rows_identical_bits(prec, n, shape):
+    """The library's shapes for FP32 chains with second-neighbour bonds (one
+    wavefront up to 2^18 sites, four beyond) give the bits of the
+    one-kernel-per-stage method, carries included."""
+    q0, p0 = workloads.chain_ics(n, 8, dtype=np.float32)
+    a = gpu_run(q0, p0, 0.01, 40, model="harmonic_nnn", prec=prec)
+    pl = a[3]
+    assert (pl["sites_per_lane"], pl["waves_per_cluster"], pl["kdepth"]) == shape
+    b = gpu_run(q0, p0, 0.01, 40, model="harmonic_nnn", prec=prec, method="naive")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    if a[4] is not None:
+        assert np.array_equal(a[4][0], b[4][0]) and np.array_equal(a[4][1], b[4][1])
+
+
 def test_large_chain_sampled_sites():
     """N = 2^22, default plan, 100 steps: sampled sites vs the oracle's light
     cones (2 * 8 * 100 + 1 sites each)."""

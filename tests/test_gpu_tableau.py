@@ -90,6 +90,10 @@ def test_shapes_and_depths_identical_bits(name):
         for k in (2, 5, 16, 32):
             got = gpu_run(q0, p0, 0.01, 37, name, sites_per_lane=s, waves_per_cluster=w, kdepth=k)
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (s, w, k)
+    # the library's plan for chains up to 2^18 sites: one wavefront of 4 per lane
+    got = gpu_run(q0, p0, 0.01, 37, name)
+    assert (got[3]["sites_per_lane"], got[3]["waves_per_cluster"]) == (4, 1)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
 @pytest.mark.parametrize("model", ["harmonic", "harmonic_nnn"])

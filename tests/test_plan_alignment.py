@@ -189,6 +189,22 @@ def test_plan_for_validates_like_create():
             rc, P = plan(n, model, L.CHAIN_FP64, 0, 0, 0)
             assert rc == L.CHAIN_OK
             assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (model, n)
+    # the FP32 forms of the second-neighbour chains
+    for prec in (L.CHAIN_FP32_KAHAN, L.CHAIN_FP32):
+        for n, shape in ((1 << 10, (2, 1, 14)), (1 << 16, (2, 1, 8)), (1 << 18, (4, 1, 16)),
+                         (1 << 20, (4, 4, 16)), (1 << 22, (8, 4, 16)), (1 << 24, (16, 4, 16))):
+            rc, P = plan(n, L.CHAIN_HARMONIC_NNN, prec, 0, 0, 0)
+            assert rc == L.CHAIN_OK
+            assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (prec, n)
+    # FP64 tableau passes: one wavefront of 4 sites per lane up to 2^18 sites
+    for name, depth, long_sites in (("rk4_38", 32, 8), ("dopri5", 21, 4)):
+        (a, b), _ = TABLEAUS[name]
+        t = make_tableau(a.tolist(), b.tolist())
+        for n, shape in ((1 << 10, (4, 1, depth)), (1 << 18, (4, 1, depth)),
+                         ((1 << 18) + 1, (long_sites, 4, depth))):
+            rc, P = plan(n, L.CHAIN_QUARTIC, L.CHAIN_FP64, 0, 0, 0, tab=t)
+            assert rc == L.CHAIN_OK
+            assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (name, n)
     # the FP32 forms: the same short-chain rows, then four-wavefront clusters
     for prec in (L.CHAIN_FP32_KAHAN, L.CHAIN_FP32):
         for n, shape in ((1 << 10, (2, 1, 28)), (1 << 14, (2, 1, 28)), (1 << 16, (2, 1, 16)),
