@@ -176,11 +176,15 @@ constexpr ShapeRow kShapeNnnFp32[] = {{int64_t(1) << 14, 2, 1, 14},
                                       {int64_t(1) << 20, 4, 4, 16},
                                       {int64_t(1) << 22, 8, 4, 16},
                                       {INT64_MAX, 16, 4, 16}};
-// FP64 tableau passes up to 2^18 sites: one wavefront of 4 sites per lane at
-// the default depth (1000 steps of 2^10..2^16 sites 0.49 against 1.37 ms for
-// the 3/8-rule tableau, 0.68 against 1.62 ms for Dormand-Prince 5; at 2^18
-// 0.78 against 1.40 and 1.22 against 2.00 ms).
+// Tableau passes up to 2^18 sites: one wavefront of 4 sites per lane at the
+// default depth (FP64: 1000 steps of 2^10..2^16 sites 0.49 against 1.37 ms
+// for the 3/8-rule tableau, 0.68 against 1.62 ms for Dormand-Prince 5; at
+// 2^18 0.78 against 1.40 and 1.22 against 2.00 ms; compensated FP32: 0.64
+// against 1.56 and 0.92 against 1.53 ms, at 2^18 0.90 against 1.58 and 1.36
+// against 1.56). Compensated FP32 up to 2^20: four wavefronts of 4 sites per
+// lane (2.01 against 2.32 ms for the 3/8 rule; Dormand-Prince 5 has them).
 constexpr int64_t kTableauShortSites = int64_t(1) << 18;
+constexpr int64_t kTableauMidSitesFp32 = int64_t(1) << 20;
 constexpr int64_t kRoesslerShortSites = int64_t(1) << 21;
 constexpr int kRoesslerShortSitesPerLane = 4;
 constexpr int kRoesslerLongSitesPerLane = 8;
@@ -411,7 +415,10 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
                            (d->prec == CHAIN_FP64 || d->prec == CHAIN_FP32 ||
                             d->prec == CHAIN_FP32_KAHAN) &&
                            !tab && free_shape;
-    const bool tab_short = tab && free_shape && d->prec == CHAIN_FP64 && d->n <= kTableauShortSites;
+    const bool tab_tuned = tab && free_shape && (d->prec == CHAIN_FP64 || d->prec == CHAIN_FP32_KAHAN);
+    const bool tab_short = tab_tuned && d->n <= kTableauShortSites;
+    const bool tab_four = tab_short || (tab_tuned && d->prec == CHAIN_FP32_KAHAN &&
+                                        d->n <= kTableauMidSitesFp32);
     const ShapeRow rrow = row_for(kShapeRoessler, d->n);
     const ShapeRow nrow = d->prec == CHAIN_FP64 ? row_for(kShapeNnnFp64, d->n)
                                                  : row_for(kShapeNnnFp32, d->n);
@@ -422,7 +429,7 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
               : nnn_table       ? nrow.sites
               : roessler        ? (d->n <= kRoesslerShortSites ? kRoesslerShortSitesPerLane
                                                                : kRoesslerLongSitesPerLane)
-              : tab_short       ? 4
+              : tab_four        ? 4
               : tab             ? default_sites_tableau(stages)
               : nn              ? row.sites
               : (d->prec == CHAIN_FP64 ? kDefaultSitesFp64 : kDefaultSitesFp32);

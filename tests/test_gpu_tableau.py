@@ -206,7 +206,7 @@ def test_large_chain_sampled_sites():
 
 @pytest.mark.parametrize("name", sorted(TABLEAUS) + ["euler"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
-@pytest.mark.parametrize("n", [1, 3, 5003])
+@pytest.mark.parametrize("n", [1, 3, 5003, 300007])
 def test_per_stage_path_gives_the_fused_bits(name, prec, n):
     """The one-kernel-per-stage implementation of a tableau method (the
     paper's standard version, Sec. 2.2) and the fused cluster pass give the

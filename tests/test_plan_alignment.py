@@ -196,15 +196,18 @@ def test_plan_for_validates_like_create():
             rc, P = plan(n, L.CHAIN_HARMONIC_NNN, prec, 0, 0, 0)
             assert rc == L.CHAIN_OK
             assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (prec, n)
-    # FP64 tableau passes: one wavefront of 4 sites per lane up to 2^18 sites
+    # tableau passes: one wavefront of 4 sites per lane up to 2^18 sites, then
+    # four wavefronts (of 4 sites per lane up to 2^20 for compensated FP32)
     for name, depth, long_sites in (("rk4_38", 32, 8), ("dopri5", 21, 4)):
         (a, b), _ = TABLEAUS[name]
         t = make_tableau(a.tolist(), b.tolist())
-        for n, shape in ((1 << 10, (4, 1, depth)), (1 << 18, (4, 1, depth)),
-                         ((1 << 18) + 1, (long_sites, 4, depth))):
-            rc, P = plan(n, L.CHAIN_QUARTIC, L.CHAIN_FP64, 0, 0, 0, tab=t)
-            assert rc == L.CHAIN_OK
-            assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (name, n)
+        for prec, mid in ((L.CHAIN_FP64, long_sites), (L.CHAIN_FP32_KAHAN, 4)):
+            for n, shape in ((1 << 10, (4, 1, depth)), (1 << 18, (4, 1, depth)),
+                             ((1 << 18) + 1, (mid, 4, depth)),
+                             ((1 << 20) + 1, (long_sites, 4, depth))):
+                rc, P = plan(n, L.CHAIN_QUARTIC, prec, 0, 0, 0, tab=t)
+                assert rc == L.CHAIN_OK
+                assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (name, prec, n)
     # the FP32 forms: the same short-chain rows, then four-wavefront clusters
     for prec in (L.CHAIN_FP32_KAHAN, L.CHAIN_FP32):
         for n, shape in ((1 << 10, (2, 1, 28)), (1 << 14, (2, 1, 28)), (1 << 16, (2, 1, 16)),
