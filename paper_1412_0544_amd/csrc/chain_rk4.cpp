@@ -185,6 +185,9 @@ constexpr ShapeRow kShapeNnnFp32[] = {{int64_t(1) << 14, 2, 1, 14},
 // lane (2.01 against 2.32 ms for the 3/8 rule; Dormand-Prince 5 has them).
 constexpr int64_t kTableauShortSites = int64_t(1) << 18;
 constexpr int64_t kTableauMidSitesFp32 = int64_t(1) << 20;
+// FP64 four-stage tableaus up to 2^20 sites: one wavefront of 8 sites per
+// lane (2.05 against 2.54 ms for 1000 steps of the 3/8 rule at 2^20).
+constexpr int64_t kTableauMidSitesFp64 = int64_t(1) << 20;
 constexpr int64_t kRoesslerShortSites = int64_t(1) << 21;
 constexpr int kRoesslerShortSitesPerLane = 4;
 constexpr int kRoesslerLongSitesPerLane = 8;
@@ -417,6 +420,8 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
                            !tab && free_shape;
     const bool tab_tuned = tab && free_shape && (d->prec == CHAIN_FP64 || d->prec == CHAIN_FP32_KAHAN);
     const bool tab_short = tab_tuned && d->n <= kTableauShortSites;
+    const bool tab_one = tab_short || (tab_tuned && d->prec == CHAIN_FP64 && stages == 4 &&
+                                       d->n <= kTableauMidSitesFp64);
     const bool tab_four = tab_short || (tab_tuned && d->prec == CHAIN_FP32_KAHAN &&
                                         d->n <= kTableauMidSitesFp32);
     const ShapeRow rrow = row_for(kShapeRoessler, d->n);
@@ -436,7 +441,7 @@ Plan make_plan(const chain_rk4_desc *d, int64_t reach_override, int stages) {
     P.waves_per_cluster = d->waves_per_cluster ? d->waves_per_cluster
                           : roe_table            ? rrow.waves
                           : nnn_table            ? nrow.waves
-                          : tab_short            ? 1
+                          : tab_one              ? 1
                           : roessler             ? kDefaultWavesRoessler
                           : nn && !tab           ? row.waves
                                                  : kDefaultWaves;

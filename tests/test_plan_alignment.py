@@ -205,6 +205,8 @@ def test_plan_for_validates_like_create():
             for n, shape in ((1 << 10, (4, 1, depth)), (1 << 18, (4, 1, depth)),
                              ((1 << 18) + 1, (mid, 4, depth)),
                              ((1 << 20) + 1, (long_sites, 4, depth))):
+                if name == "rk4_38" and prec == L.CHAIN_FP64 and n == (1 << 18) + 1:
+                    shape = (8, 1, depth)      # four stages: one wavefront up to 2^20
                 rc, P = plan(n, L.CHAIN_QUARTIC, prec, 0, 0, 0, tab=t)
                 assert rc == L.CHAIN_OK
                 assert (P.sites_per_lane, P.waves_per_cluster, P.kdepth) == shape, (name, prec, n)
